@@ -1,0 +1,162 @@
+/*
+ * mhd.h -- C ABI of libmhd, an MI355X (gfx950) implementation of the
+ * unsplit ideal-MHD update of "Magnetohydrodynamics with GAMER"
+ * (Zhang, Schive & Chiueh): the per-patch-group finite-volume update with
+ * constrained transport of the face-centred magnetic field.
+ *
+ * Conventions for every entry point
+ *   - All functions return an int status: MHD_OK (0) or a negative MHD_ERR_*
+ *     code; mhd_strerror() gives text.  No C++ exception crosses the ABI.
+ *   - Arguments are validated before any HIP call, so every invalid-argument
+ *     path is testable without a GPU.
+ *   - All state pointers are DEVICE memory owned by the caller.  The context
+ *     owns its scratch (intermediate fluxes, EMFs, half-step state) and frees
+ *     it in mhd_finalize().
+ *   - Work is enqueued on the HIP stream given to mhd_init() and is
+ *     asynchronous unless a function says it synchronises.  One context per
+ *     stream; a context is not thread-safe.
+ *   - Units: mu = 1 (paper Sec. 2).  Cells are cubic, dx = dy = dz (Sec. 3.1).
+ *
+ * Data layout of a level (a dense, periodic grid of nx*ny*nz cells):
+ *   U  : 5 components (rho, Mx, My, Mz, e), each nz*ny*nx, x fastest --
+ *        volume averages at cell centres (Eqs. 6, 11).
+ *   B  : 3 components (Bx, By, Bz), each nz*ny*nx -- face-area averages
+ *        (Eq. 14); Bx[k][j][i] sits on the lower x-face of cell (i,j,k),
+ *        By on the lower y-face, Bz on the lower z-face.
+ *   Element type: double for MHD_F64, float for MHD_F32 and MHD_F32_MIXED.
+ *   MHD_F32_MIXED additionally keeps the total energy in double in E64
+ *   (nz*ny*nx doubles); the e component of U is then ignored on input and
+ *   mirrored (rounded to float) on output.
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MHD_ABI_VERSION 1
+
+/* status codes */
+#define MHD_OK 0
+#define MHD_ERR_INVALID_ARG -1
+#define MHD_ERR_UNSUPPORTED -2
+#define MHD_ERR_GHOST_TOO_SMALL -3
+#define MHD_ERR_HIP -4
+#define MHD_ERR_NONPHYSICAL -5
+#define MHD_ERR_NO_DEVICE -6
+#define MHD_ERR_OUT_OF_MEMORY -7
+
+/* unsplit integrators, paper Sec. 3.2 */
+enum { MHD_VL = 0, MHD_CTU = 1 };
+/* reconstruction, Sec. 3.2 (CTU step 1, VL step 4); PLM limiter is minmod */
+enum { MHD_PLM = 0, MHD_PPM = 1 };
+/* Riemann solvers, Sec. 3.2 (CTU step 2); MLP = learned flux with HLLD fallback */
+enum { MHD_ROE = 0, MHD_HLLE = 1, MHD_HLLD = 2, MHD_MLP = 3 };
+/* arithmetic */
+enum { MHD_F64 = 0, MHD_F32 = 1, MHD_F32_MIXED = 2 };
+
+typedef struct mhd_ctx_s* mhd_ctx;
+
+typedef struct {
+  int scheme;        /* MHD_VL or MHD_CTU */
+  int recon;         /* MHD_PLM or MHD_PPM */
+  int riemann;       /* MHD_ROE, MHD_HLLE, MHD_HLLD, MHD_MLP */
+  int prec;          /* MHD_F64, MHD_F32, MHD_F32_MIXED */
+  double gamma;      /* adiabatic index, 5/3 in the paper (Sec. 4) */
+  double courant;    /* Courant factor, 1/2 in the paper (Sec. 4), summed over directions */
+  double beta_fp64;  /* MHD_F32_MIXED: cells with 2p/|B|^2 below this recover p in double */
+  double mlp_dp;     /* MHD_MLP: relative pressure jump above which HLLD is used */
+  double mlp_drho;   /* MHD_MLP: relative density jump above which HLLD is used */
+} mhd_config;
+
+/* One level: a dense periodic grid plus an optional list of patch groups.
+ * groups == NULL (or n_groups == 0) updates every cell.  Otherwise only the
+ * cells of the listed groups are updated; each entry is the origin (i0, j0,
+ * k0) of a group of group_edge^3 cells (paper Sec. 3.3: eight patches of N^3
+ * cells form a group of (2N)^3), and the cells outside the listed groups act
+ * as ghost zones that the caller fills (e.g. by prolongation from the coarser
+ * level).  All grid dimensions must then be multiples of group_edge. */
+typedef struct {
+  int nx, ny, nz;       /* cells; each >= 4 */
+  double dx;            /* cell width (Sec. 3.1: x_i = (i + 1/2) dx) */
+  int n_groups;         /* number of entries in groups */
+  int group_edge;       /* cells per group edge (16 = 2 patches of 8^3) */
+  const int* groups;    /* device int32[3 * n_groups] origins, or NULL */
+  void* U;              /* device, 5 * N elements, see layout above */
+  void* B;              /* device, 3 * N elements */
+  double* E64;          /* device, N doubles, MHD_F32_MIXED only */
+} mhd_level;
+
+/* Ghost width a staged patch group needs for one full step of the given
+ * integrator and reconstruction (stencil count: 3 for PLM, 4 for PPM). */
+int mhd_required_ghost(int scheme, int recon);
+
+/* Validate cfg and create a context bound to hip_stream (a hipStream_t, or
+ * NULL for the default stream) on the current device. */
+int mhd_init(const mhd_config* cfg, void* hip_stream, mhd_ctx* out);
+int mhd_finalize(mhd_ctx ctx);
+
+/* Validate a level description (no HIP call).  ctx may be NULL, which skips
+ * the checks that depend on the context's precision. */
+int mhd_check_level(mhd_ctx ctx, const mhd_level* lv);
+
+/* Conserved state from primitive cell fields (Eq. 5; cell-centred field is
+ * the mean of the two opposite faces).  W5: device, 5*N elements of the
+ * level's type (rho, vx, vy, vz, p).  Writes lv->U (and E64 when mixed). */
+int mhd_prim_to_cons(mhd_ctx ctx, const mhd_level* lv, const void* W5);
+
+/* CFL time step, Sec. 3.2: dt = courant * dx / max over cells of
+ * sum_d (|v_d| + c_f,d).  Computed and reduced in double.  dt_dev (device
+ * double*) receives it without a host sync; dt_host (host double*) syncs.
+ * Either may be NULL.  A cell with rho <= 0 or p <= 0 gives
+ * MHD_ERR_NONPHYSICAL (host path) or sets the context's sticky flag. */
+int mhd_cfl_dt(mhd_ctx ctx, const mhd_level* lv, double* dt_host, double* dt_dev);
+
+/* One full step of length dt (paper Sec. 3.2: CTU steps 1-8 or VL steps 1-7),
+ * updating lv->U and lv->B in place.  Asynchronous. */
+int mhd_step(mhd_ctx ctx, const mhd_level* lv, double dt);
+
+/* Same, with dt read from device memory at run time (graph-capturable). */
+int mhd_step_devdt(mhd_ctx ctx, const mhd_level* lv, const double* dt_dev);
+
+/* CFL step plus update in one call, with no host synchronisation: computes
+ * dt from the current state on the device, writes it to dt_dev (device,
+ * may be NULL) and adds it to t_dev (device, may be NULL). */
+int mhd_advance(mhd_ctx ctx, const mhd_level* lv, double* dt_dev, double* t_dev);
+
+/* Discrete divergence of Eq. 16 in double: max |div B| and the mean of
+ * |div B| over the level's cells.  Synchronises. */
+int mhd_divB(mhd_ctx ctx, const mhd_level* lv, double* max_abs, double* l1);
+
+/* Volume totals in double with a fixed-order reduction (bitwise
+ * reproducible): mass, Mx, My, Mz, total energy, magnetic energy (cell-centred
+ * field), kinetic energy.  Synchronises. */
+int mhd_sums(mhd_ctx ctx, const mhd_level* lv, double out[7]);
+
+/* Number of faces where the Roe solver fell back to HLLE since the last
+ * call (resets the counter).  Synchronises. */
+int mhd_fallback_count(mhd_ctx ctx, long long* count);
+
+/* Stage timing: runs nrep steps exactly as mhd_advance does (they advance
+ * the level), recording HIP events on the context's stream between the stage
+ * kernels, and writes the mean milliseconds of each stage to stage_ms
+ * (host array of mhd_num_stages() doubles).  Synchronises. */
+int mhd_profile_step(mhd_ctx ctx, const mhd_level* lv, int nrep, double* stage_ms);
+int mhd_num_stages(mhd_ctx ctx);
+/* Name of stage s (static string), or NULL when out of range. */
+const char* mhd_stage_name(mhd_ctx ctx, int stage);
+
+/* Wait for the context's stream and report sticky device-side errors
+ * (MHD_ERR_NONPHYSICAL). */
+int mhd_sync(mhd_ctx ctx);
+
+const char* mhd_strerror(int status);
+int mhd_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHD_H */

@@ -1,0 +1,571 @@
+// mhd_kernels.hpp -- stage kernels of the unsplit MHD update on a dense
+// periodic level, and the diagnostics reductions.  Included once by
+// mhd_api.hip, which instantiates and launches them.
+//
+// Storage (all SoA, x fastest, N = nx*ny*nz per component):
+//   U [5][N]  rho, Mx, My, Mz, e at cell centres
+//   B [3][N]  face-area-averaged field on the lower x/y/z face of each cell
+//   W [8][N]  primitives rho, vx, vy, vz, p, Bcx, Bcy, Bcz (cell-centred field
+//             = mean of the two opposite faces)
+//   F [3][7][N] face fluxes of the lower face of each cell, per direction:
+//             0 mass, 1..3 momentum x/y/z, 4 energy, 5 E_t1, 6 E_t2 -- the two
+//             edge-parallel EMF components carried by the face (E = -V x B)
+//   E [3][N]  edge EMFs: Ex on the x-edge at the lower (y, z) corner of the
+//             cell, Ey at the lower (z, x) corner, Ez at the lower (x, y) corner.
+//
+// Work mapping: a launch covers a list of units.  With no group list the
+// single unit is the whole grid; with a list each unit is the box of
+// (edge + 2*halo)^3 cells around one patch group, with periodic wrap.  Each
+// thread owns one cell of one unit.  Block ids are remapped so that each of
+// the eight XCDs (which take blocks round-robin) works on a contiguous range
+// of cells, which keeps stencil neighbours in that XCD's L2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mhd_device.hpp"
+
+namespace mhd {
+
+constexpr int kBlock = 256;
+
+struct Work {
+  int nx, ny, nz;
+  long long N;          // cells of the grid
+  const int* groups;    // nullptr: whole grid
+  int edge;             // group edge in cells
+  int halo;             // extra cells around each group
+  int box;              // edge + 2 * halo
+  long long items;      // threads with work
+  const int* occ;       // group occupancy map (list mode), gnx*gny*gnz
+  int gnx, gny, gnz;    // groups per dimension
+};
+
+__device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ long long lin(const Work& w, int i, int j, int k) {
+  return ((long long)k * w.ny + j) * w.nx + i;
+}
+
+// neighbour index with periodic wrap; |di|, |dj|, |dk| <= grid size
+__device__ __forceinline__ long long nbr(const Work& w, int i, int j, int k, int di, int dj, int dk) {
+  return lin(w, wrapc(i + di, w.nx), wrapc(j + dj, w.ny), wrapc(k + dk, w.nz));
+}
+
+__device__ __forceinline__ long long block_linear_id() {
+  const unsigned nb = gridDim.x;
+  const unsigned b = blockIdx.x;
+  const unsigned q = nb >> 3;
+  unsigned r = b;
+  if (b < (q << 3)) r = (b & 7u) * q + (b >> 3);  // XCD b%8 gets a contiguous range
+  return (long long)r * kBlock + threadIdx.x;
+}
+
+// cell owned by this thread; false if the thread has no work.  (a, b, c)
+// is the position inside the unit's box (the cell itself for a whole grid).
+__device__ __forceinline__ bool my_cell(const Work& w, int& i, int& j, int& k, int& a, int& b, int& c) {
+  const long long t = block_linear_id();
+  if (t >= w.items) return false;
+  if (w.groups == nullptr) {
+    i = (int)(t % w.nx);
+    const long long r = t / w.nx;
+    j = (int)(r % w.ny);
+    k = (int)(r / w.ny);
+    a = i; b = j; c = k;
+  } else {
+    const long long per = (long long)w.box * w.box * w.box;
+    const int g = (int)(t / per);
+    const int l = (int)(t - (long long)g * per);
+    a = l % w.box;
+    b = (l / w.box) % w.box;
+    c = l / (w.box * w.box);
+    i = wrapc(w.groups[3 * g + 0] - w.halo + a, w.nx);
+    j = wrapc(w.groups[3 * g + 1] - w.halo + b, w.ny);
+    k = wrapc(w.groups[3 * g + 2] - w.halo + c, w.nz);
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool my_cell(const Work& w, int& i, int& j, int& k) {
+  int a, b, c;
+  return my_cell(w, i, j, k, a, b, c);
+}
+
+// time step source: explicit value, device scalar, or CFL maximum signal
+// speed (stored as the bit pattern of a positive double)
+struct DtSrc {
+  double val;
+  const double* ptr;
+  const unsigned long long* smax;
+  double courant_dx;
+};
+
+__device__ __forceinline__ double get_dt(const DtSrc& s) {
+  if (s.smax) return s.courant_dx / __longlong_as_double((long long)*s.smax);
+  if (s.ptr) return *s.ptr;
+  return s.val;
+}
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------ primitives
+template <typename T>
+__device__ __forceinline__ void cell_prims(const Work& w, const T* __restrict__ U, const T* __restrict__ B,
+                                           int i, int j, int k, T gam, T out[8]) {
+  const long long N = w.N;
+  const long long p = lin(w, i, j, k);
+  const T bx = T(0.5) * (B[p] + B[nbr(w, i, j, k, 1, 0, 0)]);
+  const T by = T(0.5) * (B[N + p] + B[N + nbr(w, i, j, k, 0, 1, 0)]);
+  const T bz = T(0.5) * (B[2 * N + p] + B[2 * N + nbr(w, i, j, k, 0, 0, 1)]);
+  const T d = U[p];
+  const T id = T(1) / d;
+  const T vx = U[N + p] * id, vy = U[2 * N + p] * id, vz = U[3 * N + p] * id;
+  const T pr = (gam - T(1)) * (U[4 * N + p] - T(0.5) * d * (vx * vx + vy * vy + vz * vz) -
+                               T(0.5) * (bx * bx + by * by + bz * bz));
+  out[0] = d; out[1] = vx; out[2] = vy; out[3] = vz; out[4] = pr; out[5] = bx; out[6] = by; out[7] = bz;
+}
+
+// sum over directions of |v_d| + c_f,d, in double
+template <typename T>
+__device__ __forceinline__ double signal_speed(const T q[8], T gam) {
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const T cf = fast_speed(q[0], q[4], q[5 + a], q[5 + b], q[5 + c], gam);
+    s += (double)(dabs(q[1 + a]) + cf);
+  }
+  return s;
+}
+
+__device__ __forceinline__ void block_max_atomic(double v, unsigned long long* smax) {
+  __shared__ double red[kBlock / 64];
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int q = 1; q < kBlock / 64; ++q) m = fmax(m, red[q]);
+    if (m > 0.0) atomicMax(smax, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// Primitive state of every cell; optionally the CFL maximum signal speed and
+// the sticky non-physical flag.
+template <typename T, bool CFL>
+__global__ void __launch_bounds__(kBlock) k_prim(Work w, const T* __restrict__ U, const T* __restrict__ B,
+                                                 T* __restrict__ W, T gam, unsigned long long* smax,
+                                                 int* flag) {
+  int i, j, k;
+  double s = 0.0;
+  if (my_cell(w, i, j, k)) {
+    T q[8];
+    cell_prims(w, U, B, i, j, k, gam, q);
+    const long long p = lin(w, i, j, k);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) W[m * w.N + p] = q[m];
+    if (!(q[0] > T(0)) || !(q[4] > T(0))) atomicOr(flag, 1);
+    else if (CFL) s = signal_speed(q, gam);
+  }
+  if (CFL) block_max_atomic(s, smax);
+}
+
+// CFL maximum signal speed only
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cfl(Work w, const T* __restrict__ U, const T* __restrict__ B, T gam,
+                                                unsigned long long* smax, int* flag) {
+  int i, j, k;
+  double s = 0.0;
+  if (my_cell(w, i, j, k)) {
+    T q[8];
+    cell_prims(w, U, B, i, j, k, gam, q);
+    if (!(q[0] > T(0)) || !(q[4] > T(0))) atomicOr(flag, 1);
+    else s = signal_speed(q, gam);
+  }
+  block_max_atomic(s, smax);
+}
+
+__global__ void k_reset_smax(unsigned long long* smax) { *smax = 0ull; }
+
+// dt = courant dx / smax into an output scalar, and t += dt
+__global__ void k_publish_dt(const unsigned long long* smax, double courant_dx, double* dt_out, double* t_out) {
+  const double dt = courant_dx / __longlong_as_double((long long)*smax);
+  if (dt_out) *dt_out = dt;
+  if (t_out) *t_out += dt;
+}
+
+// ------------------------------------------------------------ fluxes
+template <typename T, int D>
+__device__ __forceinline__ void load_w1d(const T* __restrict__ W, long long N, long long q, T w[7]) {
+  constexpr int n = D, t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  w[0] = W[q];
+  w[1] = W[(1 + n) * N + q];
+  w[2] = W[(1 + t1) * N + q];
+  w[3] = W[(1 + t2) * N + q];
+  w[4] = W[4 * N + q];
+  w[5] = W[(5 + t1) * N + q];
+  w[6] = W[(5 + t2) * N + q];
+}
+
+// RECON: 0 = first order (cell states), 1 = PLM with minmod on primitives
+template <typename T, int D, int RECON, int SOLVER>
+__device__ __forceinline__ int face_flux(const Work& w, const T* __restrict__ W, const T* __restrict__ B,
+                                         T* __restrict__ F, int i, int j, int k, T gam) {
+  const long long N = w.N;
+  const long long pR = lin(w, i, j, k);
+  const long long pL = nbr(w, i, j, k, D == 0 ? -1 : 0, D == 1 ? -1 : 0, D == 2 ? -1 : 0);
+  T wl[7], wr[7];
+  load_w1d<T, D>(W, N, pL, wl);
+  load_w1d<T, D>(W, N, pR, wr);
+  if (RECON == 1) {
+    const long long pLL = nbr(w, i, j, k, D == 0 ? -2 : 0, D == 1 ? -2 : 0, D == 2 ? -2 : 0);
+    const long long pRR = nbr(w, i, j, k, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0);
+    T wll[7], wrr[7];
+    load_w1d<T, D>(W, N, pLL, wll);
+    load_w1d<T, D>(W, N, pRR, wrr);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      const T sL = minmod(wl[m] - wll[m], wr[m] - wl[m]);
+      const T sR = minmod(wr[m] - wl[m], wrr[m] - wr[m]);
+      wl[m] = wl[m] + T(0.5) * sL;
+      wr[m] = wr[m] - T(0.5) * sR;
+    }
+  }
+  const T bn = B[D * N + pR];
+  T f[7];
+  const int fb = riemann<SOLVER>(wl, wr, bn, gam, f);
+  constexpr int n = D, t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  T* Fd = F + (long long)D * 7 * N;
+  Fd[pR] = f[0];
+  Fd[(1 + n) * N + pR] = f[1];
+  Fd[(1 + t1) * N + pR] = f[2];
+  Fd[(1 + t2) * N + pR] = f[3];
+  Fd[4 * N + pR] = f[4];
+  Fd[5 * N + pR] = f[6];    // E_t1 = F_n[B_t2]
+  Fd[6 * N + pR] = -f[5];   // E_t2 = -F_n[B_t1]
+  return fb;
+}
+
+__device__ __forceinline__ void block_count_atomic(int v, unsigned long long* counter) {
+  __shared__ int red[kBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int q = 0; q < kBlock / 64; ++q) s += red[q];
+    if (s) atomicAdd(counter, (unsigned long long)s);
+  }
+}
+
+template <typename T, int RECON, int SOLVER>
+__global__ void __launch_bounds__(kBlock) k_flux(Work w, const T* __restrict__ W, const T* __restrict__ B,
+                                                 T* __restrict__ F, T gam, unsigned long long* nfb) {
+  int i, j, k;
+  int fb = 0;
+  if (my_cell(w, i, j, k)) {
+    fb += face_flux<T, 0, RECON, SOLVER>(w, W, B, F, i, j, k, gam);
+    fb += face_flux<T, 1, RECON, SOLVER>(w, W, B, F, i, j, k, gam);
+    fb += face_flux<T, 2, RECON, SOLVER>(w, W, B, F, i, j, k, gam);
+  }
+  if (SOLVER == 0) block_count_atomic(fb, nfb);
+}
+
+// ------------------------------------------------------------ edge EMFs
+template <typename T>
+__device__ __forceinline__ T ref_emf(const T* __restrict__ W, long long N, long long q, int a) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  return -(W[(1 + b) * N + q] * W[(5 + c) * N + q] - W[(1 + c) * N + q] * W[(5 + b) * N + q]);
+}
+
+template <typename T>
+__device__ __forceinline__ T upwind(T m, T pos, T neg) {
+  return m > T(0) ? pos : (m < T(0) ? neg : T(0.5) * (pos + neg));
+}
+
+// E_a on the edge at the lower (b, c) corner of cell (i, j, k), (a, b, c)
+// cyclic, from the four faces around the edge (upwind CT average of
+// Gardiner & Stone 2005): each face value is extrapolated to the edge with
+// the derivative taken in the upwind cell (sign of the face mass flux), and
+// the four extrapolations are averaged.
+template <typename T, int A>
+__device__ __forceinline__ T edge_emf(const Work& w, const T* __restrict__ F, const T* __restrict__ W,
+                                      int i, int j, int k) {
+  constexpr int b = (A + 1) % 3, c = (A + 2) % 3;
+  const long long N = w.N;
+  const T* Fb = F + (long long)b * 7 * N;
+  const T* Fc = F + (long long)c * 7 * N;
+  const int ob[3] = {b == 0 ? -1 : 0, b == 1 ? -1 : 0, b == 2 ? -1 : 0};
+  const int oc[3] = {c == 0 ? -1 : 0, c == 1 ? -1 : 0, c == 2 ? -1 : 0};
+  const long long p = lin(w, i, j, k);
+  const long long pb = nbr(w, i, j, k, ob[0], ob[1], ob[2]);
+  const long long pc = nbr(w, i, j, k, oc[0], oc[1], oc[2]);
+  const long long pbc = nbr(w, i, j, k, ob[0] + oc[0], ob[1] + oc[1], ob[2] + oc[2]);
+  const T eb0 = Fb[6 * N + pc], eb1 = Fb[6 * N + p];
+  const T ec0 = Fc[5 * N + pb], ec1 = Fc[5 * N + p];
+  const T mb0 = Fb[pc], mb1 = Fb[p], mc0 = Fc[pb], mc1 = Fc[p];
+  const T r00 = ref_emf(W, N, pbc, A), r10 = ref_emf(W, N, pc, A);
+  const T r01 = ref_emf(W, N, pb, A), r11 = ref_emf(W, N, p, A);
+  const T dc1 = upwind(mb1, r01 - ec0, r11 - ec1);
+  const T dc0 = upwind(mb0, ec0 - r00, ec1 - r10);
+  const T db1 = upwind(mc1, r10 - eb0, r11 - eb1);
+  const T db0 = upwind(mc0, eb0 - r00, eb1 - r01);
+  return T(0.25) * (eb0 + eb1 + ec0 + ec1) + T(0.25) * ((dc0 - dc1) + (db0 - db1));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_emf(Work w, const T* __restrict__ F, const T* __restrict__ W,
+                                                T* __restrict__ E) {
+  int i, j, k;
+  if (!my_cell(w, i, j, k)) return;
+  const long long p = lin(w, i, j, k);
+  E[p] = edge_emf<T, 0>(w, F, W, i, j, k);
+  E[w.N + p] = edge_emf<T, 1>(w, F, W, i, j, k);
+  E[2 * w.N + p] = edge_emf<T, 2>(w, F, W, i, j, k);
+}
+
+// ------------------------------------------------------------ updates
+// U - r div F (Eq. 10), differences applied in the order x, y, z
+template <typename T>
+__device__ __forceinline__ void cell_update(const Work& w, const T* __restrict__ U, const T* __restrict__ F,
+                                            int i, int j, int k, T r, T out[5]) {
+  const long long N = w.N;
+  const long long p = lin(w, i, j, k);
+  const long long px = nbr(w, i, j, k, 1, 0, 0), py = nbr(w, i, j, k, 0, 1, 0), pz = nbr(w, i, j, k, 0, 0, 1);
+  const T* Fx = F;
+  const T* Fy = F + 7 * N;
+  const T* Fz = F + 14 * N;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    T v = U[m * N + p];
+    v -= r * (Fx[m * N + px] - Fx[m * N + p]);
+    v -= r * (Fy[m * N + py] - Fy[m * N + p]);
+    v -= r * (Fz[m * N + pz] - Fz[m * N + p]);
+    out[m] = v;
+  }
+}
+
+// CT update of the three lower faces of cell (i, j, k) (Eq. 13)
+template <typename T>
+__device__ __forceinline__ void face_update(const Work& w, const T* __restrict__ B, const T* __restrict__ E,
+                                            int i, int j, int k, T r, T out[3]) {
+  const long long N = w.N;
+  const long long p = lin(w, i, j, k);
+  const long long px = nbr(w, i, j, k, 1, 0, 0), py = nbr(w, i, j, k, 0, 1, 0), pz = nbr(w, i, j, k, 0, 0, 1);
+  const T* Ex = E;
+  const T* Ey = E + N;
+  const T* Ez = E + 2 * N;
+  out[0] = B[p] - r * (Ez[py] - Ez[p]) + r * (Ey[pz] - Ey[p]);
+  out[1] = B[N + p] - r * (Ex[pz] - Ex[p]) + r * (Ez[px] - Ez[p]);
+  out[2] = B[2 * N + p] - r * (Ey[px] - Ey[p]) + r * (Ex[py] - Ex[p]);
+}
+
+// Half step over dt/2: U^{n+1/2} and face B^{n+1/2} from the predictor fluxes
+// and EMFs, written as primitives Wh (cell-centred field from the updated
+// faces, including the upper faces owned by the neighbours) and Bh.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U, const T* __restrict__ B,
+                                                 const T* __restrict__ F, const T* __restrict__ E, DtSrc dts,
+                                                 T inv_dx, T gam, T* __restrict__ Wh, T* __restrict__ Bh) {
+  int i, j, k;
+  if (!my_cell(w, i, j, k)) return;
+  const T r = T(0.5 * get_dt(dts)) * inv_dx;
+  T u[5], bl[3], bux[3], buy[3], buz[3];
+  cell_update(w, U, F, i, j, k, r, u);
+  face_update(w, B, E, i, j, k, r, bl);
+  face_update(w, B, E, wrapc(i + 1, w.nx), j, k, r, bux);
+  face_update(w, B, E, i, wrapc(j + 1, w.ny), k, r, buy);
+  face_update(w, B, E, i, j, wrapc(k + 1, w.nz), r, buz);
+  const T bx = T(0.5) * (bl[0] + bux[0]);
+  const T by = T(0.5) * (bl[1] + buy[1]);
+  const T bz = T(0.5) * (bl[2] + buz[2]);
+  const T d = u[0];
+  const T id = T(1) / d;
+  const T vx = u[1] * id, vy = u[2] * id, vz = u[3] * id;
+  const T pr = (gam - T(1)) * (u[4] - T(0.5) * d * (vx * vx + vy * vy + vz * vz) - T(0.5) * (bx * bx + by * by + bz * bz));
+  const long long N = w.N;
+  const long long p = lin(w, i, j, k);
+  Wh[p] = d; Wh[N + p] = vx; Wh[2 * N + p] = vy; Wh[3 * N + p] = vz; Wh[4 * N + p] = pr;
+  Wh[5 * N + p] = bx; Wh[6 * N + p] = by; Wh[7 * N + p] = bz;
+  Bh[p] = bl[0]; Bh[N + p] = bl[1]; Bh[2 * N + p] = bl[2];
+}
+
+// Full step over dt from time n (in place: each thread reads and writes only
+// its own cell and its own lower faces).
+//
+// With a group list, a cell on the upper boundary of its group also updates
+// the face it shares with the next cell when the next cell's group is not
+// listed (occupancy map), so every face of a listed group advances exactly
+// once and no face is read after another thread has written it.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* __restrict__ B,
+                                                  const T* __restrict__ F, const T* __restrict__ E, DtSrc dts,
+                                                  T inv_dx) {
+  int i, j, k, a, b, c;
+  if (!my_cell(w, i, j, k, a, b, c)) return;
+  const T r = T(get_dt(dts)) * inv_dx;
+  const long long N = w.N;
+  T u[5], bf[3];
+  cell_update(w, U, F, i, j, k, r, u);
+  face_update(w, B, E, i, j, k, r, bf);
+  T ux[3], uy[3], uz[3];
+  bool ex = false, ey = false, ez = false;
+  if (w.groups) {
+    const int gi = i / w.edge, gj = j / w.edge, gk = k / w.edge;
+    auto listed = [&](int x, int y, int z) {
+      return w.occ[((long long)wrapc(z, w.gnz) * w.gny + wrapc(y, w.gny)) * w.gnx + wrapc(x, w.gnx)] != 0;
+    };
+    ex = a == w.edge - 1 && !listed(gi + 1, gj, gk);
+    ey = b == w.edge - 1 && !listed(gi, gj + 1, gk);
+    ez = c == w.edge - 1 && !listed(gi, gj, gk + 1);
+  }
+  if (ex) face_update(w, B, E, wrapc(i + 1, w.nx), j, k, r, ux);
+  if (ey) face_update(w, B, E, i, wrapc(j + 1, w.ny), k, r, uy);
+  if (ez) face_update(w, B, E, i, j, wrapc(k + 1, w.nz), r, uz);
+  const long long p = lin(w, i, j, k);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) U[m * N + p] = u[m];
+  B[p] = bf[0]; B[N + p] = bf[1]; B[2 * N + p] = bf[2];
+  if (ex) B[nbr(w, i, j, k, 1, 0, 0)] = ux[0];
+  if (ey) B[N + nbr(w, i, j, k, 0, 1, 0)] = uy[1];
+  if (ez) B[2 * N + nbr(w, i, j, k, 0, 0, 1)] = uz[2];
+}
+
+// group occupancy map of a list: clear, then mark
+__global__ void __launch_bounds__(kBlock) k_occ_clear(int* occ, long long n) {
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) occ[t] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_occ_set(int* occ, const int* groups, int n_groups, int edge, int gnx,
+                                                    int gny) {
+  const int g = blockIdx.x * kBlock + threadIdx.x;
+  if (g >= n_groups) return;
+  const int gi = groups[3 * g] / edge, gj = groups[3 * g + 1] / edge, gk = groups[3 * g + 2] / edge;
+  occ[((long long)gk * gny + gj) * gnx + gi] = 1;
+}
+
+// ------------------------------------------------------------ set-up
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prim_to_cons(Work w, const T* __restrict__ W5, const T* __restrict__ B,
+                                                         T* __restrict__ U, T gam) {
+  int i, j, k;
+  if (!my_cell(w, i, j, k)) return;
+  const long long N = w.N;
+  const long long p = lin(w, i, j, k);
+  const T bx = T(0.5) * (B[p] + B[nbr(w, i, j, k, 1, 0, 0)]);
+  const T by = T(0.5) * (B[N + p] + B[N + nbr(w, i, j, k, 0, 1, 0)]);
+  const T bz = T(0.5) * (B[2 * N + p] + B[2 * N + nbr(w, i, j, k, 0, 0, 1)]);
+  const T d = W5[p], vx = W5[N + p], vy = W5[2 * N + p], vz = W5[3 * N + p], pr = W5[4 * N + p];
+  U[p] = d;
+  U[N + p] = d * vx;
+  U[2 * N + p] = d * vy;
+  U[3 * N + p] = d * vz;
+  U[4 * N + p] = pr / (gam - T(1)) + T(0.5) * d * (vx * vx + vy * vy + vz * vz) + T(0.5) * (bx * bx + by * by + bz * bz);
+}
+
+// ------------------------------------------------------------ diagnostics
+// Two-pass deterministic reductions: fixed per-block trees write partials,
+// one block combines them in index order.
+template <int NQ>
+__device__ __forceinline__ void block_partials(double v[NQ], double* part, int stride) {
+  __shared__ double red[NQ][kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double s = wave_sum(v[q]);
+    if (lane == 0) red[q][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = red[q][0];
+      for (int m = 1; m < kBlock / 64; ++m) s += red[q][m];
+      part[(long long)q * stride + blockIdx.x] = s;
+    }
+  }
+}
+
+// discrete divergence (Eq. 16): partial sums of |div B| and partial maxima
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_divb(Work w, const T* __restrict__ B, double inv_dx, double* part) {
+  int i, j, k;
+  double a = 0.0;
+  if (my_cell(w, i, j, k)) {
+    const long long N = w.N;
+    const long long p = lin(w, i, j, k);
+    const double dv = ((double)B[nbr(w, i, j, k, 1, 0, 0)] - (double)B[p]) * inv_dx +
+                      ((double)B[N + nbr(w, i, j, k, 0, 1, 0)] - (double)B[N + p]) * inv_dx +
+                      ((double)B[2 * N + nbr(w, i, j, k, 0, 0, 1)] - (double)B[2 * N + p]) * inv_dx;
+    a = fabs(dv);
+  }
+  __shared__ double mx[kBlock / 64];
+  const double wm = wave_max(a);
+  if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = wm;
+  double v[1] = {a};
+  block_partials<1>(v, part, gridDim.x);
+  if (threadIdx.x == 0) {
+    double m = mx[0];
+    for (int q = 1; q < kBlock / 64; ++q) m = fmax(m, mx[q]);
+    part[(long long)gridDim.x + blockIdx.x] = m;
+  }
+}
+
+// volume totals: mass, Mx, My, Mz, e, magnetic energy, kinetic energy
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sums(Work w, const T* __restrict__ U, const T* __restrict__ B,
+                                                 double* part) {
+  int i, j, k;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (my_cell(w, i, j, k)) {
+    const long long N = w.N;
+    const long long p = lin(w, i, j, k);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) v[m] = (double)U[m * N + p];
+    const double bx = 0.5 * ((double)B[p] + (double)B[nbr(w, i, j, k, 1, 0, 0)]);
+    const double by = 0.5 * ((double)B[N + p] + (double)B[N + nbr(w, i, j, k, 0, 1, 0)]);
+    const double bz = 0.5 * ((double)B[2 * N + p] + (double)B[2 * N + nbr(w, i, j, k, 0, 0, 1)]);
+    v[5] = 0.5 * (bx * bx + by * by + bz * bz);
+    v[6] = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0];
+  }
+  block_partials<7>(v, part, gridDim.x);
+}
+
+// combine nq rows of nb partials (sum for rows < nsum, max otherwise)
+__global__ void __launch_bounds__(kBlock) k_finish(const double* part, int nb, int nq, int nsum, double* out) {
+  __shared__ double red[kBlock];
+  for (int q = 0; q < nq; ++q) {
+    const bool is_max = q >= nsum;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+      const double x = part[(long long)q * nb + b];
+      acc = is_max ? fmax(acc, x) : acc + x;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] = is_max ? fmax(red[threadIdx.x], red[threadIdx.x + s])
+                                                     : red[threadIdx.x] + red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = red[0];
+    __syncthreads();
+  }
+}
+
+}  // namespace mhd

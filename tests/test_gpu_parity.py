@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars: FP64 results within 1e-12 relative (per component, infinity norm over
+the grid divided by the component's infinity norm), FP32 within 1e-5 per
+step, integer decisions (solver fallbacks, non-physical flags) identical.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from paper_1804_03479_amd import inputs  # noqa: E402
+from paper_1804_03479_amd.mhd import Level, MHDError, Solver  # noqa: E402
+
+SOLVERS = {"roe": oracle.ROE, "hlle": oracle.HLLE, "hlld": oracle.HLLD}
+
+
+def rel_err(a, b):
+    """per-component infinity-norm relative error, worst component"""
+    worst = 0.0
+    for m in range(a.shape[0]):
+        den = max(np.abs(b[m]).max(), 1e-300)
+        worst = max(worst, np.abs(a[m] - b[m]).max() / den)
+    return worst
+
+
+def rel_err_f32(Ug, Uo, dt, dx, courant=0.5):
+    """FP32 bar: per component relative to its infinity norm, except that the
+    momentum components are measured against the flow's momentum scale
+    max(rho) * max(c_f) (a momentum component whose own magnitude is far
+    below that scale would make a purely relative bar ill-posed)."""
+    cmax = courant * dx / dt / 3.0      # dt = C dx / max sum_d(|v_d| + c_f,d)
+    worst = 0.0
+    for m in range(Ug.shape[0]):
+        den = np.abs(Uo[m]).max()
+        if m in (1, 2, 3):
+            den = max(den, np.abs(Uo[0]).max() * cmax)
+        worst = max(worst, np.abs(Ug[m] - Uo[m]).max() / den)
+    return worst
+
+
+def level_from(U, B, dx, dtype=torch.float64, groups=None):
+    return Level(torch.from_numpy(U).to("cuda", dtype).contiguous(),
+                 torch.from_numpy(B).to("cuda", dtype).contiguous(), dx, groups=groups)
+
+
+def fetch(lv):
+    torch.cuda.synchronize()
+    return lv.U.double().cpu().numpy(), lv.B.double().cpu().numpy()
+
+
+PROBLEMS = {
+    "abc32": lambda: inputs.abc_problem(32, 0.01, seed=0),
+    "ragged": lambda: inputs.smooth_problem(20, 18, 17, seed=3),
+    "tiny": lambda: inputs.smooth_problem(4, 5, 6, seed=5),
+}
+
+
+@pytest.mark.parametrize("prob", sorted(PROBLEMS))
+def test_cfl_parity(prob):
+    p = PROBLEMS[prob]()
+    U, B = oracle.initial_state(p)
+    s = Solver()
+    lv = level_from(U, B, p["dx"])
+    assert abs(s.cfl_dt(lv) - oracle.cfl_dt(U, B, p["dx"])) <= 1e-13 * oracle.cfl_dt(U, B, p["dx"])
+
+
+@pytest.mark.parametrize("prob", sorted(PROBLEMS))
+def test_prim_to_cons_parity(prob):
+    p = PROBLEMS[prob]()
+    U, B = oracle.initial_state(p)
+    W5 = np.stack([p["rho"], p["vx"], p["vy"], p["vz"], p["p"]])
+    s = Solver()
+    lv = s.level_from_primitives(torch.from_numpy(W5), torch.from_numpy(B), p["dx"])
+    Ug, _ = fetch(lv)
+    assert rel_err(Ug, U) <= 1e-14
+
+
+@pytest.mark.parametrize("solver", sorted(SOLVERS))
+@pytest.mark.parametrize("prob", sorted(PROBLEMS))
+def test_one_step_f64(prob, solver):
+    p = PROBLEMS[prob]()
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx, riemann=SOLVERS[solver])
+    s = Solver(riemann=solver)
+    lv = level_from(U, B, dx)
+    s.step(lv, dt)
+    Ug, Bg = fetch(lv)
+    assert rel_err(Ug, Uo) <= 1e-12
+    assert rel_err(Bg, Bo) <= 1e-12
+
+
+def test_twenty_steps_abc32_f64():
+    # 32^3 ABC box, VL + PLM(minmod) + Roe + CT, Courant 1/2, 20 steps
+    p = inputs.abc_problem(32, 0.01, seed=0)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    Uo, Bo, t_o, _ = oracle.run(U, B, 20, dx)
+    s = Solver()
+    lv = level_from(U, B, dx)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(20):
+        s.advance(lv, t_dev=t)
+    Ug, Bg = fetch(lv)
+    assert abs(t.item() - t_o) <= 1e-13 * t_o
+    assert rel_err(Ug, Uo) <= 1e-12
+    assert rel_err(Bg, Bo) <= 1e-12
+    mx, _ = s.divb(lv)
+    assert mx * dx <= 1e-13
+
+
+@pytest.mark.parametrize("solver", sorted(SOLVERS))
+def test_one_step_f32(solver):
+    p = inputs.abc_problem(32, 0.01, seed=1)
+    U, B = oracle.initial_state(p)
+    # both sides start from the same FP32-representable state
+    U = U.astype(np.float32).astype(np.float64)
+    B = B.astype(np.float32).astype(np.float64)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx, riemann=SOLVERS[solver])
+    s = Solver(riemann=solver, prec="f32")
+    lv = level_from(U, B, dx, torch.float32)
+    assert abs(s.cfl_dt(lv) - dt) <= 1e-5 * dt
+    s.step(lv, dt)
+    Ug, Bg = fetch(lv)
+    assert rel_err_f32(Ug, Uo, dt, dx) <= 1e-5
+    assert rel_err(Bg, Bo) <= 1e-5
+
+
+def test_diagnostics_parity():
+    p = inputs.smooth_problem(24, 20, 16, seed=7)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    rng = np.random.default_rng(0)
+    Bn = B + 1e-3 * rng.standard_normal(B.shape)   # non-zero divergence
+    s = Solver()
+    lv = level_from(U, Bn, dx)
+    mx, l1 = s.divb(lv)
+    d = oracle.divb(Bn, dx)
+    assert abs(mx - np.abs(d).max()) <= 1e-12 * np.abs(d).max()
+    assert abs(l1 - np.abs(d).mean()) <= 1e-12 * np.abs(d).mean()
+    sg = np.array(s.sums(lv))
+    so = oracle.sums(U, Bn, dx)
+    # a total is compared relative to the sum of magnitudes of its terms
+    # (the totals of momentum are zero up to round-off here)
+    scale = np.array([np.abs(U[m]).sum() for m in range(5)] + [0.0, 0.0]) * dx ** 3
+    scale = np.maximum(scale, np.abs(so))
+    assert np.all(np.abs(sg - so) <= 1e-12 * scale)
+
+
+def test_group_list_all_groups_equals_whole_grid():
+    p = inputs.abc_problem(32, 0.05, seed=2)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    s = Solver()
+    a = level_from(U, B, dx)
+    origins = [(i, j, k) for k in (0, 16) for j in (0, 16) for i in (0, 16)]
+    g = torch.tensor(origins, dtype=torch.int32, device="cuda")
+    b = level_from(U, B, dx, groups=g)
+    dt = s.cfl_dt(a)
+    s.step(a, dt)
+    s.step(b, dt)
+    Ua, Ba = fetch(a)
+    Ub, Bb = fetch(b)
+    assert np.array_equal(Ua, Ub) and np.array_equal(Ba, Bb)
+
+
+def test_group_list_subset():
+    # listed groups advance exactly as in the whole-grid update; the rest of
+    # the grid (ghosts) is untouched except faces shared with listed groups
+    p = inputs.smooth_problem(48, 32, 32, seed=4)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx)
+    s = Solver()
+    origins = [(16, 0, 0), (32, 16, 16)]
+    g = torch.tensor(origins, dtype=torch.int32, device="cuda")
+    lv = level_from(U, B, dx, groups=g)
+    s.step(lv, dt)
+    Ug, Bg = fetch(lv)
+    mask = np.zeros(U.shape[1:], bool)
+    for (i, j, k) in origins:
+        mask[k:k + 16, j:j + 16, i:i + 16] = True
+    for m in range(5):
+        assert np.abs(Ug[m][mask] - Uo[m][mask]).max() <= 1e-12 * np.abs(Uo[m]).max()
+        assert np.array_equal(Ug[m][~mask], U[m][~mask])
+    for a in range(3):
+        assert np.abs(Bg[a][mask] - Bo[a][mask]).max() <= 1e-12 * np.abs(Bo[a]).max()
+    # upper boundary faces of the listed groups (owned by ghost cells) advanced too
+    for (i, j, k) in origins:
+        ii = (i + 16) % 48
+        assert np.abs(Bg[0][k:k + 16, j:j + 16, ii] - Bo[0][k:k + 16, j:j + 16, ii]).max() <= 1e-12
+    # a face owned by a ghost cell away from the groups is untouched
+    assert Bg[0][0, 0, 0] == B[0][0, 0, 0]
+
+
+def test_determinism_and_devdt():
+    p = inputs.abc_problem(32, 0.05, seed=3)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    s = Solver()
+    a, b, c = level_from(U, B, dx), level_from(U, B, dx), level_from(U, B, dx)
+    dt = s.cfl_dt(a)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        s.step(a, dt)
+        s.step(b, dt)
+        s.step_devdt(c, dt_dev)
+    Ua, Ba = fetch(a)
+    Ub, Bb = fetch(b)
+    Uc, Bc = fetch(c)
+    assert np.array_equal(Ua, Ub) and np.array_equal(Ba, Bb)
+    assert np.array_equal(Ua, Uc) and np.array_equal(Ba, Bc)
+
+
+def test_roe_fallback_count_matches_oracle():
+    # two streams moving apart fast: near-vacuum linearised states at the
+    # separating faces, where Roe falls back to HLLE
+    n = 16
+    p = inputs.smooth_problem(n, 8, 8, seed=1, vamp=0.0)
+    p["p"][:] = 0.05
+    p["vx"][:] = np.where(np.arange(n)[None, None, :] < n // 2, -4.0, 4.0)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    _, _, nfb = oracle.step(U, B, dt, dx, return_fallbacks=True)
+    assert nfb > 0
+    s = Solver()
+    s.fallback_count()
+    lv = level_from(U, B, dx)
+    s.step(lv, dt)
+    assert s.fallback_count() == nfb
+
+
+def test_nonphysical_state_reported():
+    p = inputs.abc_problem(16, 0.0)
+    U, B = oracle.initial_state(p)
+    U[4, 3, 4, 5] = 0.1     # total energy below the magnetic energy: p < 0
+    s = Solver()
+    lv = level_from(U, B, p["dx"])
+    with pytest.raises(MHDError) as e:
+        s.cfl_dt(lv)
+    assert e.value.status == -5
+
+
+def test_full_size_one_step_128_f64():
+    # the benchmark's grid and launch configuration, compared everywhere
+    p = inputs.abc_problem(128, 0.01, seed=0)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx)
+    s = Solver()
+    lv = level_from(U, B, dx)
+    dtd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.advance(lv, dt_dev=dtd)
+    assert abs(dtd.item() - dt) <= 1e-13 * dt
+    Ug, Bg = fetch(lv)
+    assert rel_err(Ug, Uo) <= 1e-12
+    assert rel_err(Bg, Bo) <= 1e-12
