@@ -5,7 +5,7 @@
 #define MHD_ORACLE_H
 
 enum { OR_VL = 0, OR_CTU = 1 };
-enum { OR_PLM = 0, OR_PPM = 1, OR_FIRST_ORDER = 2, OR_PLM_UNLIMITED = 3 };
+enum { OR_PLM = 0, OR_PPM = 1, OR_FIRST_ORDER = 2, OR_PLM_UNLIMITED = 3, OR_PPM_UNLIMITED = 4 };
 enum { OR_ROE = 0, OR_HLLE = 1, OR_HLLD = 2 };
 
 int or_version(void);

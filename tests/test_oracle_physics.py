@@ -192,3 +192,89 @@ def test_thread_count_independence(orc):
     finally:
         orc.set_threads(n0)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------- CTU
+def ctu_wave_l1(orc, n, wave, recon, solver):
+    W5, B, T, dx = wave_setup(n, wave)
+    U = orc.prim_to_cons(W5, B)
+    W0 = orc.cons_to_prim(U, B)
+    U, B = run_to(orc, U, B, dx, T, scheme=1, recon=recon, riemann=solver)
+    return np.abs(orc.cons_to_prim(U, B) - W0).mean(axis=(1, 2, 3)).sum()
+
+
+@pytest.mark.parametrize("solver", [0, 2])
+def test_ctu_conservation_and_divergence(orc, solver):
+    p = inputs.smooth_problem(12, 10, 9, seed=4)
+    U, B = orc.initial_state(p)
+    dx = p["dx"]
+    s0 = orc.sums(U, B, dx)
+    for _ in range(5):
+        U, B = orc.step(U, B, orc.cfl_dt(U, B, dx), dx, scheme=1, recon=1, riemann=solver)
+    s1 = orc.sums(U, B, dx)
+    assert np.all(np.abs(s1[:5] - s0[:5]) <= 1e-13 * (1 + np.abs(s0[:5])))
+    assert np.abs(orc.divb(B, dx)).max() * dx < 1e-13
+
+
+def test_ctu_divergence_unchanged_for_any_face_field(orc):
+    rng = np.random.default_rng(10)
+    p = inputs.smooth_problem(8, 9, 10, seed=2)
+    U, B = orc.initial_state(p)
+    B = B + 0.01 * rng.standard_normal(B.shape)
+    dx = p["dx"]
+    d0 = orc.divb(B, dx)
+    _, B1 = orc.step(U, B, 0.2 * orc.cfl_dt(U, B, dx), dx, scheme=1, recon=1, riemann=2)
+    assert np.abs(orc.divb(B1, dx) - d0).max() * dx < 1e-13
+
+
+@pytest.mark.parametrize("wave", ["alfven", "slow"])
+def test_ctu_linear_wave_second_order_unlimited(orc, wave):
+    # unlimited fourth-order PPM edges isolate the integrator's order (the
+    # transverse corrections of CTU step 5 included)
+    e8 = ctu_wave_l1(orc, 8, wave, 4, 2)
+    e16 = ctu_wave_l1(orc, 16, wave, 4, 2)
+    assert e16 < e8 / 3.8
+
+
+@pytest.mark.parametrize("wave", ["fast", "alfven", "slow"])
+def test_ctu_ppm_hlld_linear_wave_converges(orc, wave):
+    e16 = ctu_wave_l1(orc, 16, wave, 1, 2)
+    e32 = ctu_wave_l1(orc, 32, wave, 1, 2)
+    assert e32 < e16 / 2.8
+
+
+def test_ctu_plm_roe_linear_wave_converges(orc):
+    # the paper's linear-wave combination: CTU + PLM + Roe (Sec. 4.1(i))
+    e16 = ctu_wave_l1(orc, 16, "fast", 0, 0)
+    e32 = ctu_wave_l1(orc, 32, "fast", 0, 0)
+    assert e32 < e16 / 2.5
+
+
+def test_ctu_boosted_abc_converges(orc):
+    def err(n, V0=0.1, T=0.05):
+        p = inputs.abc_problem(n, 0.0, drift=(V0, V0, V0))
+        U, B = orc.initial_state(p)
+        U, B = run_to(orc, U, B, p["dx"], T, scheme=1, recon=1, riemann=2)
+        d = 1.0 / n
+        k = 2 * math.pi
+        s = math.sin(k * d / 2) / (k * d / 2)
+        c = (np.arange(n) + 0.5) * d
+        X, Y, Z = c[None, None, :] - V0 * T, c[None, :, None] - V0 * T, c[:, None, None] - V0 * T
+        full = (n, n, n)
+        exact = np.stack([np.broadcast_to(s * (np.sin(k * Z) + np.cos(k * Y)), full),
+                          np.broadcast_to(s * (np.sin(k * X) + np.cos(k * Z)), full),
+                          np.broadcast_to(s * (np.sin(k * Y) + np.cos(k * X)), full)])
+        return np.abs(B - exact).mean()
+    assert err(32) < err(16) / 4.0
+
+
+def test_ctu_abc_cyclic_symmetry(orc):
+    p = inputs.abc_problem(12, 0.0, drift=(0.05, 0.05, 0.05))
+    U, B = orc.initial_state(p)
+    dx = p["dx"]
+    for _ in range(3):
+        U, B = orc.step(U, B, orc.cfl_dt(U, B, dx), dx, scheme=1, recon=1, riemann=2)
+    Uc, Bc = cyclic(U, B)
+    assert np.abs(Bc - B).max() <= 1e-13 * np.abs(B).max()
+    for m in range(5):
+        assert np.abs(Uc[m] - U[m]).max() <= 1e-13 * max(np.abs(U[m]).max(), 1.0)
