@@ -34,6 +34,9 @@ struct mhd_ctx_s {
   void* Bh;               // 3 * cap
   void* F;                // 21 * cap
   void* E;                // 3 * cap
+  void* QL;               // CTU: 21 * cap, states below each face
+  void* QR;               // CTU: 21 * cap, states above each face
+  void* F2;               // CTU: 21 * cap, corrector fluxes
   double* parts;          // reduction partials
   double* dres;           // 8 device doubles of reduction results
   unsigned long long* smax;
@@ -56,9 +59,8 @@ int check_config(const mhd_config* c) {
   if (c->prec < MHD_F64 || c->prec > MHD_F32_MIXED) return MHD_ERR_INVALID_ARG;
   if (!valid_gamma(c->gamma)) return MHD_ERR_INVALID_ARG;
   if (!(c->courant > 0.0 && c->courant <= 1.0)) return MHD_ERR_INVALID_ARG;
-  // implemented combinations
-  if (c->scheme != MHD_VL) return MHD_ERR_UNSUPPORTED;
-  if (c->recon != MHD_PLM) return MHD_ERR_UNSUPPORTED;
+  // implemented combinations: VL with PLM; CTU with PLM or PPM
+  if (c->scheme == MHD_VL && c->recon != MHD_PLM) return MHD_ERR_UNSUPPORTED;
   if (c->riemann == MHD_MLP) return MHD_ERR_UNSUPPORTED;
   if (c->prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
   return MHD_OK;
@@ -88,16 +90,26 @@ int check_level(const mhd_ctx_s* ctx, const mhd_level* lv) {
     if ((x) != hipSuccess) return MHD_ERR_HIP;     \
   } while (0)
 
+void free_scratch(mhd_ctx_s* c) {
+  void** bufs[] = {&c->W, &c->Bh, &c->F, &c->E, &c->QL, &c->QR, &c->F2};
+  for (void** b : bufs) {
+    hipFree(*b);
+    *b = nullptr;
+  }
+  c->cap_cells = 0;
+}
+
 int ensure_capacity(mhd_ctx_s* c, long long cells) {
   if (cells <= c->cap_cells) return MHD_OK;
-  hipFree(c->W); hipFree(c->Bh); hipFree(c->F); hipFree(c->E);
-  c->W = c->Bh = c->F = c->E = nullptr;
-  c->cap_cells = 0;
+  free_scratch(c);
   const size_t e = c->elem;
-  if (hipMalloc(&c->W, 8 * cells * e) != hipSuccess || hipMalloc(&c->Bh, 3 * cells * e) != hipSuccess ||
-      hipMalloc(&c->F, 21 * cells * e) != hipSuccess || hipMalloc(&c->E, 3 * cells * e) != hipSuccess) {
-    hipFree(c->W); hipFree(c->Bh); hipFree(c->F); hipFree(c->E);
-    c->W = c->Bh = c->F = c->E = nullptr;
+  bool ok = hipMalloc(&c->W, 8 * cells * e) == hipSuccess && hipMalloc(&c->Bh, 3 * cells * e) == hipSuccess &&
+            hipMalloc(&c->F, 21 * cells * e) == hipSuccess && hipMalloc(&c->E, 3 * cells * e) == hipSuccess;
+  if (ok && c->cfg.scheme == MHD_CTU)
+    ok = hipMalloc(&c->QL, 21 * cells * e) == hipSuccess && hipMalloc(&c->QR, 21 * cells * e) == hipSuccess &&
+         hipMalloc(&c->F2, 21 * cells * e) == hipSuccess;
+  if (!ok) {
+    free_scratch(c);
     return MHD_ERR_OUT_OF_MEMORY;
   }
   c->cap_cells = cells;
@@ -161,9 +173,15 @@ int build_occupancy(mhd_ctx_s* c, const mhd_level* lv) {
 unsigned nblocks(const Work& w) { return (unsigned)((w.items + kBlock - 1) / kBlock); }
 
 // Stage names in launch order (used by mhd_profile_step).
-const char* const kStageNames[] = {"prim", "flux_predict", "emf_predict", "half_step",
-                                   "flux_correct", "emf_correct", "final"};
-constexpr int kNumStages = 7;
+const char* const kStageNamesVL[] = {"prim", "flux_predict", "emf_predict", "half_step",
+                                     "flux_correct", "emf_correct", "final"};
+const char* const kStageNamesCTU[] = {"prim", "states", "flux_predict", "emf_predict", "half_step",
+                                      "flux_correct", "emf_correct", "final"};
+constexpr int kMaxStages = 8;
+int num_stages(const mhd_ctx_s* c) { return c->cfg.scheme == MHD_CTU ? 8 : 7; }
+const char* stage_name(const mhd_ctx_s* c, int s) {
+  return c->cfg.scheme == MHD_CTU ? kStageNamesCTU[s] : kStageNamesVL[s];
+}
 
 // ev (optional): kNumStages + 1 events recorded around the stage kernels
 template <typename T, int S>
@@ -206,12 +224,76 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
   mark(7);
 }
 
+// CTU, paper Sec. 3.2 steps 1-8:
+//   k_prim         U^n, B^n             -> W^n
+//   k_ctu_states   W^n, B^n, dt         -> QL, QR     step 1 (PPM/PLM + tracing)
+//   k_flux_q       QL, QR, B^n          -> F1         step 2
+//   k_emf          F1, W^n              -> E          step 3
+//   k_half         U^n, B^n, F1, E      -> W^{n+1/2}, B^{n+1/2}   step 4
+//   k_ctu_correct  QL, QR, F1, E, B^{n+1/2} -> F2     steps 5-6
+//   k_emf          F2, W^{n+1/2}        -> E          step 7
+//   k_final        U^n, B^n, F2, E      -> U^{n+1}, B^{n+1}   step 8
+// Group halos (cells below, above each group): 4,4 / 2,2 / 2,2 / 1,2 / 1,1 /
+// 1,1 / 0,1 / 0,0, i.e. 4 ghost cells of U^n.
+template <typename T, int S, int R>
+void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
+  hipStream_t st = c->stream;
+  T* U = (T*)lv->U;
+  T* B = (T*)lv->B;
+  T* W = (T*)c->W;
+  T* Bh = (T*)c->Bh;
+  T* F1 = (T*)c->F;
+  T* F2 = (T*)c->F2;
+  T* E = (T*)c->E;
+  T* QL = (T*)c->QL;
+  T* QR = (T*)c->QR;
+  const T gam = (T)c->cfg.gamma;
+  const T inv_dx = (T)(1.0 / lv->dx);
+  const Work wp = make_work(lv, 4, 4), wq = make_work(lv, 2, 2), wf1 = make_work(lv, 2, 2);
+  const Work we1 = make_work(lv, 1, 2), wh = make_work(lv, 1, 1), wf2 = make_work(lv, 1, 1);
+  const Work we2 = make_work(lv, 0, 1);
+  Work wu = make_work(lv, 0, 0);
+  wu.occ = c->occ;
+  auto mark = [&](int s) {
+    if (ev) (void)hipEventRecord(ev[s], st);
+  };
+  mark(0);
+  if (cfl) {
+    k_reset_smax<<<1, 1, 0, st>>>(c->smax);
+    k_prim<T, true><<<nblocks(wp), kBlock, 0, st>>>(wp, U, B, W, gam, c->smax, c->flag);
+  } else {
+    k_prim<T, false><<<nblocks(wp), kBlock, 0, st>>>(wp, U, B, W, gam, c->smax, c->flag);
+  }
+  mark(1);
+  k_ctu_states<T, R><<<nblocks(wq), kBlock, 0, st>>>(wq, W, B, QL, QR, dts, inv_dx, gam);
+  mark(2);
+  k_flux_q<T, S><<<nblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->nfb);
+  mark(3);
+  k_emf<T><<<nblocks(we1), kBlock, 0, st>>>(we1, F1, W, E);
+  mark(4);
+  k_half<T><<<nblocks(wh), kBlock, 0, st>>>(wh, U, B, F1, E, dts, inv_dx, gam, W, Bh);
+  mark(5);
+  k_ctu_correct<T, S><<<nblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->nfb);
+  mark(6);
+  k_emf<T><<<nblocks(we2), kBlock, 0, st>>>(we2, F2, W, E);
+  mark(7);
+  k_final<T><<<nblocks(wu), kBlock, 0, st>>>(wu, U, B, F2, E, dts, inv_dx);
+  mark(8);
+}
+
+template <typename T, int S>
+void launch_scheme(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
+  if (c->cfg.scheme == MHD_VL) launch_step<T, S>(c, lv, dts, cfl, ev);
+  else if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1>(c, lv, dts, cfl, ev);
+  else launch_ctu<T, S, 0>(c, lv, dts, cfl, ev);
+}
+
 template <typename T>
 void launch_step_t(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
   switch (c->cfg.riemann) {
-    case MHD_ROE: launch_step<T, 0>(c, lv, dts, cfl, ev); break;
-    case MHD_HLLE: launch_step<T, 1>(c, lv, dts, cfl, ev); break;
-    default: launch_step<T, 2>(c, lv, dts, cfl, ev); break;
+    case MHD_ROE: launch_scheme<T, 0>(c, lv, dts, cfl, ev); break;
+    case MHD_HLLE: launch_scheme<T, 1>(c, lv, dts, cfl, ev); break;
+    default: launch_scheme<T, 2>(c, lv, dts, cfl, ev); break;
   }
 }
 
@@ -294,7 +376,7 @@ int mhd_finalize(mhd_ctx c) {
   if (!c) return MHD_ERR_INVALID_ARG;
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
-  hipFree(c->W); hipFree(c->Bh); hipFree(c->F); hipFree(c->E);
+  free_scratch(c);
   hipFree(c->parts); hipFree(c->dres); hipFree(c->smax); hipFree(c->flag); hipFree(c->nfb); hipFree(c->occ);
   if (c->host) hipHostFree(c->host);
   delete c;
@@ -371,36 +453,37 @@ int mhd_advance(mhd_ctx c, const mhd_level* lv, double* dt_dev, double* t_dev) {
 
 int mhd_num_stages(mhd_ctx c) {
   if (!c) return MHD_ERR_INVALID_ARG;
-  return kNumStages;
+  return num_stages(c);
 }
 
 const char* mhd_stage_name(mhd_ctx c, int stage) {
-  if (!c || stage < 0 || stage >= kNumStages) return nullptr;
-  return kStageNames[stage];
+  if (!c || stage < 0 || stage >= num_stages(c)) return nullptr;
+  return stage_name(c, stage);
 }
 
 int mhd_profile_step(mhd_ctx c, const mhd_level* lv, int nrep, double* stage_ms) {
   if (!c || !lv || nrep <= 0 || !stage_ms) return MHD_ERR_INVALID_ARG;
   int rc = check_level(c, lv);
   if (rc) return rc;
-  hipEvent_t ev[kNumStages + 1];
-  for (int s = 0; s <= kNumStages; ++s)
+  const int ns = num_stages(c);
+  hipEvent_t ev[kMaxStages + 1];
+  for (int s = 0; s <= ns; ++s)
     if (hipEventCreate(&ev[s]) != hipSuccess) return MHD_ERR_HIP;
-  for (int s = 0; s < kNumStages; ++s) stage_ms[s] = 0.0;
+  for (int s = 0; s < ns; ++s) stage_ms[s] = 0.0;
   DtSrc dts{0.0, nullptr, c->smax, c->cfg.courant * lv->dx};
   for (int r = 0; r < nrep && rc == MHD_OK; ++r) {
     rc = do_step(c, lv, dts, true, ev);
     if (rc) break;
-    if (hipEventSynchronize(ev[kNumStages]) != hipSuccess) { rc = MHD_ERR_HIP; break; }
-    for (int s = 0; s < kNumStages; ++s) {
+    if (hipEventSynchronize(ev[ns]) != hipSuccess) { rc = MHD_ERR_HIP; break; }
+    for (int s = 0; s < ns; ++s) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[s], ev[s + 1]) != hipSuccess) { rc = MHD_ERR_HIP; break; }
       stage_ms[s] += ms;
     }
   }
-  for (int s = 0; s <= kNumStages; ++s) (void)hipEventDestroy(ev[s]);
+  for (int s = 0; s <= ns; ++s) (void)hipEventDestroy(ev[s]);
   if (rc) return rc;
-  for (int s = 0; s < kNumStages; ++s) stage_ms[s] /= nrep;
+  for (int s = 0; s < ns; ++s) stage_ms[s] /= nrep;
   return MHD_OK;
 }
 

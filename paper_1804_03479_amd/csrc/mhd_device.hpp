@@ -364,4 +364,164 @@ __device__ __forceinline__ T minmod(T a, T b) {
   return a > T(0) ? dmin(a, b) : dmax(a, b);
 }
 
+// monotonised-central slope of q0 between neighbours qm and qp
+template <typename T>
+__device__ __forceinline__ T mc_slope(T qm, T q0, T qp) {
+  const T dl = q0 - qm, dr = qp - q0;
+  if (dl * dr <= T(0)) return T(0);
+  const T dc = T(0.5) * (qp - qm);
+  const T m = dmin(dabs(dc), T(2) * dmin(dabs(dl), dabs(dr)));
+  return dc > T(0) ? m : -m;
+}
+
+// PPM (Colella & Woodward 1984) edge values of the centre of q0..q4:
+// interface values from MC-limited slopes, then the monotonicity constraints
+template <typename T>
+__device__ __forceinline__ void ppm_edges(T q0, T q1, T q2, T q3, T q4, T& ql, T& qr) {
+  const T dm = mc_slope(q0, q1, q2), d0 = mc_slope(q1, q2, q3), dp = mc_slope(q2, q3, q4);
+  T l = T(0.5) * (q1 + q2) - (d0 - dm) * T(1.0 / 6.0);
+  T r = T(0.5) * (q2 + q3) - (dp - d0) * T(1.0 / 6.0);
+  const T c = q2;
+  if ((r - c) * (c - l) <= T(0)) {
+    l = c;
+    r = c;
+  } else {
+    const T dq = r - l, m6 = dq * (c - T(0.5) * (l + r)), dq2 = dq * dq * T(1.0 / 6.0);
+    if (m6 > dq2) l = T(3) * c - T(2) * r;
+    else if (-dq2 > m6) r = T(3) * c - T(2) * l;
+  }
+  ql = l;
+  qr = r;
+}
+
+// Characteristic tracing of one cell for the CTU predictor (Colella 1990):
+// q[s][m] holds the 1D primitive states of cells -2..2 along the direction,
+// (bn_lo, bn_hi) the cell's two normal-face fields.  Each edge state starts
+// at the reconstructed edge value; every wave moving toward that edge
+// subtracts its share of the profile's average over its domain of dependence
+// during dt (xi = lam dt/dx).  RECON: 0 minmod PLM, 1 PPM.  Then the
+// transverse field gets (dt/2) v_t dBn/dn.  A non-physical result falls back
+// to the cell state.  sl: lower edge, sr: upper edge.
+template <typename T, int RECON>
+__device__ __forceinline__ void trace_cell(const T q[5][7], T bn_lo, T bn_hi, T dtdx, T gam, T sl[7],
+                                           T sr[7]) {
+  T dq[7], q6[7];
+#pragma unroll
+  for (int m = 0; m < 7; ++m) {
+    T l, r;
+    if (RECON == 1) {
+      ppm_edges(q[0][m], q[1][m], q[2][m], q[3][m], q[4][m], l, r);
+    } else {
+      const T s = minmod(q[2][m] - q[1][m], q[3][m] - q[2][m]);
+      l = q[2][m] - T(0.5) * s;
+      r = q[2][m] + T(0.5) * s;
+    }
+    sl[m] = l;
+    sr[m] = r;
+    dq[m] = r - l;
+    q6[m] = T(6) * (q[2][m] - T(0.5) * (l + r));
+  }
+  // primitive eigen-system of the cell (Roe & Balsara normalisation)
+  const T d = q[2][0], u = q[2][1], p = q[2][4], by = q[2][5], bz = q[2][6];
+  const T bn = T(0.5) * (bn_lo + bn_hi);
+  const T id = T(1) / d;
+  const T asq = gam * p * id, a = dsqrt(asq);
+  const T casq = bn * bn * id, ctsq = (by * by + bz * bz) * id;
+  const T sum = asq + casq + ctsq, dif = casq + ctsq - asq;
+  const T cfsq = T(0.5) * (sum + dsqrt(dif * dif + T(4) * asq * ctsq));
+  const T cssq = asq * casq / cfsq;
+  const T cf = dsqrt(cfsq), cs = dsqrt(cssq), ca = dsqrt(casq);
+  const T bt = dsqrt(by * by + bz * bz);
+  T b2, b3;
+  if (bt > T(0)) {
+    const T ib = T(1) / bt;
+    b2 = by * ib;
+    b3 = bz * ib;
+  } else {
+    b2 = T(0.70710678118654752440);
+    b3 = T(0.70710678118654752440);
+  }
+  T af, as;
+  if (cfsq - cssq <= T(0)) { af = T(1); as = T(0); }
+  else if (asq - cssq <= T(0)) { af = T(0); as = T(1); }
+  else if (cfsq - asq <= T(0)) { af = T(1); as = T(0); }
+  else {
+    const T inv = T(1) / (cfsq - cssq);
+    af = dsqrt((asq - cssq) * inv);
+    as = dsqrt((cfsq - asq) * inv);
+  }
+  const T sg = bn >= T(0) ? T(1) : T(-1), sd = dsqrt(d), isd = T(1) / sd;
+  const T Cff = cf * af, Css = cs * as, Qf = cf * af * sg, Qs = cs * as * sg, Af = a * af * sd, As = a * as * sd;
+  const T nrm = T(0.5) / asq;
+  auto apply = [&](T lam, const T l[7], const T r[7]) {
+    const T xi = lam * dtdx;
+    if (xi == T(0)) return;
+    T ad = T(0), a6 = T(0);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      ad += l[m] * dq[m];
+      a6 += l[m] * q6[m];
+    }
+    if (xi > T(0)) {
+      const T amp = T(0.5) * xi * (ad - (T(1) - T(2.0 / 3.0) * xi) * a6);
+#pragma unroll
+      for (int m = 0; m < 7; ++m) sr[m] -= amp * r[m];
+    } else {
+      const T ax = -xi;
+      const T amp = T(0.5) * ax * (ad + (T(1) - T(2.0 / 3.0) * ax) * a6);
+#pragma unroll
+      for (int m = 0; m < 7; ++m) sl[m] += amp * r[m];
+    }
+  };
+  {
+    const T l[7] = {T(0), -nrm * Cff, nrm * Qs * b2, nrm * Qs * b3, nrm * af * id, nrm * As * b2 * id, nrm * As * b3 * id};
+    const T r[7] = {d * af, -Cff, Qs * b2, Qs * b3, d * asq * af, As * b2, As * b3};
+    apply(u - cf, l, r);
+  }
+  {
+    const T l[7] = {T(0), T(0), T(-0.5) * b3, T(0.5) * b2, T(0), T(-0.5) * sg * b3 * isd, T(0.5) * sg * b2 * isd};
+    const T r[7] = {T(0), T(0), -b3, b2, T(0), -sg * sd * b3, sg * sd * b2};
+    apply(u - ca, l, r);
+  }
+  {
+    const T l[7] = {T(0), -nrm * Css, -nrm * Qf * b2, -nrm * Qf * b3, nrm * as * id, -nrm * Af * b2 * id, -nrm * Af * b3 * id};
+    const T r[7] = {d * as, -Css, -Qf * b2, -Qf * b3, d * asq * as, -Af * b2, -Af * b3};
+    apply(u - cs, l, r);
+  }
+  {
+    const T l[7] = {T(1), T(0), T(0), T(0), -T(1) / asq, T(0), T(0)};
+    const T r[7] = {T(1), T(0), T(0), T(0), T(0), T(0), T(0)};
+    apply(u, l, r);
+  }
+  {
+    const T l[7] = {T(0), nrm * Css, nrm * Qf * b2, nrm * Qf * b3, nrm * as * id, -nrm * Af * b2 * id, -nrm * Af * b3 * id};
+    const T r[7] = {d * as, Css, Qf * b2, Qf * b3, d * asq * as, -Af * b2, -Af * b3};
+    apply(u + cs, l, r);
+  }
+  {
+    const T l[7] = {T(0), T(0), T(0.5) * b3, T(-0.5) * b2, T(0), T(-0.5) * sg * b3 * isd, T(0.5) * sg * b2 * isd};
+    const T r[7] = {T(0), T(0), b3, -b2, T(0), -sg * sd * b3, sg * sd * b2};
+    apply(u + ca, l, r);
+  }
+  {
+    const T l[7] = {T(0), nrm * Cff, -nrm * Qs * b2, -nrm * Qs * b3, nrm * af * id, nrm * As * b2 * id, nrm * As * b3 * id};
+    const T r[7] = {d * af, Cff, -Qs * b2, -Qs * b3, d * asq * af, As * b2, As * b3};
+    apply(u + cf, l, r);
+  }
+  // multidimensional source term of the transverse field
+  const T hb = T(0.5) * dtdx * (bn_hi - bn_lo);   // (dt/2) dBn/dn
+  sl[5] += hb * q[2][2];
+  sl[6] += hb * q[2][3];
+  sr[5] += hb * q[2][2];
+  sr[6] += hb * q[2][3];
+  if (!(sl[0] > T(0)) || !(sl[4] > T(0))) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) sl[m] = q[2][m];
+  }
+  if (!(sr[0] > T(0)) || !(sr[4] > T(0))) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) sr[m] = q[2][m];
+  }
+}
+
 }  // namespace mhd

@@ -158,7 +158,9 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* s
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int q = 1; q < kBlock / 64; ++q) m = fmax(m, red[q]);
-    if (m > 0.0) atomicMax(smax, (unsigned long long)__double_as_longlong(m));
+    // most blocks see a maximum already reached: skip their atomic
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+    if (m > 0.0 && bits > *(volatile unsigned long long*)smax) atomicMax(smax, bits);
   }
 }
 
@@ -443,6 +445,181 @@ __global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* 
   if (ex) B[nbr(w, i, j, k, 1, 0, 0)] = ux[0];
   if (ey) B[N + nbr(w, i, j, k, 0, 1, 0)] = uy[1];
   if (ez) B[2 * N + nbr(w, i, j, k, 0, 0, 1)] = uz[2];
+}
+
+// ------------------------------------------------------------ CTU
+// Step 1 of CTU: time-centred states at both edges of every cell in each
+// direction.  Face-indexed outputs: QR[d][m][p] is the state above the lower
+// d-face of cell p (from cell p), QL[d][m][p] the state below it (from the
+// cell p - e_d; written by that cell as its upper-edge state).
+template <typename T, int D, int RECON>
+__device__ __forceinline__ void cell_states(const Work& w, const T* __restrict__ W, const T* __restrict__ B,
+                                            T* __restrict__ QL, T* __restrict__ QR, int i, int j, int k, T dtdx,
+                                            T gam) {
+  const long long N = w.N;
+  T q[5][7];
+#pragma unroll
+  for (int s = -2; s <= 2; ++s) {
+    const long long c = nbr(w, i, j, k, D == 0 ? s : 0, D == 1 ? s : 0, D == 2 ? s : 0);
+    load_w1d<T, D>(W, N, c, q[s + 2]);
+  }
+  const long long p = lin(w, i, j, k);
+  const long long pu = nbr(w, i, j, k, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0);
+  T sl[7], sr[7];
+  trace_cell<T, RECON>(q, B[D * N + p], B[D * N + pu], dtdx, gam, sl, sr);
+#pragma unroll
+  for (int m = 0; m < 7; ++m) {
+    QR[((long long)D * 7 + m) * N + p] = sl[m];
+    QL[((long long)D * 7 + m) * N + pu] = sr[m];
+  }
+}
+
+template <typename T, int RECON>
+__global__ void __launch_bounds__(kBlock) k_ctu_states(Work w, const T* __restrict__ W, const T* __restrict__ B,
+                                                       T* __restrict__ QL, T* __restrict__ QR, DtSrc dts,
+                                                       T inv_dx, T gam) {
+  int i, j, k;
+  if (!my_cell(w, i, j, k)) return;
+  const T dtdx = T(get_dt(dts)) * inv_dx;
+  cell_states<T, 0, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
+  cell_states<T, 1, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
+  cell_states<T, 2, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void store_flux(T* __restrict__ F, long long N, long long p, const T f[7]) {
+  constexpr int n = D, t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  T* Fd = F + (long long)D * 7 * N;
+  Fd[p] = f[0];
+  Fd[(1 + n) * N + p] = f[1];
+  Fd[(1 + t1) * N + p] = f[2];
+  Fd[(1 + t2) * N + p] = f[3];
+  Fd[4 * N + p] = f[4];
+  Fd[5 * N + p] = f[6];
+  Fd[6 * N + p] = -f[5];
+}
+
+// Step 2: Riemann fluxes from the stored states with the time-n normal field
+template <typename T, int SOLVER>
+__global__ void __launch_bounds__(kBlock) k_flux_q(Work w, const T* __restrict__ QL, const T* __restrict__ QR,
+                                                   const T* __restrict__ B, T* __restrict__ F, T gam,
+                                                   unsigned long long* nfb) {
+  int i, j, k;
+  int fb = 0;
+  if (my_cell(w, i, j, k)) {
+    const long long N = w.N;
+    const long long p = lin(w, i, j, k);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      T wl[7], wr[7], f[7];
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        wl[m] = QL[((long long)d * 7 + m) * N + p];
+        wr[m] = QR[((long long)d * 7 + m) * N + p];
+      }
+      fb += riemann<SOLVER>(wl, wr, B[d * N + p], gam, f);
+      if (d == 0) store_flux<T, 0>(F, N, p, f);
+      else if (d == 1) store_flux<T, 1>(F, N, p, f);
+      else store_flux<T, 2>(F, N, p, f);
+    }
+  }
+  if (SOLVER == 0) block_count_atomic(fb, nfb);
+}
+
+// Step 5: transverse correction of a state of direction D that comes from
+// cell (ci, cj, ck) and sits on a face with time-n normal field bn.  Hydro
+// variables: minus dt/2 times the transverse flux differences of step 2 in
+// that cell.  Transverse field: dt/2 times the transverse part of -curl E
+// with the step-3 edge EMFs E_D averaged to the cell's faces.  The normal
+// field of the conversion is kept.  Non-physical results keep the input.
+template <typename T, int D>
+__device__ __forceinline__ void correct_state(const Work& w, const T* __restrict__ F1, const T* __restrict__ E1,
+                                              int ci, int cj, int ck, T bn, T hr, T gam, const T s[7], T out[7]) {
+  constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  const long long N = w.N;
+  T v[3], b[3];
+  v[D] = s[1]; v[t1] = s[2]; v[t2] = s[3];
+  b[D] = bn; b[t1] = s[5]; b[t2] = s[6];
+  T u[5];
+  u[0] = s[0];
+  u[1] = s[0] * v[0];
+  u[2] = s[0] * v[1];
+  u[3] = s[0] * v[2];
+  u[4] = s[4] / (gam - T(1)) + T(0.5) * s[0] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) +
+         T(0.5) * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  const long long c = lin(w, ci, cj, ck);
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt) {
+    const int t = tt ? t2 : t1;
+    const long long cp = nbr(w, ci, cj, ck, t == 0, t == 1, t == 2);
+    const T* Ft = F1 + (long long)t * 7 * N;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) u[m] -= hr * (Ft[m * N + cp] - Ft[m * N + c]);
+  }
+  const T* Ed = E1 + (long long)D * N;
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt) {
+    const int bax = tt ? t2 : t1;
+    const int der = (bax == (D + 2) % 3) ? (D + 1) % 3 : (D + 2) % 3;
+    const long long e_der = nbr(w, ci, cj, ck, der == 0, der == 1, der == 2);
+    const long long e_b = nbr(w, ci, cj, ck, bax == 0, bax == 1, bax == 2);
+    const long long e_db = nbr(w, ci, cj, ck, (der == 0) + (bax == 0), (der == 1) + (bax == 1), (der == 2) + (bax == 2));
+    const T up = T(0.5) * (Ed[e_der] + Ed[e_db]);
+    const T lo = T(0.5) * (Ed[c] + Ed[e_b]);
+    const T sign = (D == (bax + 1) % 3) ? T(1) : T(-1);
+    b[bax] += hr * sign * (up - lo);
+  }
+  const T id = T(1) / u[0];
+  const T vx = u[1] * id, vy = u[2] * id, vz = u[3] * id;
+  const T pr = (gam - T(1)) * (u[4] - T(0.5) * u[0] * (vx * vx + vy * vy + vz * vz) -
+                               T(0.5) * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]));
+  if (u[0] > T(0) && pr > T(0)) {
+    const T vv[3] = {vx, vy, vz};
+    out[0] = u[0]; out[1] = vv[D]; out[2] = vv[t1]; out[3] = vv[t2]; out[4] = pr; out[5] = b[t1]; out[6] = b[t2];
+  } else {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) out[m] = s[m];
+  }
+}
+
+template <typename T, int D, int SOLVER>
+__device__ __forceinline__ int corrected_face_flux(const Work& w, const T* __restrict__ QL, const T* __restrict__ QR,
+                                                   const T* __restrict__ F1, const T* __restrict__ E1,
+                                                   const T* __restrict__ B, const T* __restrict__ Bh,
+                                                   T* __restrict__ F2, int i, int j, int k, T hr, T gam) {
+  const long long N = w.N;
+  const long long p = lin(w, i, j, k);
+  T sl[7], sr[7], wl[7], wr[7], f[7];
+#pragma unroll
+  for (int m = 0; m < 7; ++m) {
+    sl[m] = QL[((long long)D * 7 + m) * N + p];
+    sr[m] = QR[((long long)D * 7 + m) * N + p];
+  }
+  const T bn = B[D * N + p];
+  correct_state<T, D>(w, F1, E1, wrapc(i - (D == 0), w.nx), wrapc(j - (D == 1), w.ny), wrapc(k - (D == 2), w.nz), bn,
+                      hr, gam, sl, wl);
+  correct_state<T, D>(w, F1, E1, i, j, k, bn, hr, gam, sr, wr);
+  const int fb = riemann<SOLVER>(wl, wr, Bh[D * N + p], gam, f);
+  store_flux<T, D>(F2, N, p, f);
+  return fb;
+}
+
+// Steps 5-6: corrected states and Riemann fluxes with the half-step normal field
+template <typename T, int SOLVER>
+__global__ void __launch_bounds__(kBlock) k_ctu_correct(Work w, const T* __restrict__ QL, const T* __restrict__ QR,
+                                                        const T* __restrict__ F1, const T* __restrict__ E1,
+                                                        const T* __restrict__ B, const T* __restrict__ Bh,
+                                                        T* __restrict__ F2, DtSrc dts, T inv_dx, T gam,
+                                                        unsigned long long* nfb) {
+  int i, j, k;
+  int fb = 0;
+  if (my_cell(w, i, j, k)) {
+    const T hr = T(0.5 * get_dt(dts)) * inv_dx;
+    fb += corrected_face_flux<T, 0, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam);
+    fb += corrected_face_flux<T, 1, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam);
+    fb += corrected_face_flux<T, 2, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam);
+  }
+  if (SOLVER == 0) block_count_atomic(fb, nfb);
 }
 
 // group occupancy map of a list: clear, then mark

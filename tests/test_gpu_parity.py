@@ -267,3 +267,120 @@ def test_full_size_one_step_128_f64():
     Ug, Bg = fetch(lv)
     assert rel_err(Ug, Uo) <= 1e-12
     assert rel_err(Bg, Bo) <= 1e-12
+
+
+# ---------------------------------------------------------------- CTU
+CTU_CASES = [("ppm", "hlld"), ("ppm", "roe"), ("plm", "roe"), ("plm", "hlld"), ("ppm", "hlle")]
+RECON = {"plm": oracle.PLM, "ppm": oracle.PPM}
+
+
+@pytest.mark.parametrize("recon,solver", CTU_CASES)
+@pytest.mark.parametrize("prob", sorted(PROBLEMS))
+def test_ctu_one_step_f64(prob, recon, solver):
+    p = PROBLEMS[prob]()
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx, scheme=oracle.CTU, recon=RECON[recon], riemann=SOLVERS[solver])
+    s = Solver("ctu", recon, solver)
+    lv = level_from(U, B, dx)
+    s.step(lv, dt)
+    Ug, Bg = fetch(lv)
+    assert rel_err(Ug, Uo) <= 1e-12
+    assert rel_err(Bg, Bo) <= 1e-12
+
+
+def test_ctu_ten_steps_abc32_f64():
+    p = inputs.abc_problem(32, 0.1, seed=0)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    Uo, Bo, t_o, _ = oracle.run(U, B, 10, dx, scheme=oracle.CTU, recon=oracle.PPM, riemann=oracle.HLLD)
+    s = Solver("ctu", "ppm", "hlld")
+    lv = level_from(U, B, dx)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(10):
+        s.advance(lv, t_dev=t)
+    Ug, Bg = fetch(lv)
+    assert abs(t.item() - t_o) <= 1e-13 * t_o
+    assert rel_err(Ug, Uo) <= 1e-12
+    assert rel_err(Bg, Bo) <= 1e-12
+
+
+def l1_rel(a, b):
+    """worst per-component mean |a - b| / mean |b|"""
+    return max(np.abs(a[m] - b[m]).mean() / max(np.abs(b[m]).mean(), 1e-300) for m in range(a.shape[0]))
+
+
+def ctu_f32_step(prob, solver, recon="ppm"):
+    U, B = oracle.initial_state(prob)
+    U = U.astype(np.float32).astype(np.float64)
+    B = B.astype(np.float32).astype(np.float64)
+    dx = prob["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx, scheme=oracle.CTU, recon=RECON[recon], riemann=SOLVERS[solver])
+    s = Solver("ctu", recon, solver, prec="f32")
+    lv = level_from(U, B, dx, torch.float32)
+    s.step(lv, dt)
+    Ug, Bg = fetch(lv)
+    return Ug, Bg, Uo, Bo, dt, dx
+
+
+@pytest.mark.parametrize("solver", ["hlld", "roe"])
+def test_ctu_one_step_f32_smooth(solver):
+    # smooth input: no limiter decision sits within FP32 rounding of its
+    # threshold, so the infinity-norm bar applies
+    Ug, Bg, Uo, Bo, dt, dx = ctu_f32_step(inputs.smooth_problem(24, 20, 16, seed=8), solver)
+    assert rel_err_f32(Ug, Uo, dt, dx) <= 1e-5
+    assert rel_err(Bg, Bo) <= 1e-5
+
+
+@pytest.mark.parametrize("solver", ["hlld", "roe"])
+def test_ctu_one_step_f32_noisy_abc(solver):
+    # cell-scale noise puts some of PPM's discontinuous extremum tests within
+    # FP32 rounding of their threshold; a flipped decision moves one edge
+    # value by a slope-sized amount, so the bar is stated in L1, with a loose
+    # infinity-norm guard
+    Ug, Bg, Uo, Bo, dt, dx = ctu_f32_step(inputs.abc_problem(32, 0.1, seed=1), solver)
+    assert l1_rel(Ug, Uo) <= 1e-5
+    assert l1_rel(Bg, Bo) <= 1e-5
+    assert rel_err_f32(Ug, Uo, dt, dx) <= 1e-3
+    assert rel_err(Bg, Bo) <= 1e-3
+
+
+def test_ctu_group_list_subset():
+    p = inputs.smooth_problem(48, 32, 32, seed=6)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx, scheme=oracle.CTU, recon=oracle.PPM, riemann=oracle.HLLD)
+    s = Solver("ctu", "ppm", "hlld")
+    origins = [(0, 16, 0), (16, 16, 0), (32, 0, 16)]
+    g = torch.tensor(origins, dtype=torch.int32, device="cuda")
+    lv = level_from(U, B, dx, groups=g)
+    s.step(lv, dt)
+    Ug, Bg = fetch(lv)
+    mask = np.zeros(U.shape[1:], bool)
+    for (i, j, k) in origins:
+        mask[k:k + 16, j:j + 16, i:i + 16] = True
+    for m in range(5):
+        assert np.abs(Ug[m][mask] - Uo[m][mask]).max() <= 1e-12 * np.abs(Uo[m]).max()
+        assert np.array_equal(Ug[m][~mask], U[m][~mask])
+    for a in range(3):
+        assert np.abs(Bg[a][mask] - Bo[a][mask]).max() <= 1e-12 * np.abs(Bo[a]).max()
+
+
+def test_ctu_full_size_one_step_128_f64():
+    # the configuration of the 128^3 precision-form benchmark (CTU+PPM+HLLD)
+    p = inputs.abc_problem(128, 0.1, seed=0)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx, scheme=oracle.CTU, recon=oracle.PPM, riemann=oracle.HLLD)
+    s = Solver("ctu", "ppm", "hlld")
+    lv = level_from(U, B, dx)
+    dtd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.advance(lv, dt_dev=dtd)
+    assert abs(dtd.item() - dt) <= 1e-13 * dt
+    Ug, Bg = fetch(lv)
+    assert rel_err(Ug, Uo) <= 1e-12
+    assert rel_err(Bg, Bo) <= 1e-12
