@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MHD_ABI_VERSION 1
+#define MHD_ABI_VERSION 2
 
 /* status codes */
 #define MHD_OK 0
@@ -68,8 +68,8 @@ typedef struct {
   double gamma;      /* adiabatic index, 5/3 in the paper (Sec. 4) */
   double courant;    /* Courant factor, 1/2 in the paper (Sec. 4), summed over directions */
   double beta_fp64;  /* MHD_F32_MIXED: cells with 2p/|B|^2 below this recover p in double */
-  double mlp_dp;     /* MHD_MLP: relative pressure jump above which HLLD is used */
-  double mlp_drho;   /* MHD_MLP: relative density jump above which HLLD is used */
+  double mlp_dp;     /* MHD_MLP: relative pressure jump above which HLLD is used (negative: every face) */
+  double mlp_drho;   /* MHD_MLP: relative density jump above which HLLD is used (negative: every face) */
 } mhd_config;
 
 /* One level: a dense periodic grid plus an optional list of patch groups.
@@ -88,6 +88,10 @@ typedef struct {
   void* U;              /* device, 5 * N elements, see layout above */
   void* B;              /* device, 3 * N elements */
   double* E64;          /* device, N doubles, MHD_F32_MIXED only */
+  const int* n_groups_dev; /* optional device int: the number of listed groups
+                              actually used (<= n_groups, which is then the
+                              capacity); lets a captured graph replay after
+                              the list changed */
 } mhd_level;
 
 /* Ghost width a staged patch group needs for one full step of the given
@@ -127,6 +131,39 @@ int mhd_step_devdt(mhd_ctx ctx, const mhd_level* lv, const double* dt_dev);
  * may be NULL) and adds it to t_dev (device, may be NULL). */
 int mhd_advance(mhd_ctx ctx, const mhd_level* lv, double* dt_dev, double* t_dev);
 
+/* mhd_advance through a HIP graph: the first call for a level description
+ * (and the same dt_dev/t_dev) captures the step's kernels on the context's
+ * stream and instantiates the graph; later calls replay it.  dt comes from
+ * the on-device CFL reduction and a group count from n_groups_dev, so a
+ * replay needs no host work.  A different description re-captures. */
+int mhd_advance_graph(mhd_ctx ctx, const mhd_level* lv, double* dt_dev, double* t_dev);
+
+/* Launch shape of the stage kernels: at most blocks_per_cu 256-thread blocks
+ * per compute unit walk the work with a grid-wide stride (0 = one thread per
+ * work item, no cap).  Drops any captured graph.  The reduction kernels of
+ * mhd_divB and mhd_sums keep their fixed shape (bitwise-stable results). */
+int mhd_set_launch(mhd_ctx ctx, int blocks_per_cu);
+
+/* Minimum of the level's CFL time step and *dt_dev, written to *dt_dev (a
+ * shared step for several levels, without a host sync). */
+int mhd_cfl_dt_min(mhd_ctx ctx, const mhd_level* lv, double* dt_dev);
+
+/* AMR support between a coarse level and a fine level of twice its cells per
+ * dimension (paper Sec. 3.3).  The coarse level is read (prolong) or written
+ * (restrict) as a whole grid; its own group list, if any, is ignored.
+ * mhd_prolong: with no fine group list, fills the whole fine level from the
+ * coarse one; with a list, fills the ghost halo (halo cells around each listed
+ * group, plus one above) of the listed groups: cells outside every listed
+ * group, and faces whose two cells are both outside.  Density and momentum are
+ * injected (the children average to the parent), the energy is rebuilt from
+ * the parent's pressure with the child's field; a fine face on a coarse face
+ * takes its value, a fine face inside a coarse cell the mean of the two coarse
+ * faces bracketing it, so each fine cell's divergence equals its parent's.
+ * mhd_restrict: coarse cells under the listed fine groups (all cells with no
+ * list) take the mean of their eight children.  Not for MHD_F32_MIXED. */
+int mhd_prolong(mhd_ctx ctx, const mhd_level* coarse, const mhd_level* fine, int halo);
+int mhd_restrict(mhd_ctx ctx, const mhd_level* fine, const mhd_level* coarse);
+
 /* Discrete divergence of Eq. 16 in double: max |div B| and the mean of
  * |div B| over the level's cells.  Synchronises. */
 int mhd_divB(mhd_ctx ctx, const mhd_level* lv, double* max_abs, double* l1);
@@ -148,6 +185,50 @@ int mhd_profile_step(mhd_ctx ctx, const mhd_level* lv, int nrep, double* stage_m
 int mhd_num_stages(mhd_ctx ctx);
 /* Name of stage s (static string), or NULL when out of range. */
 const char* mhd_stage_name(mhd_ctx ctx, int stage);
+
+/* ---- learned interface flux (an addition to the paper's method) ----
+ * A 15 -> 64 -> 64 -> 7 GELU network replaces HLLD (paper Sec. 3.2, CTU
+ * step 2 names HLLD) at interfaces whose relative pressure and density jumps
+ * are below cfg.mlp_dp / cfg.mlp_drho; stronger jumps keep HLLD.  Inputs (15)
+ * come from the face-frame primitive states w = (rho, vn, vt1, vt2, p, Bt1,
+ * Bt2) on both sides and Bn, in units sc = (rho0, v0, v0, v0, p0, B0, B0) with
+ * rho0 = mean rho, p0 = mean p, v0 = sqrt(p0/rho0), B0 = sqrt(p0): with
+ * d = (wR - wL)/sc and s = |d|, x = (mean rho/rho0, mean (vn, vt1, vt2)/v0,
+ * s, mean (Bt1, Bt2)/B0, d/s, Bn/B0).  Outputs: the dissipative part of the
+ * flux, i.e. the flux minus the central flux (F(wl) + F(wr))/2 computed
+ * exactly (Eq. 7), divided by s (rho0 v0, p0, p0, p0, p0 v0, B0 v0, B0 v0).
+ * BF16 operands, FP32 accumulation (MFMA).  Parameters: FP32 device
+ * array of mhd_mlp_num_params() values, packed W1[15][64] b1[64] W2[64][64]
+ * b2[64] W3[64][7] b3[7] ([in][out], row-major).  Usable with MHD_CTU in
+ * MHD_F32 or MHD_F32_MIXED; mhd_fallback_count() then counts HLLD faces. */
+int mhd_mlp_num_params(void);
+/* Load inference weights (device params) into the context; required before a
+ * step with MHD_MLP. */
+int mhd_mlp_set_weights(mhd_ctx ctx, const float* params_dev);
+/* Y[n][7] = network(X[n][15]) for normalised features (device arrays). */
+int mhd_mlp_forward(mhd_ctx ctx, const float* params_dev, const float* X_dev, int n, float* Y_dev);
+/* Gradient of sum(dY * network(X)) with respect to the parameters. */
+int mhd_mlp_backward(mhd_ctx ctx, const float* params_dev, const float* X_dev, const float* dY_dev, int n,
+                     float* grads_dev);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, bias-corrected at step >= 1) on
+ * the mean squared error over the batch; params, adam_m, adam_v, grads are
+ * device arrays of mhd_mlp_num_params() floats, loss_dev (may be NULL)
+ * receives the batch loss before the update. */
+int mhd_mlp_train_step(mhd_ctx ctx, float* params_dev, float* adam_m, float* adam_v, float* grads_dev, int step,
+                       const float* X_dev, const float* T_dev, int n, float lr, float* loss_dev);
+/* Captured samples S[n][22] = (wl[7], wr[7], bn, flux[7]) -> features
+ * X[n][15], normalised targets T[n][7] = (flux - central flux) / (s scales)
+ * and flags: bit 0 = strong jump (HLLD at run time), bit 1 = jump size s below
+ * 1e-4, where the target is dominated by float round-off. */
+int mhd_mlp_prepare(mhd_ctx ctx, const float* samples_dev, int n, float* X_dev, float* T_dev, int* flags_dev);
+/* Learned flux with HLLD fallback for n interfaces S[n][15] = (wl[7], wr[7],
+ * bn) in the face frame -> flux[n][7]; used_hlld[n] = 1 where HLLD was used. */
+int mhd_mlp_face_flux(mhd_ctx ctx, const float* states_dev, int n, float* flux_dev, int* used_hlld_dev);
+/* Interface capture for training data: while set, every stride-th face of the
+ * CTU Riemann stages writes (wl, wr, bn, flux) to buf_dev[cap][22] (FP32
+ * forms only); *count_dev counts attempted writes (writes stop at cap).
+ * buf_dev == NULL turns capture off. */
+int mhd_set_capture(mhd_ctx ctx, float* buf_dev, long long cap, unsigned long long* count_dev, int stride);
 
 /* Wait for the context's stream and report sticky device-side errors
  * (MHD_ERR_NONPHYSICAL). */

@@ -14,9 +14,11 @@
 // the later stages read (3 ghost cells per side for U^n).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "../../include/mhd.h"
 #include "mhd_kernels.hpp"
@@ -45,6 +47,18 @@ struct mhd_ctx_s {
   double* host;           // pinned host scratch (16 doubles)
   int* occ;               // group occupancy map
   long long cap_occ;
+  MlpWeights* mlpw;       // inference weights of the learned flux
+  bool mlp_ready;
+  Capture capture;        // interface capture (buf == nullptr: off)
+  float* mlp_ws;          // training workspace
+  long long cap_mlp;      // batch capacity of mlp_ws
+  int num_cu;             // compute units of the device
+  long long max_blocks;   // cap on stage-kernel grids (0: none)
+  hipGraph_t graph;       // captured mhd_advance
+  hipGraphExec_t graph_exec;
+  mhd_level graph_key;
+  double* graph_dt;
+  double* graph_t;
 };
 
 namespace {
@@ -61,8 +75,10 @@ int check_config(const mhd_config* c) {
   if (!(c->courant > 0.0 && c->courant <= 1.0)) return MHD_ERR_INVALID_ARG;
   // implemented combinations: VL with PLM; CTU with PLM or PPM
   if (c->scheme == MHD_VL && c->recon != MHD_PLM) return MHD_ERR_UNSUPPORTED;
-  if (c->riemann == MHD_MLP) return MHD_ERR_UNSUPPORTED;
-  if (c->prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
+  // the learned flux runs in FP32 inside the CTU Riemann stages
+  if (c->riemann == MHD_MLP && (c->scheme != MHD_CTU || c->prec == MHD_F64)) return MHD_ERR_UNSUPPORTED;
+  if (c->riemann == MHD_MLP && !(std::isfinite(c->mlp_dp) && std::isfinite(c->mlp_drho))) return MHD_ERR_INVALID_ARG;
+  if (c->prec == MHD_F32_MIXED && !(c->beta_fp64 >= 0.0)) return MHD_ERR_INVALID_ARG;
   return MHD_OK;
 }
 
@@ -150,6 +166,8 @@ Work make_work(const mhd_level* lv, int lo, int hi) {
     w.gnx = w.gny = w.gnz = 0;
   }
   w.occ = nullptr;
+  w.n_dev = (lv->groups && lv->n_groups > 0) ? lv->n_groups_dev : nullptr;
+  w.oshift = 0;
   return w;
 }
 
@@ -166,11 +184,22 @@ int build_occupancy(mhd_ctx_s* c, const mhd_level* lv) {
   }
   k_occ_clear<<<(unsigned)((ng + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(c->occ, ng);
   k_occ_set<<<(unsigned)((lv->n_groups + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-      c->occ, lv->groups, lv->n_groups, lv->group_edge, lv->nx / lv->group_edge, lv->ny / lv->group_edge);
+      c->occ, lv->groups, lv->n_groups, lv->n_groups_dev, lv->group_edge, lv->nx / lv->group_edge,
+      lv->ny / lv->group_edge);
   return MHD_OK;
 }
 
+// grid of a reduction kernel: one thread per item (fixed, so results are
+// bitwise stable)
 unsigned nblocks(const Work& w) { return (unsigned)((w.items + kBlock - 1) / kBlock); }
+
+// grid of a stage kernel: capped by the context's launch shape
+thread_local long long g_max_blocks = 0;
+unsigned sblocks(const Work& w) {
+  long long b = (w.items + kBlock - 1) / kBlock;
+  if (g_max_blocks > 0 && b > g_max_blocks) b = g_max_blocks;
+  return (unsigned)b;
+}
 
 // Stage names in launch order (used by mhd_profile_step).
 const char* const kStageNamesVL[] = {"prim", "flux_predict", "emf_predict", "half_step",
@@ -184,8 +213,9 @@ const char* stage_name(const mhd_ctx_s* c, int s) {
 }
 
 // ev (optional): kNumStages + 1 events recorded around the stage kernels
-template <typename T, int S>
+template <typename T, int S, bool MIX>
 void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev = nullptr) {
+  const Mix mix{MIX ? lv->E64 : nullptr, c->cfg.beta_fp64};
   hipStream_t st = c->stream;
   T* U = (T*)lv->U;
   T* B = (T*)lv->B;
@@ -205,22 +235,22 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
   mark(0);
   if (cfl) {
     k_reset_smax<<<1, 1, 0, st>>>(c->smax);
-    k_prim<T, true><<<nblocks(wp), kBlock, 0, st>>>(wp, U, B, W, gam, c->smax, c->flag);
+    k_prim<T, true, MIX><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   } else {
-    k_prim<T, false><<<nblocks(wp), kBlock, 0, st>>>(wp, U, B, W, gam, c->smax, c->flag);
+    k_prim<T, false, MIX><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   }
   mark(1);
-  k_flux<T, 0, S><<<nblocks(wf1), kBlock, 0, st>>>(wf1, W, B, F, gam, c->nfb);
+  k_flux<T, 0, S><<<sblocks(wf1), kBlock, 0, st>>>(wf1, W, B, F, gam, c->nfb);
   mark(2);
-  k_emf<T><<<nblocks(we1), kBlock, 0, st>>>(we1, F, W, E);
+  k_emf<T><<<sblocks(we1), kBlock, 0, st>>>(we1, F, W, E);
   mark(3);
-  k_half<T><<<nblocks(wh), kBlock, 0, st>>>(wh, U, B, F, E, dts, inv_dx, gam, W, Bh);
+  k_half<T, MIX><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F, E, dts, inv_dx, gam, W, Bh);
   mark(4);
-  k_flux<T, 1, S><<<nblocks(wf2), kBlock, 0, st>>>(wf2, W, Bh, F, gam, c->nfb);
+  k_flux<T, 1, S><<<sblocks(wf2), kBlock, 0, st>>>(wf2, W, Bh, F, gam, c->nfb);
   mark(5);
-  k_emf<T><<<nblocks(we2), kBlock, 0, st>>>(we2, F, W, E);
+  k_emf<T><<<sblocks(we2), kBlock, 0, st>>>(we2, F, W, E);
   mark(6);
-  k_final<T><<<nblocks(wu), kBlock, 0, st>>>(wu, U, B, F, E, dts, inv_dx);
+  k_final<T, MIX><<<sblocks(wu), kBlock, 0, st>>>(wu, U, B, mix, F, E, dts, inv_dx);
   mark(7);
 }
 
@@ -235,8 +265,9 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
 //   k_final        U^n, B^n, F2, E      -> U^{n+1}, B^{n+1}   step 8
 // Group halos (cells below, above each group): 4,4 / 2,2 / 2,2 / 1,2 / 1,1 /
 // 1,1 / 0,1 / 0,0, i.e. 4 ghost cells of U^n.
-template <typename T, int S, int R>
+template <typename T, int S, int R, bool MIX>
 void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
+  const Mix mix{MIX ? lv->E64 : nullptr, c->cfg.beta_fp64};
   hipStream_t st = c->stream;
   T* U = (T*)lv->U;
   T* B = (T*)lv->B;
@@ -260,52 +291,72 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
   mark(0);
   if (cfl) {
     k_reset_smax<<<1, 1, 0, st>>>(c->smax);
-    k_prim<T, true><<<nblocks(wp), kBlock, 0, st>>>(wp, U, B, W, gam, c->smax, c->flag);
+    k_prim<T, true, MIX><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   } else {
-    k_prim<T, false><<<nblocks(wp), kBlock, 0, st>>>(wp, U, B, W, gam, c->smax, c->flag);
+    k_prim<T, false, MIX><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   }
   mark(1);
-  k_ctu_states<T, R><<<nblocks(wq), kBlock, 0, st>>>(wq, W, B, QL, QR, dts, inv_dx, gam);
+  k_ctu_states<T, R><<<sblocks(wq), kBlock, 0, st>>>(wq, W, B, QL, QR, dts, inv_dx, gam);
   mark(2);
-  k_flux_q<T, S><<<nblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->nfb);
+  constexpr bool kMlp = S == 3 && std::is_same<T, float>::value;
+  const float dp = (float)c->cfg.mlp_dp, drho = (float)c->cfg.mlp_drho;
+  if constexpr (kMlp)
+    k_flux_q_mlp<<<sblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb);
+  else
+    k_flux_q<T, S><<<sblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->nfb, c->capture);
   mark(3);
-  k_emf<T><<<nblocks(we1), kBlock, 0, st>>>(we1, F1, W, E);
+  k_emf<T><<<sblocks(we1), kBlock, 0, st>>>(we1, F1, W, E);
   mark(4);
-  k_half<T><<<nblocks(wh), kBlock, 0, st>>>(wh, U, B, F1, E, dts, inv_dx, gam, W, Bh);
+  k_half<T, MIX><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F1, E, dts, inv_dx, gam, W, Bh);
   mark(5);
-  k_ctu_correct<T, S><<<nblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->nfb);
+  if constexpr (kMlp)
+    k_ctu_correct_mlp<<<sblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->mlpw, dp,
+                                                       drho, c->nfb);
+  else
+    k_ctu_correct<T, S><<<sblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->nfb,
+                                                         c->capture);
   mark(6);
-  k_emf<T><<<nblocks(we2), kBlock, 0, st>>>(we2, F2, W, E);
+  k_emf<T><<<sblocks(we2), kBlock, 0, st>>>(we2, F2, W, E);
   mark(7);
-  k_final<T><<<nblocks(wu), kBlock, 0, st>>>(wu, U, B, F2, E, dts, inv_dx);
+  k_final<T, MIX><<<sblocks(wu), kBlock, 0, st>>>(wu, U, B, mix, F2, E, dts, inv_dx);
   mark(8);
 }
 
-template <typename T, int S>
+template <typename T, int S, bool MIX>
 void launch_scheme(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
-  if (c->cfg.scheme == MHD_VL) launch_step<T, S>(c, lv, dts, cfl, ev);
-  else if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1>(c, lv, dts, cfl, ev);
-  else launch_ctu<T, S, 0>(c, lv, dts, cfl, ev);
+  if constexpr (S == 3) {
+    // learned flux: CTU only (validated at mhd_init)
+    if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX>(c, lv, dts, cfl, ev);
+    else launch_ctu<T, S, 0, MIX>(c, lv, dts, cfl, ev);
+    return;
+  }
+  if (c->cfg.scheme == MHD_VL) launch_step<T, S, MIX>(c, lv, dts, cfl, ev);
+  else if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX>(c, lv, dts, cfl, ev);
+  else launch_ctu<T, S, 0, MIX>(c, lv, dts, cfl, ev);
 }
 
-template <typename T>
+template <typename T, bool MIX>
 void launch_step_t(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
   switch (c->cfg.riemann) {
-    case MHD_ROE: launch_scheme<T, 0>(c, lv, dts, cfl, ev); break;
-    case MHD_HLLE: launch_scheme<T, 1>(c, lv, dts, cfl, ev); break;
-    default: launch_scheme<T, 2>(c, lv, dts, cfl, ev); break;
+    case MHD_ROE: launch_scheme<T, 0, MIX>(c, lv, dts, cfl, ev); break;
+    case MHD_HLLE: launch_scheme<T, 1, MIX>(c, lv, dts, cfl, ev); break;
+    case MHD_HLLD: launch_scheme<T, 2, MIX>(c, lv, dts, cfl, ev); break;
+    default: launch_scheme<T, 3, MIX>(c, lv, dts, cfl, ev); break;
   }
 }
 
 int do_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev = nullptr) {
   int rc = check_level(c, lv);
   if (rc) return rc;
+  if (c->cfg.riemann == MHD_MLP && !c->mlp_ready) return MHD_ERR_INVALID_ARG;
   rc = ensure_capacity(c, (long long)lv->nx * lv->ny * lv->nz);
   if (rc) return rc;
   rc = build_occupancy(c, lv);
   if (rc) return rc;
-  if (c->cfg.prec == MHD_F64) launch_step_t<double>(c, lv, dts, cfl, ev);
-  else launch_step_t<float>(c, lv, dts, cfl, ev);
+  g_max_blocks = c->max_blocks;
+  if (c->cfg.prec == MHD_F64) launch_step_t<double, false>(c, lv, dts, cfl, ev);
+  else if (c->cfg.prec == MHD_F32) launch_step_t<float, false>(c, lv, dts, cfl, ev);
+  else launch_step_t<float, true>(c, lv, dts, cfl, ev);
   return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 
@@ -356,6 +407,12 @@ int mhd_init(const mhd_config* cfg, void* hip_stream, mhd_ctx* out) {
   c->stream = (hipStream_t)hip_stream;
   HIP_TRY(hipGetDevice(&c->device));
   c->elem = cfg->prec == MHD_F64 ? sizeof(double) : sizeof(float);
+  c->capture = Capture{nullptr, 0, nullptr, 1};
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (c->num_cu <= 0) c->num_cu = 256;
+  }
   if (hipMalloc(&c->dres, 8 * sizeof(double)) != hipSuccess || hipMalloc(&c->smax, sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->flag, sizeof(int)) != hipSuccess || hipMalloc(&c->nfb, sizeof(unsigned long long)) != hipSuccess ||
       hipHostMalloc(&c->host, 16 * sizeof(double)) != hipSuccess) {
@@ -376,7 +433,11 @@ int mhd_finalize(mhd_ctx c) {
   if (!c) return MHD_ERR_INVALID_ARG;
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
   free_scratch(c);
+  hipFree(c->mlpw);
+  hipFree(c->mlp_ws);
   hipFree(c->parts); hipFree(c->dres); hipFree(c->smax); hipFree(c->flag); hipFree(c->nfb); hipFree(c->occ);
   if (c->host) hipHostFree(c->host);
   delete c;
@@ -390,12 +451,16 @@ int mhd_prim_to_cons(mhd_ctx c, const mhd_level* lv, const void* W5) {
   int rc = check_level(c, lv);
   if (rc) return rc;
   const Work w = make_work(lv, 0, 0);
+  const Mix mix{lv->E64, c->cfg.beta_fp64};
   if (c->cfg.prec == MHD_F64)
-    k_prim_to_cons<double><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const double*)W5, (const double*)lv->B,
-                                                                  (double*)lv->U, c->cfg.gamma);
+    k_prim_to_cons<double, false><<<nblocks(w), kBlock, 0, c->stream>>>(
+        w, (const double*)W5, (const double*)lv->B, (double*)lv->U, mix, c->cfg.gamma);
+  else if (c->cfg.prec == MHD_F32)
+    k_prim_to_cons<float, false><<<nblocks(w), kBlock, 0, c->stream>>>(
+        w, (const float*)W5, (const float*)lv->B, (float*)lv->U, mix, (float)c->cfg.gamma);
   else
-    k_prim_to_cons<float><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const float*)W5, (const float*)lv->B,
-                                                                 (float*)lv->U, (float)c->cfg.gamma);
+    k_prim_to_cons<float, true><<<nblocks(w), kBlock, 0, c->stream>>>(
+        w, (const float*)W5, (const float*)lv->B, (float*)lv->U, mix, (float)c->cfg.gamma);
   return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 
@@ -405,12 +470,16 @@ int mhd_cfl_dt(mhd_ctx c, const mhd_level* lv, double* dt_host, double* dt_dev) 
   if (rc) return rc;
   const Work w = make_work(lv, 0, 0);
   k_reset_smax<<<1, 1, 0, c->stream>>>(c->smax);
+  const Mix mix{lv->E64, c->cfg.beta_fp64};
   if (c->cfg.prec == MHD_F64)
-    k_cfl<double><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const double*)lv->U, (const double*)lv->B,
-                                                         c->cfg.gamma, c->smax, c->flag);
+    k_cfl<double, false><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const double*)lv->U, (const double*)lv->B, mix,
+                                                                c->cfg.gamma, c->smax, c->flag);
+  else if (c->cfg.prec == MHD_F32)
+    k_cfl<float, false><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const float*)lv->U, (const float*)lv->B, mix,
+                                                               (float)c->cfg.gamma, c->smax, c->flag);
   else
-    k_cfl<float><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const float*)lv->U, (const float*)lv->B,
-                                                        (float)c->cfg.gamma, c->smax, c->flag);
+    k_cfl<float, true><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const float*)lv->U, (const float*)lv->B, mix,
+                                                              (float)c->cfg.gamma, c->smax, c->flag);
   const double cdx = c->cfg.courant * lv->dx;
   if (dt_dev) k_publish_dt<<<1, 1, 0, c->stream>>>(c->smax, cdx, dt_dev, nullptr);
   if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
@@ -487,6 +556,172 @@ int mhd_profile_step(mhd_ctx c, const mhd_level* lv, int nrep, double* stage_ms)
   return MHD_OK;
 }
 
+static void drop_graph(mhd_ctx_s* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
+int mhd_set_launch(mhd_ctx c, int blocks_per_cu) {
+  if (!c || blocks_per_cu < 0) return MHD_ERR_INVALID_ARG;
+  c->max_blocks = blocks_per_cu > 0 ? (long long)blocks_per_cu * c->num_cu : 0;
+  drop_graph(c);
+  return MHD_OK;
+}
+
+int mhd_advance_graph(mhd_ctx c, const mhd_level* lv, double* dt_dev, double* t_dev) {
+  if (!c || !lv) return MHD_ERR_INVALID_ARG;
+  if (!c->stream) return MHD_ERR_INVALID_ARG;   // capture needs a non-default stream
+  int rc = check_level(c, lv);
+  if (rc) return rc;
+  if (c->cfg.riemann == MHD_MLP && !c->mlp_ready) return MHD_ERR_INVALID_ARG;
+  const bool same = c->graph_exec && std::memcmp(&c->graph_key, lv, sizeof(mhd_level)) == 0 &&
+                    c->graph_dt == dt_dev && c->graph_t == t_dev;
+  if (!same) {
+    drop_graph(c);
+    // allocations happen before the capture
+    rc = ensure_capacity(c, (long long)lv->nx * lv->ny * lv->nz);
+    if (rc) return rc;
+    if (lv->groups && lv->n_groups > 0) {
+      const long long ng =
+          (long long)(lv->nx / lv->group_edge) * (lv->ny / lv->group_edge) * (lv->nz / lv->group_edge);
+      if (ng > c->cap_occ) {
+        hipFree(c->occ);
+        c->occ = nullptr;
+        c->cap_occ = 0;
+        if (hipMalloc(&c->occ, ng * sizeof(int)) != hipSuccess) return MHD_ERR_OUT_OF_MEMORY;
+        c->cap_occ = ng;
+      }
+    }
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return MHD_ERR_HIP;
+    DtSrc s{0.0, nullptr, c->smax, c->cfg.courant * lv->dx};
+    rc = do_step(c, lv, s, true);
+    if (rc == MHD_OK && (dt_dev || t_dev))
+      k_publish_dt<<<1, 1, 0, c->stream>>>(c->smax, c->cfg.courant * lv->dx, dt_dev, t_dev);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess || !g) return MHD_ERR_HIP;
+    c->graph = g;
+    if (hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      drop_graph(c);
+      return MHD_ERR_HIP;
+    }
+    c->graph_key = *lv;
+    c->graph_dt = dt_dev;
+    c->graph_t = t_dev;
+  }
+  return hipGraphLaunch(c->graph_exec, c->stream) == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_cfl_dt_min(mhd_ctx c, const mhd_level* lv, double* dt_dev) {
+  if (!c || !dt_dev) return MHD_ERR_INVALID_ARG;
+  int rc = check_level(c, lv);
+  if (rc) return rc;
+  const Work w = make_work(lv, 0, 0);
+  const Mix mix{lv->E64, c->cfg.beta_fp64};
+  k_reset_smax<<<1, 1, 0, c->stream>>>(c->smax);
+  if (c->cfg.prec == MHD_F64)
+    k_cfl<double, false><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const double*)lv->U, (const double*)lv->B, mix,
+                                                                c->cfg.gamma, c->smax, c->flag);
+  else if (c->cfg.prec == MHD_F32)
+    k_cfl<float, false><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const float*)lv->U, (const float*)lv->B, mix,
+                                                               (float)c->cfg.gamma, c->smax, c->flag);
+  else
+    k_cfl<float, true><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const float*)lv->U, (const float*)lv->B, mix,
+                                                              (float)c->cfg.gamma, c->smax, c->flag);
+  k_min_dt<<<1, 1, 0, c->stream>>>(c->smax, c->cfg.courant * lv->dx, dt_dev);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+}  // extern "C"
+
+namespace {
+int check_pair(mhd_ctx_s* c, const mhd_level* coarse, const mhd_level* fine) {
+  int rc = check_level(c, coarse);
+  if (rc) return rc;
+  rc = check_level(c, fine);
+  if (rc) return rc;
+  if (fine->nx != 2 * coarse->nx || fine->ny != 2 * coarse->ny || fine->nz != 2 * coarse->nz)
+    return MHD_ERR_INVALID_ARG;
+  return MHD_OK;
+}
+
+// the coarse side of a transfer is addressed as a whole grid, whatever its list
+mhd_level whole_grid(const mhd_level* lv) {
+  mhd_level w = *lv;
+  w.n_groups = 0;
+  w.groups = nullptr;
+  w.n_groups_dev = nullptr;
+  return w;
+}
+
+template <typename T>
+void launch_prolong(mhd_ctx_s* c, const mhd_level* coarse, const mhd_level* fine, int halo) {
+  const mhd_level cw = whole_grid(coarse);
+  const Work wc = make_work(&cw, 0, 0);
+  if (fine->groups && fine->n_groups > 0) {
+    Work wf = make_work(fine, halo, halo + 1);
+    wf.occ = c->occ;
+    k_prolong_ghosts<T><<<sblocks(wf), kBlock, 0, c->stream>>>(wc, wf, (const T*)coarse->U, (const T*)coarse->B,
+                                                               (T*)fine->U, (T*)fine->B, (T)c->cfg.gamma);
+  } else {
+    const Work wf = make_work(fine, 0, 0);
+    k_prolong_all<T><<<sblocks(wf), kBlock, 0, c->stream>>>(wc, wf, (const T*)coarse->U, (const T*)coarse->B,
+                                                            (T*)fine->U, (T*)fine->B, (T)c->cfg.gamma);
+  }
+}
+
+template <typename T>
+void launch_restrict(mhd_ctx_s* c, const mhd_level* fine, const mhd_level* coarse) {
+  const Work wf = make_work(fine, 0, 0);
+  const mhd_level cw = whole_grid(coarse);
+  Work wc = make_work(&cw, 0, 0);
+  if (fine->groups && fine->n_groups > 0) {
+    // coarse footprint of each fine group: the fine origins halved, edge/2
+    wc.groups = fine->groups;
+    wc.edge = fine->group_edge / 2;
+    wc.halo = 0;
+    wc.box = fine->group_edge / 2;
+    wc.items = (long long)fine->n_groups * wc.box * wc.box * wc.box;
+    wc.n_dev = fine->n_groups_dev;
+    wc.gnx = wc.gny = wc.gnz = 0;
+    wc.oshift = 1;
+  }
+  k_restrict<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, (const T*)fine->U, (T*)coarse->U);
+}
+}  // namespace
+
+extern "C" {
+
+int mhd_prolong(mhd_ctx c, const mhd_level* coarse, const mhd_level* fine, int halo) {
+  if (!c || !coarse || !fine || halo < 0 || halo > 8) return MHD_ERR_INVALID_ARG;
+  int rc = check_pair(c, coarse, fine);
+  if (rc) return rc;
+  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
+  rc = build_occupancy(c, fine);
+  if (rc) return rc;
+  g_max_blocks = c->max_blocks;
+  if (c->cfg.prec == MHD_F64) launch_prolong<double>(c, coarse, fine, halo);
+  else launch_prolong<float>(c, coarse, fine, halo);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_restrict(mhd_ctx c, const mhd_level* fine, const mhd_level* coarse) {
+  if (!c || !coarse || !fine) return MHD_ERR_INVALID_ARG;
+  int rc = check_pair(c, coarse, fine);
+  if (rc) return rc;
+  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
+  g_max_blocks = c->max_blocks;
+  if (c->cfg.prec == MHD_F64) launch_restrict<double>(c, fine, coarse);
+  else launch_restrict<float>(c, fine, coarse);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
 int mhd_divB(mhd_ctx c, const mhd_level* lv, double* max_abs, double* l1) {
   if (!c) return MHD_ERR_INVALID_ARG;
   int rc = check_level(c, lv);
@@ -516,10 +751,11 @@ int mhd_sums(mhd_ctx c, const mhd_level* lv, double out[7]) {
   const unsigned nb = nblocks(w);
   rc = ensure_parts(c, 7LL * nb);
   if (rc) return rc;
+  const double* e64 = c->cfg.prec == MHD_F32_MIXED ? lv->E64 : nullptr;
   if (c->cfg.prec == MHD_F64)
-    k_sums<double><<<nb, kBlock, 0, c->stream>>>(w, (const double*)lv->U, (const double*)lv->B, c->parts);
+    k_sums<double><<<nb, kBlock, 0, c->stream>>>(w, (const double*)lv->U, (const double*)lv->B, nullptr, c->parts);
   else
-    k_sums<float><<<nb, kBlock, 0, c->stream>>>(w, (const float*)lv->U, (const float*)lv->B, c->parts);
+    k_sums<float><<<nb, kBlock, 0, c->stream>>>(w, (const float*)lv->U, (const float*)lv->B, e64, c->parts);
   k_finish<<<1, kBlock, 0, c->stream>>>(c->parts, (int)nb, 7, 7, c->dres);
   if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
   HIP_TRY(hipMemcpyAsync(c->host, c->dres, 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -537,6 +773,175 @@ int mhd_fallback_count(mhd_ctx c, long long* count) {
   std::memcpy(&v, c->host, sizeof v);
   *count = (long long)v;
   HIP_TRY(hipMemsetAsync(c->nfb, 0, sizeof(unsigned long long), c->stream));
+  return MHD_OK;
+}
+
+// ------------------------------------------------------------ learned flux
+int mhd_mlp_set_weights(mhd_ctx c, const float* params_dev) {
+  if (!c || !params_dev) return MHD_ERR_INVALID_ARG;
+  if (!c->mlpw && hipMalloc(&c->mlpw, sizeof(MlpWeights)) != hipSuccess) return MHD_ERR_OUT_OF_MEMORY;
+  k_mlp_pack<<<16, 256, 0, c->stream>>>(params_dev, c->mlpw);
+  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  c->mlp_ready = true;
+  return MHD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// training workspace: Z1, H1, Z2, H2, dZ2, dZ1 (n x 64 each), Y, dY (n x 7),
+// loss partials
+int ensure_mlp_ws(mhd_ctx_s* c, long long n) {
+  if (n <= c->cap_mlp) return MHD_OK;
+  hipFree(c->mlp_ws);
+  c->mlp_ws = nullptr;
+  c->cap_mlp = 0;
+  const long long words = 6 * 64 * n + 2 * 7 * n + (7 * n + 255) / 256 + 16;
+  if (hipMalloc(&c->mlp_ws, words * sizeof(float)) != hipSuccess) return MHD_ERR_OUT_OF_MEMORY;
+  c->cap_mlp = n;
+  return MHD_OK;
+}
+
+struct MlpBufs {
+  float *Z1, *H1, *Z2, *H2, *dZ2, *dZ1, *Y, *dY, *part;
+};
+
+MlpBufs mlp_bufs(mhd_ctx_s* c) {
+  const long long n = c->cap_mlp;
+  float* b = c->mlp_ws;
+  MlpBufs m;
+  m.Z1 = b; m.H1 = b + 64 * n; m.Z2 = b + 128 * n; m.H2 = b + 192 * n; m.dZ2 = b + 256 * n; m.dZ1 = b + 320 * n;
+  m.Y = b + 384 * n; m.dY = b + 391 * n; m.part = b + 398 * n;
+  return m;
+}
+
+template <int EPI>
+void gemm(hipStream_t st, int M, int N, int K, const float* A, long long sam, long long sak, const float* Bm,
+          long long sbk, long long sbn, const float* bias, const float* Zin, float* C, float* H, int ldc) {
+  const long long waves = (long long)((M + 15) / 16) * ((N + 15) / 16);
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  k_mlp_gemm<EPI><<<blocks, 256, 0, st>>>(M, N, K, A, sam, sak, Bm, sbk, sbn, bias, Zin, C, H, ldc);
+}
+
+void mlp_forward(mhd_ctx_s* c, const float* P, const float* X, int n, const MlpBufs& b, float* Y) {
+  hipStream_t st = c->stream;
+  gemm<EPI_BIAS_GELU>(st, n, kNh, kNin, X, kNin, 1, P + oW1, kNh, 1, P + ob1, nullptr, b.Z1, b.H1, kNh);
+  gemm<EPI_BIAS_GELU>(st, n, kNh, kNh, b.H1, kNh, 1, P + oW2, kNh, 1, P + ob2, nullptr, b.Z2, b.H2, kNh);
+  gemm<EPI_BIAS>(st, n, kNout, kNh, b.H2, kNh, 1, P + oW3, kNout, 1, P + ob3, nullptr, Y, nullptr, kNout);
+}
+
+void mlp_backward(mhd_ctx_s* c, const float* P, const float* X, const float* dY, int n, const MlpBufs& b, float* G) {
+  hipStream_t st = c->stream;
+  gemm<EPI_STORE>(st, kNh, kNout, n, b.H2, 1, kNh, dY, kNout, 1, nullptr, nullptr, G + oW3, nullptr, kNout);
+  k_mlp_colsum<<<kNout, 256, 0, st>>>(n, kNout, dY, G + ob3);
+  gemm<EPI_GELU_PRIME>(st, n, kNh, kNout, dY, kNout, 1, P + oW3, 1, kNout, nullptr, b.Z2, b.dZ2, nullptr, kNh);
+  k_mlp_colsum<<<kNh, 256, 0, st>>>(n, kNh, b.dZ2, G + ob2);
+  gemm<EPI_STORE>(st, kNh, kNh, n, b.H1, 1, kNh, b.dZ2, kNh, 1, nullptr, nullptr, G + oW2, nullptr, kNh);
+  gemm<EPI_GELU_PRIME>(st, n, kNh, kNh, b.dZ2, kNh, 1, P + oW2, 1, kNh, nullptr, b.Z1, b.dZ1, nullptr, kNh);
+  k_mlp_colsum<<<kNh, 256, 0, st>>>(n, kNh, b.dZ1, G + ob1);
+  gemm<EPI_STORE>(st, kNin, kNh, n, X, 1, kNin, b.dZ1, kNh, 1, nullptr, nullptr, G + oW1, nullptr, kNh);
+}
+}  // namespace
+
+extern "C" {
+
+int mhd_mlp_num_params(void) { return kParams; }
+
+int mhd_mlp_forward(mhd_ctx c, const float* params_dev, const float* X_dev, int n, float* Y_dev) {
+  if (!c || !params_dev || !X_dev || !Y_dev || n <= 0) return MHD_ERR_INVALID_ARG;
+  int rc = ensure_mlp_ws(c, n);
+  if (rc) return rc;
+  mlp_forward(c, params_dev, X_dev, n, mlp_bufs(c), Y_dev);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_mlp_backward(mhd_ctx c, const float* params_dev, const float* X_dev, const float* dY_dev, int n,
+                     float* grads_dev) {
+  if (!c || !params_dev || !X_dev || !dY_dev || !grads_dev || n <= 0) return MHD_ERR_INVALID_ARG;
+  int rc = ensure_mlp_ws(c, n);
+  if (rc) return rc;
+  const MlpBufs b = mlp_bufs(c);
+  mlp_forward(c, params_dev, X_dev, n, b, b.Y);
+  mlp_backward(c, params_dev, X_dev, dY_dev, n, b, grads_dev);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_mlp_train_step(mhd_ctx c, float* params_dev, float* adam_m, float* adam_v, float* grads_dev, int step,
+                       const float* X_dev, const float* T_dev, int n, float lr, float* loss_dev) {
+  if (!c || !params_dev || !adam_m || !adam_v || !grads_dev || !X_dev || !T_dev || n <= 0 || step < 1 ||
+      !(lr > 0.f))
+    return MHD_ERR_INVALID_ARG;
+  int rc = ensure_mlp_ws(c, n);
+  if (rc) return rc;
+  hipStream_t st = c->stream;
+  const MlpBufs b = mlp_bufs(c);
+  mlp_forward(c, params_dev, X_dev, n, b, b.Y);
+  const long long total = 7LL * n;
+  const unsigned nb = (unsigned)((total + 255) / 256);
+  k_mlp_mse<<<nb, 256, 0, st>>>(total, b.Y, T_dev, b.dY, b.part);
+  if (loss_dev) k_mlp_loss<<<1, 64, 0, st>>>(b.part, (int)nb, total, loss_dev);
+  mlp_backward(c, params_dev, X_dev, b.dY, n, b, grads_dev);
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  k_mlp_adam<<<(kParams + 255) / 256, 256, 0, st>>>(params_dev, adam_m, adam_v, grads_dev, kParams, lr, b1, b2, 1e-8f,
+                                                    c1, c2);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_mlp_prepare(mhd_ctx c, const float* samples_dev, int n, float* X_dev, float* T_dev, int* flags_dev) {
+  if (!c || !samples_dev || !X_dev || !T_dev || !flags_dev || n <= 0) return MHD_ERR_INVALID_ARG;
+  k_mlp_prepare<<<(n + 255) / 256, 256, 0, c->stream>>>(samples_dev, n, (float)c->cfg.gamma, (float)c->cfg.mlp_dp,
+                                                        (float)c->cfg.mlp_drho, X_dev, T_dev, flags_dev);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+}  // extern "C"
+
+namespace {
+__global__ void __launch_bounds__(kBlock) k_mlp_faces(const float* __restrict__ S, int n, const MlpWeights* mw,
+                                                      float gam, float dp, float drho, float* __restrict__ F,
+                                                      int* __restrict__ used_hlld) {
+  __shared__ MlpShared sh;
+  mlp_load_weights(sh, mw);
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool active = i < n;
+  float wl[7], wr[7], f[7];
+  float bn = 1.0f;
+#pragma unroll
+  for (int m = 0; m < 7; ++m) {
+    wl[m] = active ? S[(long long)i * 15 + m] : 1.0f;
+    wr[m] = active ? S[(long long)i * 15 + 7 + m] : 1.0f;
+  }
+  if (active) bn = S[(long long)i * 15 + 14];
+  const int h = mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) F[(long long)i * 7 + m] = f[m];
+    used_hlld[i] = h;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int mhd_mlp_face_flux(mhd_ctx c, const float* states_dev, int n, float* flux_dev, int* used_hlld_dev) {
+  if (!c || !states_dev || !flux_dev || !used_hlld_dev || n <= 0) return MHD_ERR_INVALID_ARG;
+  if (!c->mlp_ready) return MHD_ERR_INVALID_ARG;
+  k_mlp_faces<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(states_dev, n, c->mlpw, (float)c->cfg.gamma,
+                                                                     (float)c->cfg.mlp_dp, (float)c->cfg.mlp_drho,
+                                                                     flux_dev, used_hlld_dev);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_set_capture(mhd_ctx c, float* buf_dev, long long cap, unsigned long long* count_dev, int stride) {
+  if (!c) return MHD_ERR_INVALID_ARG;
+  if (!buf_dev) {
+    c->capture = Capture{nullptr, 0, nullptr, 1};
+    return MHD_OK;
+  }
+  if (cap <= 0 || !count_dev || stride <= 0) return MHD_ERR_INVALID_ARG;
+  if (c->cfg.prec == MHD_F64) return MHD_ERR_UNSUPPORTED;
+  c->capture = Capture{buf_dev, cap, count_dev, stride};
   return MHD_OK;
 }
 

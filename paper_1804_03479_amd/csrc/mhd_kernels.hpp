@@ -24,6 +24,7 @@
 #include <stdint.h>
 
 #include "mhd_device.hpp"
+#include "mhd_mlp.hpp"
 
 namespace mhd {
 
@@ -36,9 +37,11 @@ struct Work {
   int edge;             // group edge in cells
   int halo;             // extra cells around each group
   int box;              // edge + 2 * halo
-  long long items;      // threads with work
+  long long items;      // work items (cells), upper bound when n_dev is set
   const int* occ;       // group occupancy map (list mode), gnx*gny*gnz
   int gnx, gny, gnz;    // groups per dimension
+  const int* n_dev;     // list mode: number of groups read from device memory, or nullptr
+  int oshift;           // list mode: group origins are divided by 2^oshift (coarse footprint)
 };
 
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -61,11 +64,22 @@ __device__ __forceinline__ long long block_linear_id() {
   return (long long)r * kBlock + threadIdx.x;
 }
 
-// cell owned by this thread; false if the thread has no work.  (a, b, c)
-// is the position inside the unit's box (the cell itself for a whole grid).
-__device__ __forceinline__ bool my_cell(const Work& w, int& i, int& j, int& k, int& a, int& b, int& c) {
-  const long long t = block_linear_id();
-  if (t >= w.items) return false;
+// Persistent launches: a grid of at most a tuned number of blocks walks the
+// work items with a grid-wide stride; the item count of a group list may be
+// read from device memory, so a captured graph replays over a changed list.
+__device__ __forceinline__ long long work_items(const Work& w) {
+  if (w.n_dev) {
+    const long long n = *w.n_dev;
+    const long long m = (long long)w.box * w.box * w.box * n;
+    return m < w.items ? m : w.items;
+  }
+  return w.items;
+}
+__device__ __forceinline__ long long item_stride() { return (long long)gridDim.x * kBlock; }
+
+// cell of work item t.  (a, b, c) is the position inside the unit's box (the
+// cell itself for a whole grid).
+__device__ __forceinline__ void cell_of(const Work& w, long long t, int& i, int& j, int& k, int& a, int& b, int& c) {
   if (w.groups == nullptr) {
     i = (int)(t % w.nx);
     const long long r = t / w.nx;
@@ -79,17 +93,20 @@ __device__ __forceinline__ bool my_cell(const Work& w, int& i, int& j, int& k, i
     a = l % w.box;
     b = (l / w.box) % w.box;
     c = l / (w.box * w.box);
-    i = wrapc(w.groups[3 * g + 0] - w.halo + a, w.nx);
-    j = wrapc(w.groups[3 * g + 1] - w.halo + b, w.ny);
-    k = wrapc(w.groups[3 * g + 2] - w.halo + c, w.nz);
+    i = wrapc((w.groups[3 * g + 0] >> w.oshift) - w.halo + a, w.nx);
+    j = wrapc((w.groups[3 * g + 1] >> w.oshift) - w.halo + b, w.ny);
+    k = wrapc((w.groups[3 * g + 2] >> w.oshift) - w.halo + c, w.nz);
   }
-  return true;
 }
 
-__device__ __forceinline__ bool my_cell(const Work& w, int& i, int& j, int& k) {
+__device__ __forceinline__ void cell_of(const Work& w, long long t, int& i, int& j, int& k) {
   int a, b, c;
-  return my_cell(w, i, j, k, a, b, c);
+  cell_of(w, t, i, j, k, a, b, c);
 }
+
+// loop over this thread's work items
+#define FOR_ITEMS(w, t) for (long long t = block_linear_id(), t##_n = work_items(w); t < t##_n; t += item_stride())
+
 
 // time step source: explicit value, device scalar, or CFL maximum signal
 // speed (stored as the bit pattern of a positive double)
@@ -120,9 +137,32 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ------------------------------------------------------------ primitives
-template <typename T>
+// Energy storage of the mixed form: total energy in double, and the plasma
+// beta below which the pressure is recovered in double.
+struct Mix {
+  double* E64;      // nullptr unless the mixed form
+  double beta;
+};
+
+// gas pressure from the total energy (Eq. 5).  In the mixed form the
+// subtraction p = (gam-1)(e - rho v^2/2 - B^2/2) is redone in double when
+// the plasma beta 2p/|B|^2 of the float estimate is below mix.beta: there
+// the kinetic and magnetic terms nearly cancel e.
+template <typename T, bool MIX>
+__device__ __forceinline__ T recover_pressure(double e, T d, T vx, T vy, T vz, T bx, T by, T bz, T gam,
+                                              double beta) {
+  const T b2 = bx * bx + by * by + bz * bz;
+  const T pf = (gam - T(1)) * (T(e) - T(0.5) * d * (vx * vx + vy * vy + vz * vz) - T(0.5) * b2);
+  if (MIX && T(2) * pf < T(beta) * b2) {
+    const double dd = d, ux = vx, uy = vy, uz = vz, b2d = (double)bx * bx + (double)by * by + (double)bz * bz;
+    return T(((double)gam - 1.0) * (e - 0.5 * dd * (ux * ux + uy * uy + uz * uz) - 0.5 * b2d));
+  }
+  return pf;
+}
+
+template <typename T, bool MIX>
 __device__ __forceinline__ void cell_prims(const Work& w, const T* __restrict__ U, const T* __restrict__ B,
-                                           int i, int j, int k, T gam, T out[8]) {
+                                           const Mix& mix, int i, int j, int k, T gam, T out[8]) {
   const long long N = w.N;
   const long long p = lin(w, i, j, k);
   const T bx = T(0.5) * (B[p] + B[nbr(w, i, j, k, 1, 0, 0)]);
@@ -131,8 +171,13 @@ __device__ __forceinline__ void cell_prims(const Work& w, const T* __restrict__ 
   const T d = U[p];
   const T id = T(1) / d;
   const T vx = U[N + p] * id, vy = U[2 * N + p] * id, vz = U[3 * N + p] * id;
-  const T pr = (gam - T(1)) * (U[4 * N + p] - T(0.5) * d * (vx * vx + vy * vy + vz * vz) -
-                               T(0.5) * (bx * bx + by * by + bz * bz));
+  T pr;
+  if (MIX) {
+    pr = recover_pressure<T, true>(mix.E64[p], d, vx, vy, vz, bx, by, bz, gam, mix.beta);
+  } else {
+    pr = (gam - T(1)) * (U[4 * N + p] - T(0.5) * d * (vx * vx + vy * vy + vz * vz) -
+                         T(0.5) * (bx * bx + by * by + bz * bz));
+  }
   out[0] = d; out[1] = vx; out[2] = vy; out[3] = vz; out[4] = pr; out[5] = bx; out[6] = by; out[7] = bz;
 }
 
@@ -166,40 +211,48 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* s
 
 // Primitive state of every cell; optionally the CFL maximum signal speed and
 // the sticky non-physical flag.
-template <typename T, bool CFL>
-__global__ void __launch_bounds__(kBlock) k_prim(Work w, const T* __restrict__ U, const T* __restrict__ B,
+template <typename T, bool CFL, bool MIX>
+__global__ void __launch_bounds__(kBlock) k_prim(Work w, const T* __restrict__ U, const T* __restrict__ B, Mix mix,
                                                  T* __restrict__ W, T gam, unsigned long long* smax,
                                                  int* flag) {
-  int i, j, k;
   double s = 0.0;
-  if (my_cell(w, i, j, k)) {
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
     T q[8];
-    cell_prims(w, U, B, i, j, k, gam, q);
+    cell_prims<T, MIX>(w, U, B, mix, i, j, k, gam, q);
     const long long p = lin(w, i, j, k);
 #pragma unroll
     for (int m = 0; m < 8; ++m) W[m * w.N + p] = q[m];
     if (!(q[0] > T(0)) || !(q[4] > T(0))) atomicOr(flag, 1);
-    else if (CFL) s = signal_speed(q, gam);
+    else if (CFL) s = fmax(s, signal_speed(q, gam));
   }
   if (CFL) block_max_atomic(s, smax);
 }
 
 // CFL maximum signal speed only
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cfl(Work w, const T* __restrict__ U, const T* __restrict__ B, T gam,
-                                                unsigned long long* smax, int* flag) {
-  int i, j, k;
+template <typename T, bool MIX>
+__global__ void __launch_bounds__(kBlock) k_cfl(Work w, const T* __restrict__ U, const T* __restrict__ B, Mix mix,
+                                                T gam, unsigned long long* smax, int* flag) {
   double s = 0.0;
-  if (my_cell(w, i, j, k)) {
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
     T q[8];
-    cell_prims(w, U, B, i, j, k, gam, q);
+    cell_prims<T, MIX>(w, U, B, mix, i, j, k, gam, q);
     if (!(q[0] > T(0)) || !(q[4] > T(0))) atomicOr(flag, 1);
-    else s = signal_speed(q, gam);
+    else s = fmax(s, signal_speed(q, gam));
   }
   block_max_atomic(s, smax);
 }
 
 __global__ void k_reset_smax(unsigned long long* smax) { *smax = 0ull; }
+
+// *dt = min(*dt, courant dx / smax)
+__global__ void k_min_dt(const unsigned long long* smax, double courant_dx, double* dt) {
+  const double v = courant_dx / __longlong_as_double((long long)*smax);
+  if (v < *dt) *dt = v;
+}
 
 // dt = courant dx / smax into an output scalar, and t += dt
 __global__ void k_publish_dt(const unsigned long long* smax, double courant_dx, double* dt_out, double* t_out) {
@@ -277,9 +330,10 @@ __device__ __forceinline__ void block_count_atomic(int v, unsigned long long* co
 template <typename T, int RECON, int SOLVER>
 __global__ void __launch_bounds__(kBlock) k_flux(Work w, const T* __restrict__ W, const T* __restrict__ B,
                                                  T* __restrict__ F, T gam, unsigned long long* nfb) {
-  int i, j, k;
   int fb = 0;
-  if (my_cell(w, i, j, k)) {
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
     fb += face_flux<T, 0, RECON, SOLVER>(w, W, B, F, i, j, k, gam);
     fb += face_flux<T, 1, RECON, SOLVER>(w, W, B, F, i, j, k, gam);
     fb += face_flux<T, 2, RECON, SOLVER>(w, W, B, F, i, j, k, gam);
@@ -332,19 +386,22 @@ __device__ __forceinline__ T edge_emf(const Work& w, const T* __restrict__ F, co
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_emf(Work w, const T* __restrict__ F, const T* __restrict__ W,
                                                 T* __restrict__ E) {
-  int i, j, k;
-  if (!my_cell(w, i, j, k)) return;
-  const long long p = lin(w, i, j, k);
-  E[p] = edge_emf<T, 0>(w, F, W, i, j, k);
-  E[w.N + p] = edge_emf<T, 1>(w, F, W, i, j, k);
-  E[2 * w.N + p] = edge_emf<T, 2>(w, F, W, i, j, k);
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
+    const long long p = lin(w, i, j, k);
+    E[p] = edge_emf<T, 0>(w, F, W, i, j, k);
+    E[w.N + p] = edge_emf<T, 1>(w, F, W, i, j, k);
+    E[2 * w.N + p] = edge_emf<T, 2>(w, F, W, i, j, k);
+  }
 }
 
 // ------------------------------------------------------------ updates
-// U - r div F (Eq. 10), differences applied in the order x, y, z
-template <typename T>
+// U - r div F (Eq. 10), differences applied in the order x, y, z.  In the
+// mixed form the energy is updated in double from E64 (returned in e64).
+template <typename T, bool MIX>
 __device__ __forceinline__ void cell_update(const Work& w, const T* __restrict__ U, const T* __restrict__ F,
-                                            int i, int j, int k, T r, T out[5]) {
+                                            const Mix& mix, int i, int j, int k, T r, T out[5], double& e64) {
   const long long N = w.N;
   const long long p = lin(w, i, j, k);
   const long long px = nbr(w, i, j, k, 1, 0, 0), py = nbr(w, i, j, k, 0, 1, 0), pz = nbr(w, i, j, k, 0, 0, 1);
@@ -353,12 +410,23 @@ __device__ __forceinline__ void cell_update(const Work& w, const T* __restrict__
   const T* Fz = F + 14 * N;
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
+    if (MIX && m == 4) {
+      const double rd = (double)r;
+      double v = mix.E64[p];
+      v -= rd * ((double)Fx[4 * N + px] - (double)Fx[4 * N + p]);
+      v -= rd * ((double)Fy[4 * N + py] - (double)Fy[4 * N + p]);
+      v -= rd * ((double)Fz[4 * N + pz] - (double)Fz[4 * N + p]);
+      e64 = v;
+      out[4] = T(v);
+      continue;
+    }
     T v = U[m * N + p];
     v -= r * (Fx[m * N + px] - Fx[m * N + p]);
     v -= r * (Fy[m * N + py] - Fy[m * N + p]);
     v -= r * (Fz[m * N + pz] - Fz[m * N + p]);
     out[m] = v;
   }
+  if (!MIX) e64 = (double)out[4];
 }
 
 // CT update of the three lower faces of cell (i, j, k) (Eq. 13)
@@ -379,15 +447,17 @@ __device__ __forceinline__ void face_update(const Work& w, const T* __restrict__
 // Half step over dt/2: U^{n+1/2} and face B^{n+1/2} from the predictor fluxes
 // and EMFs, written as primitives Wh (cell-centred field from the updated
 // faces, including the upper faces owned by the neighbours) and Bh.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U, const T* __restrict__ B,
+template <typename T, bool MIX>
+__global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U, const T* __restrict__ B, Mix mix,
                                                  const T* __restrict__ F, const T* __restrict__ E, DtSrc dts,
                                                  T inv_dx, T gam, T* __restrict__ Wh, T* __restrict__ Bh) {
-  int i, j, k;
-  if (!my_cell(w, i, j, k)) return;
   const T r = T(0.5 * get_dt(dts)) * inv_dx;
+  FOR_ITEMS(w, t) {
+  int i, j, k;
+  cell_of(w, t, i, j, k);
   T u[5], bl[3], bux[3], buy[3], buz[3];
-  cell_update(w, U, F, i, j, k, r, u);
+  double eh;
+  cell_update<T, MIX>(w, U, F, mix, i, j, k, r, u, eh);
   face_update(w, B, E, i, j, k, r, bl);
   face_update(w, B, E, wrapc(i + 1, w.nx), j, k, r, bux);
   face_update(w, B, E, i, wrapc(j + 1, w.ny), k, r, buy);
@@ -398,12 +468,15 @@ __global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U
   const T d = u[0];
   const T id = T(1) / d;
   const T vx = u[1] * id, vy = u[2] * id, vz = u[3] * id;
-  const T pr = (gam - T(1)) * (u[4] - T(0.5) * d * (vx * vx + vy * vy + vz * vz) - T(0.5) * (bx * bx + by * by + bz * bz));
+  T pr;
+  if (MIX) pr = recover_pressure<T, true>(eh, d, vx, vy, vz, bx, by, bz, gam, mix.beta);
+  else pr = (gam - T(1)) * (u[4] - T(0.5) * d * (vx * vx + vy * vy + vz * vz) - T(0.5) * (bx * bx + by * by + bz * bz));
   const long long N = w.N;
   const long long p = lin(w, i, j, k);
   Wh[p] = d; Wh[N + p] = vx; Wh[2 * N + p] = vy; Wh[3 * N + p] = vz; Wh[4 * N + p] = pr;
   Wh[5 * N + p] = bx; Wh[6 * N + p] = by; Wh[7 * N + p] = bz;
   Bh[p] = bl[0]; Bh[N + p] = bl[1]; Bh[2 * N + p] = bl[2];
+  }
 }
 
 // Full step over dt from time n (in place: each thread reads and writes only
@@ -413,16 +486,18 @@ __global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U
 // the face it shares with the next cell when the next cell's group is not
 // listed (occupancy map), so every face of a listed group advances exactly
 // once and no face is read after another thread has written it.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* __restrict__ B,
+template <typename T, bool MIX>
+__global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* __restrict__ B, Mix mix,
                                                   const T* __restrict__ F, const T* __restrict__ E, DtSrc dts,
                                                   T inv_dx) {
-  int i, j, k, a, b, c;
-  if (!my_cell(w, i, j, k, a, b, c)) return;
   const T r = T(get_dt(dts)) * inv_dx;
   const long long N = w.N;
+  FOR_ITEMS(w, t) {
+  int i, j, k, a, b, c;
+  cell_of(w, t, i, j, k, a, b, c);
   T u[5], bf[3];
-  cell_update(w, U, F, i, j, k, r, u);
+  double e64;
+  cell_update<T, MIX>(w, U, F, mix, i, j, k, r, u, e64);
   face_update(w, B, E, i, j, k, r, bf);
   T ux[3], uy[3], uz[3];
   bool ex = false, ey = false, ez = false;
@@ -441,10 +516,12 @@ __global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* 
   const long long p = lin(w, i, j, k);
 #pragma unroll
   for (int m = 0; m < 5; ++m) U[m * N + p] = u[m];
+  if (MIX) mix.E64[p] = e64;
   B[p] = bf[0]; B[N + p] = bf[1]; B[2 * N + p] = bf[2];
   if (ex) B[nbr(w, i, j, k, 1, 0, 0)] = ux[0];
   if (ey) B[N + nbr(w, i, j, k, 0, 1, 0)] = uy[1];
   if (ez) B[2 * N + nbr(w, i, j, k, 0, 0, 1)] = uz[2];
+  }
 }
 
 // ------------------------------------------------------------ CTU
@@ -478,12 +555,14 @@ template <typename T, int RECON>
 __global__ void __launch_bounds__(kBlock) k_ctu_states(Work w, const T* __restrict__ W, const T* __restrict__ B,
                                                        T* __restrict__ QL, T* __restrict__ QR, DtSrc dts,
                                                        T inv_dx, T gam) {
-  int i, j, k;
-  if (!my_cell(w, i, j, k)) return;
   const T dtdx = T(get_dt(dts)) * inv_dx;
-  cell_states<T, 0, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
-  cell_states<T, 1, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
-  cell_states<T, 2, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
+    cell_states<T, 0, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
+    cell_states<T, 1, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
+    cell_states<T, 2, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
+  }
 }
 
 template <typename T, int D>
@@ -503,10 +582,11 @@ __device__ __forceinline__ void store_flux(T* __restrict__ F, long long N, long 
 template <typename T, int SOLVER>
 __global__ void __launch_bounds__(kBlock) k_flux_q(Work w, const T* __restrict__ QL, const T* __restrict__ QR,
                                                    const T* __restrict__ B, T* __restrict__ F, T gam,
-                                                   unsigned long long* nfb) {
-  int i, j, k;
+                                                   unsigned long long* nfb, Capture cp) {
   int fb = 0;
-  if (my_cell(w, i, j, k)) {
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
     const long long N = w.N;
     const long long p = lin(w, i, j, k);
 #pragma unroll
@@ -518,12 +598,50 @@ __global__ void __launch_bounds__(kBlock) k_flux_q(Work w, const T* __restrict__
         wr[m] = QR[((long long)d * 7 + m) * N + p];
       }
       fb += riemann<SOLVER>(wl, wr, B[d * N + p], gam, f);
+      if constexpr (sizeof(T) == 4) capture_face(cp, 3 * p + d, wl, wr, B[d * N + p], f);
       if (d == 0) store_flux<T, 0>(F, N, p, f);
       else if (d == 1) store_flux<T, 1>(F, N, p, f);
       else store_flux<T, 2>(F, N, p, f);
     }
   }
   if (SOLVER == 0) block_count_atomic(fb, nfb);
+}
+
+// Step 2 with the learned flux (HLLD at strong jumps); counts HLLD faces
+__global__ void __launch_bounds__(kBlock) k_flux_q_mlp(Work w, const float* __restrict__ QL,
+                                                       const float* __restrict__ QR, const float* __restrict__ B,
+                                                       float* __restrict__ F, float gam, const MlpWeights* mw,
+                                                       float dp, float drho, unsigned long long* nfb) {
+  __shared__ MlpShared sh;
+  mlp_load_weights(sh, mw);
+  const long long N = w.N;
+  const long long nitems = work_items(w);
+  int fb = 0;
+  // block-uniform trips: the network uses block barriers
+  for (long long base = block_linear_id() - threadIdx.x; base < nitems; base += item_stride()) {
+    const long long t = base + threadIdx.x;
+    const bool active = t < nitems;
+    int i = 0, j = 0, k = 0;
+    if (active) cell_of(w, t, i, j, k);
+    const long long p = active ? lin(w, i, j, k) : 0;
+    for (int d = 0; d < 3; ++d) {
+      float wl[7], wr[7], f[7];
+      float bn = 1.0f;
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        wl[m] = active ? QL[((long long)d * 7 + m) * N + p] : 1.0f;
+        wr[m] = active ? QR[((long long)d * 7 + m) * N + p] : 1.0f;
+      }
+      if (active) bn = B[d * N + p];
+      fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
+      if (active) {
+        if (d == 0) store_flux<float, 0>(F, N, p, f);
+        else if (d == 1) store_flux<float, 1>(F, N, p, f);
+        else store_flux<float, 2>(F, N, p, f);
+      }
+    }
+  }
+  block_count_atomic(fb, nfb);
 }
 
 // Step 5: transverse correction of a state of direction D that comes from
@@ -582,14 +700,14 @@ __device__ __forceinline__ void correct_state(const Work& w, const T* __restrict
   }
 }
 
-template <typename T, int D, int SOLVER>
-__device__ __forceinline__ int corrected_face_flux(const Work& w, const T* __restrict__ QL, const T* __restrict__ QR,
-                                                   const T* __restrict__ F1, const T* __restrict__ E1,
-                                                   const T* __restrict__ B, const T* __restrict__ Bh,
-                                                   T* __restrict__ F2, int i, int j, int k, T hr, T gam) {
+template <typename T, int D>
+__device__ __forceinline__ void corrected_states(const Work& w, const T* __restrict__ QL, const T* __restrict__ QR,
+                                                 const T* __restrict__ F1, const T* __restrict__ E1,
+                                                 const T* __restrict__ B, int i, int j, int k, T hr, T gam, T wl[7],
+                                                 T wr[7]) {
   const long long N = w.N;
   const long long p = lin(w, i, j, k);
-  T sl[7], sr[7], wl[7], wr[7], f[7];
+  T sl[7], sr[7];
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
     sl[m] = QL[((long long)D * 7 + m) * N + p];
@@ -599,7 +717,20 @@ __device__ __forceinline__ int corrected_face_flux(const Work& w, const T* __res
   correct_state<T, D>(w, F1, E1, wrapc(i - (D == 0), w.nx), wrapc(j - (D == 1), w.ny), wrapc(k - (D == 2), w.nz), bn,
                       hr, gam, sl, wl);
   correct_state<T, D>(w, F1, E1, i, j, k, bn, hr, gam, sr, wr);
+}
+
+template <typename T, int D, int SOLVER>
+__device__ __forceinline__ int corrected_face_flux(const Work& w, const T* __restrict__ QL, const T* __restrict__ QR,
+                                                   const T* __restrict__ F1, const T* __restrict__ E1,
+                                                   const T* __restrict__ B, const T* __restrict__ Bh,
+                                                   T* __restrict__ F2, int i, int j, int k, T hr, T gam,
+                                                   const Capture& cp) {
+  const long long N = w.N;
+  const long long p = lin(w, i, j, k);
+  T wl[7], wr[7], f[7];
+  corrected_states<T, D>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
   const int fb = riemann<SOLVER>(wl, wr, Bh[D * N + p], gam, f);
+  if constexpr (sizeof(T) == 4) capture_face(cp, 3 * p + D, wl, wr, Bh[D * N + p], f);
   store_flux<T, D>(F2, N, p, f);
   return fb;
 }
@@ -610,16 +741,59 @@ __global__ void __launch_bounds__(kBlock) k_ctu_correct(Work w, const T* __restr
                                                         const T* __restrict__ F1, const T* __restrict__ E1,
                                                         const T* __restrict__ B, const T* __restrict__ Bh,
                                                         T* __restrict__ F2, DtSrc dts, T inv_dx, T gam,
-                                                        unsigned long long* nfb) {
-  int i, j, k;
+                                                        unsigned long long* nfb, Capture cp) {
   int fb = 0;
-  if (my_cell(w, i, j, k)) {
-    const T hr = T(0.5 * get_dt(dts)) * inv_dx;
-    fb += corrected_face_flux<T, 0, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam);
-    fb += corrected_face_flux<T, 1, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam);
-    fb += corrected_face_flux<T, 2, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam);
+  const T hr = T(0.5 * get_dt(dts)) * inv_dx;
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
+    fb += corrected_face_flux<T, 0, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam, cp);
+    fb += corrected_face_flux<T, 1, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam, cp);
+    fb += corrected_face_flux<T, 2, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam, cp);
   }
   if (SOLVER == 0) block_count_atomic(fb, nfb);
+}
+
+// Steps 5-6 with the learned flux (HLLD at strong jumps); counts HLLD faces
+__global__ void __launch_bounds__(kBlock) k_ctu_correct_mlp(Work w, const float* __restrict__ QL,
+                                                            const float* __restrict__ QR, const float* __restrict__ F1,
+                                                            const float* __restrict__ E1, const float* __restrict__ B,
+                                                            const float* __restrict__ Bh, float* __restrict__ F2,
+                                                            DtSrc dts, float inv_dx, float gam, const MlpWeights* mw,
+                                                            float dp, float drho, unsigned long long* nfb) {
+  __shared__ MlpShared sh;
+  mlp_load_weights(sh, mw);
+  const long long N = w.N;
+  const float hr = float(0.5 * get_dt(dts)) * inv_dx;
+  const long long nitems = work_items(w);
+  int fb = 0;
+  for (long long base = block_linear_id() - threadIdx.x; base < nitems; base += item_stride()) {
+  const long long t = base + threadIdx.x;
+  const bool active = t < nitems;
+  int i = 0, j = 0, k = 0;
+  if (active) cell_of(w, t, i, j, k);
+  const long long p = active ? lin(w, i, j, k) : 0;
+  for (int d = 0; d < 3; ++d) {
+    float wl[7], wr[7], f[7];
+    float bn = 1.0f;
+    if (active) {
+      if (d == 0) corrected_states<float, 0>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
+      else if (d == 1) corrected_states<float, 1>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
+      else corrected_states<float, 2>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
+      bn = Bh[d * N + p];
+    } else {
+#pragma unroll
+      for (int m = 0; m < 7; ++m) wl[m] = wr[m] = 1.0f;
+    }
+    fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
+    if (active) {
+      if (d == 0) store_flux<float, 0>(F2, N, p, f);
+      else if (d == 1) store_flux<float, 1>(F2, N, p, f);
+      else store_flux<float, 2>(F2, N, p, f);
+    }
+  }
+  }
+  block_count_atomic(fb, nfb);
 }
 
 // group occupancy map of a list: clear, then mark
@@ -628,20 +802,128 @@ __global__ void __launch_bounds__(kBlock) k_occ_clear(int* occ, long long n) {
   if (t < n) occ[t] = 0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_occ_set(int* occ, const int* groups, int n_groups, int edge, int gnx,
-                                                    int gny) {
+__global__ void __launch_bounds__(kBlock) k_occ_set(int* occ, const int* groups, int n_groups, const int* n_dev,
+                                                    int edge, int gnx, int gny) {
   const int g = blockIdx.x * kBlock + threadIdx.x;
-  if (g >= n_groups) return;
+  const int n = n_dev ? min(*n_dev, n_groups) : n_groups;
+  if (g >= n) return;
   const int gi = groups[3 * g] / edge, gj = groups[3 * g + 1] / edge, gk = groups[3 * g + 2] / edge;
   occ[((long long)gk * gny + gj) * gnx + gi] = 1;
 }
 
-// ------------------------------------------------------------ set-up
+// ------------------------------------------------------------ AMR support
+// Prolongation from a coarse level (nc) to a fine level (2 nc), paper
+// Sec. 3.3 (refinement operation).  Cell data: density and momentum are
+// injected (conservative: the 8 children average to the parent); the energy
+// is rebuilt from the parent's pressure and kinetic energy with the child's
+// own face field, which keeps the pressure positive.  Face field: a fine face
+// lying on a coarse face takes the coarse value; a fine face inside a coarse
+// cell takes the mean of the two coarse faces bracketing it.  Every fine
+// cell's discrete divergence then equals its parent's (zero for a solenoidal
+// coarse field) and the area average of fine faces equals the coarse face.
+// (A first-order, divergence-free stand-in for Balsara's second-order
+// reconstruction.)
+template <typename T, int A>
+__device__ __forceinline__ T prolong_face(const Work& wc, const T* __restrict__ Bc, int I, int J, int K) {
+  const int cf[3] = {I >> 1, J >> 1, K >> 1};
+  const int odd = (A == 0 ? I : (A == 1 ? J : K)) & 1;
+  const long long lo = lin(wc, cf[0], cf[1], cf[2]);
+  const T b0 = Bc[A * wc.N + lo];
+  if (!odd) return b0;
+  const long long hi = nbr(wc, cf[0], cf[1], cf[2], A == 0, A == 1, A == 2);
+  return T(0.5) * (b0 + Bc[A * wc.N + hi]);
+}
+
+// fill fine cell (I, J, K) and, where allowed, its three lower faces
 template <typename T>
+__device__ __forceinline__ void prolong_cell(const Work& wc, const Work& wf, const T* __restrict__ Uc,
+                                             const T* __restrict__ Bc, T* __restrict__ Uf, T* __restrict__ Bf,
+                                             int I, int J, int K, bool cell, const bool face[3], T gam) {
+  const long long pc = lin(wc, I >> 1, J >> 1, K >> 1);
+  const long long pf = lin(wf, I, J, K);
+  if (face[0]) Bf[pf] = prolong_face<T, 0>(wc, Bc, I, J, K);
+  if (face[1]) Bf[wf.N + pf] = prolong_face<T, 1>(wc, Bc, I, J, K);
+  if (face[2]) Bf[2 * wf.N + pf] = prolong_face<T, 2>(wc, Bc, I, J, K);
+  if (!cell) return;
+  const T bx = T(0.5) * (prolong_face<T, 0>(wc, Bc, I, J, K) + prolong_face<T, 0>(wc, Bc, wrapc(I + 1, wf.nx), J, K));
+  const T by = T(0.5) * (prolong_face<T, 1>(wc, Bc, I, J, K) + prolong_face<T, 1>(wc, Bc, I, wrapc(J + 1, wf.ny), K));
+  const T bz = T(0.5) * (prolong_face<T, 2>(wc, Bc, I, J, K) + prolong_face<T, 2>(wc, Bc, I, J, wrapc(K + 1, wf.nz)));
+  // parent's pressure (cell-centred parent field)
+  const int ci = I >> 1, cj = J >> 1, ck = K >> 1;
+  const T cbx = T(0.5) * (Bc[pc] + Bc[nbr(wc, ci, cj, ck, 1, 0, 0)]);
+  const T cby = T(0.5) * (Bc[wc.N + pc] + Bc[wc.N + nbr(wc, ci, cj, ck, 0, 1, 0)]);
+  const T cbz = T(0.5) * (Bc[2 * wc.N + pc] + Bc[2 * wc.N + nbr(wc, ci, cj, ck, 0, 0, 1)]);
+  const T d = Uc[pc], mx = Uc[wc.N + pc], my = Uc[2 * wc.N + pc], mz = Uc[3 * wc.N + pc];
+  const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / d;
+  const T pr = (gam - T(1)) * (Uc[4 * wc.N + pc] - ek - T(0.5) * (cbx * cbx + cby * cby + cbz * cbz));
+  Uf[pf] = d;
+  Uf[wf.N + pf] = mx;
+  Uf[2 * wf.N + pf] = my;
+  Uf[3 * wf.N + pf] = mz;
+  Uf[4 * wf.N + pf] = pr / (gam - T(1)) + ek + T(0.5) * (bx * bx + by * by + bz * bz);
+}
+
+// whole fine level from the coarse level
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_all(Work wc, Work wf, const T* __restrict__ Uc,
+                                                        const T* __restrict__ Bc, T* __restrict__ Uf,
+                                                        T* __restrict__ Bf, T gam) {
+  const bool all3[3] = {true, true, true};
+  FOR_ITEMS(wf, t) {
+    int I, J, K;
+    cell_of(wf, t, I, J, K);
+    prolong_cell(wc, wf, Uc, Bc, Uf, Bf, I, J, K, true, all3, gam);
+  }
+}
+
+// ghost halos of the listed fine groups: cells outside every listed group,
+// and faces whose two cells are both outside every listed group
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_ghosts(Work wc, Work wf, const T* __restrict__ Uc,
+                                                           const T* __restrict__ Bc, T* __restrict__ Uf,
+                                                           T* __restrict__ Bf, T gam) {
+  FOR_ITEMS(wf, t) {
+    int I, J, K;
+    cell_of(wf, t, I, J, K);
+    auto listed = [&](int x, int y, int z) {
+      x = wrapc(x, wf.nx); y = wrapc(y, wf.ny); z = wrapc(z, wf.nz);
+      return wf.occ[((long long)(z / wf.edge) * wf.gny + y / wf.edge) * wf.gnx + x / wf.edge] != 0;
+    };
+    const bool ghost = !listed(I, J, K);
+    const bool face[3] = {ghost && !listed(I - 1, J, K), ghost && !listed(I, J - 1, K), ghost && !listed(I, J, K - 1)};
+    if (ghost) prolong_cell(wc, wf, Uc, Bc, Uf, Bf, I, J, K, true, face, gam);
+  }
+}
+
+// restriction (Sec. 3.3, correction operation): coarse cells under listed
+// fine groups take the volume average of their 8 children
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict(Work wc, Work wf, const T* __restrict__ Uf, T* __restrict__ Uc) {
+  // work items are coarse cells of the fine groups' footprints (edge/2)^3
+  FOR_ITEMS(wc, t) {
+    int i, j, k;
+    cell_of(wc, t, i, j, k);
+    const long long pc = lin(wc, i, j, k);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      T s = T(0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int I = 2 * i + (c & 1), J = 2 * j + ((c >> 1) & 1), K = 2 * k + (c >> 2);
+        s += Uf[m * wf.N + lin(wf, I, J, K)];
+      }
+      Uc[m * wc.N + pc] = T(0.125) * s;
+    }
+  }
+}
+
+// ------------------------------------------------------------ set-up
+template <typename T, bool MIX>
 __global__ void __launch_bounds__(kBlock) k_prim_to_cons(Work w, const T* __restrict__ W5, const T* __restrict__ B,
-                                                         T* __restrict__ U, T gam) {
+                                                         T* __restrict__ U, Mix mix, T gam) {
+  FOR_ITEMS(w, t) {
   int i, j, k;
-  if (!my_cell(w, i, j, k)) return;
+  cell_of(w, t, i, j, k);
   const long long N = w.N;
   const long long p = lin(w, i, j, k);
   const T bx = T(0.5) * (B[p] + B[nbr(w, i, j, k, 1, 0, 0)]);
@@ -652,7 +934,16 @@ __global__ void __launch_bounds__(kBlock) k_prim_to_cons(Work w, const T* __rest
   U[N + p] = d * vx;
   U[2 * N + p] = d * vy;
   U[3 * N + p] = d * vz;
-  U[4 * N + p] = pr / (gam - T(1)) + T(0.5) * d * (vx * vx + vy * vy + vz * vz) + T(0.5) * (bx * bx + by * by + bz * bz);
+  if (MIX) {
+    const double e = (double)pr / ((double)gam - 1.0) +
+                     0.5 * (double)d * ((double)vx * vx + (double)vy * vy + (double)vz * vz) +
+                     0.5 * ((double)bx * bx + (double)by * by + (double)bz * bz);
+    mix.E64[p] = e;
+    U[4 * N + p] = T(e);
+  } else {
+    U[4 * N + p] = pr / (gam - T(1)) + T(0.5) * d * (vx * vx + vy * vy + vz * vz) + T(0.5) * (bx * bx + by * by + bz * bz);
+  }
+  }
 }
 
 // ------------------------------------------------------------ diagnostics
@@ -681,18 +972,20 @@ __device__ __forceinline__ void block_partials(double v[NQ], double* part, int s
 // discrete divergence (Eq. 16): partial sums of |div B| and partial maxima
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_divb(Work w, const T* __restrict__ B, double inv_dx, double* part) {
-  int i, j, k;
-  double a = 0.0;
-  if (my_cell(w, i, j, k)) {
+  double a = 0.0, amax = 0.0;
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
     const long long N = w.N;
     const long long p = lin(w, i, j, k);
     const double dv = ((double)B[nbr(w, i, j, k, 1, 0, 0)] - (double)B[p]) * inv_dx +
                       ((double)B[N + nbr(w, i, j, k, 0, 1, 0)] - (double)B[N + p]) * inv_dx +
                       ((double)B[2 * N + nbr(w, i, j, k, 0, 0, 1)] - (double)B[2 * N + p]) * inv_dx;
-    a = fabs(dv);
+    a += fabs(dv);
+    amax = fmax(amax, fabs(dv));
   }
   __shared__ double mx[kBlock / 64];
-  const double wm = wave_max(a);
+  const double wm = wave_max(amax);
   if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = wm;
   double v[1] = {a};
   block_partials<1>(v, part, gridDim.x);
@@ -706,19 +999,24 @@ __global__ void __launch_bounds__(kBlock) k_divb(Work w, const T* __restrict__ B
 // volume totals: mass, Mx, My, Mz, e, magnetic energy, kinetic energy
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_sums(Work w, const T* __restrict__ U, const T* __restrict__ B,
-                                                 double* part) {
-  int i, j, k;
+                                                 const double* __restrict__ E64, double* part) {
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
-  if (my_cell(w, i, j, k)) {
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
     const long long N = w.N;
     const long long p = lin(w, i, j, k);
+    double u[5];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) v[m] = (double)U[m * N + p];
+    for (int m = 0; m < 5; ++m) u[m] = (double)U[m * N + p];
+    if (E64) u[4] = E64[p];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) v[m] += u[m];
     const double bx = 0.5 * ((double)B[p] + (double)B[nbr(w, i, j, k, 1, 0, 0)]);
     const double by = 0.5 * ((double)B[N + p] + (double)B[N + nbr(w, i, j, k, 0, 1, 0)]);
     const double bz = 0.5 * ((double)B[2 * N + p] + (double)B[2 * N + nbr(w, i, j, k, 0, 0, 1)]);
-    v[5] = 0.5 * (bx * bx + by * by + bz * bz);
-    v[6] = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0];
+    v[5] += 0.5 * (bx * bx + by * by + bz * bz);
+    v[6] += 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
   }
   block_partials<7>(v, part, gridDim.x);
 }

@@ -44,7 +44,8 @@ class Config(ctypes.Structure):
 class LevelDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dx", ctypes.c_double),
                 ("n_groups", ctypes.c_int), ("group_edge", ctypes.c_int), ("groups", ctypes.c_void_p),
-                ("U", ctypes.c_void_p), ("B", ctypes.c_void_p), ("E64", ctypes.c_void_p)]
+                ("U", ctypes.c_void_p), ("B", ctypes.c_void_p), ("E64", ctypes.c_void_p),
+                ("n_groups_dev", ctypes.c_void_p)]
 
 
 _lib = None
@@ -52,7 +53,10 @@ _lib = None
 EXPORTS = ["mhd_abi_version", "mhd_strerror", "mhd_required_ghost", "mhd_init", "mhd_finalize",
            "mhd_check_level", "mhd_prim_to_cons", "mhd_cfl_dt", "mhd_step", "mhd_step_devdt",
            "mhd_advance", "mhd_divB", "mhd_sums", "mhd_fallback_count", "mhd_sync",
-           "mhd_profile_step", "mhd_num_stages", "mhd_stage_name"]
+           "mhd_profile_step", "mhd_num_stages", "mhd_stage_name",
+           "mhd_mlp_num_params", "mhd_mlp_set_weights", "mhd_mlp_forward", "mhd_mlp_backward",
+           "mhd_mlp_train_step", "mhd_mlp_prepare", "mhd_mlp_face_flux", "mhd_set_capture",
+           "mhd_advance_graph", "mhd_set_launch", "mhd_cfl_dt_min", "mhd_prolong", "mhd_restrict"]
 
 
 def load(path: str = LIB_PATH):
@@ -83,6 +87,19 @@ def load(path: str = LIB_PATH):
     lib.mhd_num_stages.argtypes = [P]
     lib.mhd_stage_name.restype = ctypes.c_char_p
     lib.mhd_stage_name.argtypes = [P, I]
+    lib.mhd_mlp_num_params.argtypes = []
+    lib.mhd_mlp_set_weights.argtypes = [P, P]
+    lib.mhd_mlp_forward.argtypes = [P, P, P, I, P]
+    lib.mhd_mlp_backward.argtypes = [P, P, P, P, I, P]
+    lib.mhd_mlp_train_step.argtypes = [P, P, P, P, P, I, P, P, I, ctypes.c_float, P]
+    lib.mhd_mlp_prepare.argtypes = [P, P, I, P, P, P]
+    lib.mhd_mlp_face_flux.argtypes = [P, P, I, P, P]
+    lib.mhd_set_capture.argtypes = [P, P, ctypes.c_longlong, P, I]
+    lib.mhd_advance_graph.argtypes = [P, ctypes.POINTER(LevelDesc), P, P]
+    lib.mhd_set_launch.argtypes = [P, I]
+    lib.mhd_cfl_dt_min.argtypes = [P, ctypes.POINTER(LevelDesc), P]
+    lib.mhd_prolong.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc), I]
+    lib.mhd_restrict.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc)]
     _lib = lib
     return lib
 
@@ -114,6 +131,7 @@ class Level:
         self.U, self.B, self.dx = U, B, float(dx)
         self.E64 = E64
         self.group_edge = int(group_edge)
+        self.n_groups_dev = None
         self.set_groups(groups)
 
     def set_groups(self, groups):
@@ -132,7 +150,8 @@ class Level:
         g = self.groups
         return LevelDesc(nx, ny, nz, self.dx, 0 if g is None else int(g.shape[0]), self.group_edge,
                          None if g is None else g.data_ptr(), self.U.data_ptr(), self.B.data_ptr(),
-                         None if self.E64 is None else self.E64.data_ptr())
+                         None if self.E64 is None else self.E64.data_ptr(),
+                         None if self.n_groups_dev is None else self.n_groups_dev.data_ptr())
 
 
 class Solver:
@@ -168,7 +187,10 @@ class Solver:
         W5 = W5.to(device="cuda", dtype=self.dtype).contiguous()
         B = B.to(device="cuda", dtype=self.dtype).contiguous()
         U = torch.empty_like(W5)
-        lv = Level(U, B, dx, groups, group_edge)
+        E64 = None
+        if self.prec == F32_MIXED:
+            E64 = torch.empty(tuple(U.shape[1:]), dtype=torch.float64, device="cuda")
+        lv = Level(U, B, dx, groups, group_edge, E64=E64)
         self.prim_to_cons(lv, W5)
         return lv
 
@@ -181,6 +203,10 @@ class Solver:
     def _check_level(self, lv: Level):
         if lv.U.dtype != self.dtype:
             raise ValueError(f"level dtype {lv.U.dtype} does not match solver precision {self.dtype}")
+        if self.prec == F32_MIXED:
+            e = lv.E64
+            if e is None or e.dtype != torch.float64 or tuple(e.shape) != lv.shape or not e.is_contiguous():
+                raise ValueError("the mixed form needs a contiguous float64 E64 of the grid's shape")
 
     # -- the update
     def cfl_dt(self, lv: Level) -> float:
@@ -209,6 +235,30 @@ class Solver:
         _check(self.lib.mhd_advance(self.h, ctypes.byref(d),
                                     None if dt_dev is None else ctypes.c_void_p(dt_dev.data_ptr()),
                                     None if t_dev is None else ctypes.c_void_p(t_dev.data_ptr())), "mhd_advance")
+
+    def advance_graph(self, lv: Level, dt_dev: torch.Tensor | None = None, t_dev: torch.Tensor | None = None):
+        """mhd_advance replayed from a captured HIP graph (needs a non-default stream)."""
+        self._check_level(lv)
+        d = lv.desc()
+        _check(self.lib.mhd_advance_graph(self.h, ctypes.byref(d),
+                                          None if dt_dev is None else ctypes.c_void_p(dt_dev.data_ptr()),
+                                          None if t_dev is None else ctypes.c_void_p(t_dev.data_ptr())),
+               "mhd_advance_graph")
+
+    def set_launch(self, blocks_per_cu: int):
+        _check(self.lib.mhd_set_launch(self.h, int(blocks_per_cu)), "mhd_set_launch")
+
+    def cfl_dt_min(self, lv: Level, dt_dev: torch.Tensor):
+        d = lv.desc()
+        _check(self.lib.mhd_cfl_dt_min(self.h, ctypes.byref(d), ctypes.c_void_p(dt_dev.data_ptr())), "mhd_cfl_dt_min")
+
+    def prolong(self, coarse: Level, fine: Level, halo: int = 4):
+        dc, df = coarse.desc(), fine.desc()
+        _check(self.lib.mhd_prolong(self.h, ctypes.byref(dc), ctypes.byref(df), int(halo)), "mhd_prolong")
+
+    def restrict(self, fine: Level, coarse: Level):
+        dc, df = coarse.desc(), fine.desc()
+        _check(self.lib.mhd_restrict(self.h, ctypes.byref(df), ctypes.byref(dc)), "mhd_restrict")
 
     # -- diagnostics
     def divb(self, lv: Level):
@@ -239,3 +289,81 @@ class Solver:
         _check(self.lib.mhd_profile_step(self.h, ctypes.byref(d), int(nrep), ctypes.cast(out, ctypes.c_void_p)),
                "mhd_profile_step")
         return {self.lib.mhd_stage_name(self.h, s).decode(): out[s] for s in range(n)}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, shape=None, what="tensor"):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous float32 device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+class MlpOps:
+    """Learned-flux entry points of one Solver (its context and stream)."""
+
+    def __init__(self, solver: Solver):
+        self.s = solver
+        self.lib = solver.lib
+        self.nparam = self.lib.mhd_mlp_num_params()
+
+    def set_weights(self, params):
+        _dev_f32(params, (self.nparam,), "params")
+        _check(self.lib.mhd_mlp_set_weights(self.s.h, _ptr(params)), "mhd_mlp_set_weights")
+
+    def forward(self, params, X):
+        n = X.shape[0]
+        _dev_f32(params, (self.nparam,), "params")
+        _dev_f32(X, (n, 15), "X")
+        Y = torch.empty((n, 7), dtype=torch.float32, device="cuda")
+        _check(self.lib.mhd_mlp_forward(self.s.h, _ptr(params), _ptr(X), n, _ptr(Y)), "mhd_mlp_forward")
+        return Y
+
+    def backward(self, params, X, dY):
+        n = X.shape[0]
+        _dev_f32(params, (self.nparam,), "params")
+        _dev_f32(X, (n, 15), "X")
+        _dev_f32(dY, (n, 7), "dY")
+        G = torch.empty(self.nparam, dtype=torch.float32, device="cuda")
+        _check(self.lib.mhd_mlp_backward(self.s.h, _ptr(params), _ptr(X), _ptr(dY), n, _ptr(G)), "mhd_mlp_backward")
+        return G
+
+    def train_step(self, params, m, v, grads, step: int, X, T, lr: float, loss=None):
+        n = X.shape[0]
+        for t, nm in ((params, "params"), (m, "adam_m"), (v, "adam_v"), (grads, "grads")):
+            _dev_f32(t, (self.nparam,), nm)
+        _dev_f32(X, (n, 15), "X")
+        _dev_f32(T, (n, 7), "T")
+        _check(self.lib.mhd_mlp_train_step(self.s.h, _ptr(params), _ptr(m), _ptr(v), _ptr(grads), int(step), _ptr(X),
+                                           _ptr(T), n, float(lr), _ptr(loss)), "mhd_mlp_train_step")
+
+    def prepare(self, samples):
+        n = samples.shape[0]
+        _dev_f32(samples, (n, 22), "samples")
+        X = torch.empty((n, 15), dtype=torch.float32, device="cuda")
+        T = torch.empty((n, 7), dtype=torch.float32, device="cuda")
+        F = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(self.lib.mhd_mlp_prepare(self.s.h, _ptr(samples), n, _ptr(X), _ptr(T), _ptr(F)), "mhd_mlp_prepare")
+        return X, T, F
+
+    def face_flux(self, states):
+        n = states.shape[0]
+        _dev_f32(states, (n, 15), "states")
+        Fl = torch.empty((n, 7), dtype=torch.float32, device="cuda")
+        used = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(self.lib.mhd_mlp_face_flux(self.s.h, _ptr(states), n, _ptr(Fl), _ptr(used)), "mhd_mlp_face_flux")
+        return Fl, used
+
+    def set_capture(self, buf=None, count=None, stride: int = 1):
+        if buf is None:
+            _check(self.lib.mhd_set_capture(self.s.h, None, 0, None, 1), "mhd_set_capture")
+            return
+        _dev_f32(buf, (buf.shape[0], 22), "capture buffer")
+        if not (count.is_cuda and count.dtype == torch.int64 and count.numel() == 1):
+            raise ValueError("count must be a one-element int64 device tensor")
+        _check(self.lib.mhd_set_capture(self.s.h, _ptr(buf), buf.shape[0], _ptr(count), int(stride)),
+               "mhd_set_capture")

@@ -38,7 +38,7 @@ def test_header_matches_exports(mhd):
 
 def test_abi_version_and_strings(mhd):
     lib = mhd.load()
-    assert lib.mhd_abi_version() == 1
+    assert lib.mhd_abi_version() == 2
     for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert len(lib.mhd_strerror(s)) > 0
     assert lib.mhd_strerror(-999) == b"unknown status"

@@ -1,0 +1,172 @@
+"""GPU tests of the batched level update: HIP-graph replay, persistent launch
+shapes, AMR prolongation/restriction against the oracle, and a three-level
+hierarchy with uneven group lists."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from oracle import amr as oamr  # noqa: E402
+from paper_1804_03479_amd import inputs  # noqa: E402
+from paper_1804_03479_amd.amr import Hierarchy, nested_groups  # noqa: E402
+from paper_1804_03479_amd.mhd import Level, Solver  # noqa: E402
+
+
+def lvl(U, B, dx, dtype=torch.float64, groups=None):
+    return Level(torch.from_numpy(U).to("cuda", dtype).contiguous(),
+                 torch.from_numpy(B).to("cuda", dtype).contiguous(), dx, groups=groups)
+
+
+@pytest.mark.parametrize("blocks_per_cu", [0, 1, 3])
+def test_launch_shape_does_not_change_results(blocks_per_cu):
+    p = inputs.abc_problem(32, 0.1, seed=4)
+    U, B = oracle.initial_state(p)
+    ref = Solver("ctu", "ppm", "hlld")
+    a = lvl(U, B, p["dx"])
+    s = Solver("ctu", "ppm", "hlld")
+    s.set_launch(blocks_per_cu)
+    b = lvl(U, B, p["dx"])
+    for _ in range(3):
+        ref.advance(a)
+        s.advance(b)
+    torch.cuda.synchronize()
+    assert torch.equal(a.U, b.U) and torch.equal(a.B, b.B)
+
+
+def test_graph_replay_matches_eager():
+    stream = torch.cuda.Stream()
+    p = inputs.abc_problem(32, 0.1, seed=5)
+    U, B = oracle.initial_state(p)
+    with torch.cuda.stream(stream):
+        s = Solver("ctu", "ppm", "hlld", stream=stream)
+        e = Solver("ctu", "ppm", "hlld", stream=stream)
+        g_lv, e_lv = lvl(U, B, p["dx"]), lvl(U, B, p["dx"])
+        t_g = torch.zeros(1, dtype=torch.float64, device="cuda")
+        t_e = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for rep in range(4):
+            s.advance_graph(g_lv, t_dev=t_g)
+            e.advance(e_lv, t_dev=t_e)
+            stream.synchronize()
+            # eager work between replays
+            assert torch.equal(g_lv.U, e_lv.U) and torch.equal(g_lv.B, e_lv.B), rep
+            assert t_g.item() == t_e.item()
+
+
+def test_graph_replay_with_device_group_count():
+    stream = torch.cuda.Stream()
+    p = inputs.smooth_problem(48, 32, 32, seed=6)
+    U, B = oracle.initial_state(p)
+    origins = torch.tensor([(0, 0, 0), (16, 16, 16), (32, 0, 16)], dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(stream):
+        s = Solver("vl", "plm", "roe", stream=stream)
+        e = Solver("vl", "plm", "roe", stream=stream)
+        a = lvl(U, B, p["dx"], groups=origins)
+        a.n_groups_dev = torch.tensor([3], dtype=torch.int32, device="cuda")
+        b = lvl(U, B, p["dx"], groups=origins)
+        s.advance_graph(a)
+        e.advance(b)
+        a.n_groups_dev.fill_(2)            # shrink the list without re-capture
+        b.set_groups(origins[:2].contiguous())
+        s.advance_graph(a)
+        e.advance(b)
+        stream.synchronize()
+    assert torch.equal(a.U, b.U) and torch.equal(a.B, b.B)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_prolong_all_and_restrict_match_oracle(prec):
+    p = inputs.smooth_problem(8, 6, 4, seed=7)
+    Uc, Bc = oracle.initial_state(p)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    if prec == "f32":
+        Uc = Uc.astype(np.float32).astype(np.float64)
+        Bc = Bc.astype(np.float32).astype(np.float64)
+    Uf, Bf = oamr.prolong(Uc, Bc)
+    s = Solver("vl", "plm", "roe", prec)
+    c = lvl(Uc, Bc, p["dx"], dtype)
+    f = Level(torch.empty((5, 8, 12, 16), dtype=dtype, device="cuda"),
+              torch.empty((3, 8, 12, 16), dtype=dtype, device="cuda"), p["dx"] / 2)
+    s.prolong(c, f)
+    torch.cuda.synchronize()
+    tol = 1e-14 if prec == "f64" else 2e-6
+    assert np.allclose(f.U.double().cpu().numpy(), Uf, rtol=tol, atol=tol)
+    assert np.allclose(f.B.double().cpu().numpy(), Bf, rtol=tol, atol=tol)
+    c2 = lvl(np.zeros_like(Uc), Bc, p["dx"], dtype)
+    s.restrict(f, c2)
+    torch.cuda.synchronize()
+    assert np.allclose(c2.U.double().cpu().numpy(), oamr.restrict(Uf), rtol=tol, atol=tol)
+
+
+def test_prolong_ghosts_respects_listed_groups():
+    p = inputs.abc_problem(32, 0.05, seed=8)
+    Uc, Bc = oracle.initial_state(p)
+    Uf_all, Bf_all = oamr.prolong(Uc, Bc)
+    s = Solver("ctu", "ppm", "hlld")
+    c = lvl(Uc, Bc, p["dx"])
+    origins = np.array([[16, 16, 16], [32, 16, 16]], dtype=np.int32)
+    sentinel = 7.0
+    f = Level(torch.full((5, 64, 64, 64), sentinel, dtype=torch.float64, device="cuda"),
+              torch.full((3, 64, 64, 64), sentinel, dtype=torch.float64, device="cuda"), p["dx"] / 2,
+              groups=torch.from_numpy(origins).cuda())
+    s.prolong(c, f, halo=4)
+    torch.cuda.synchronize()
+    U, B = f.U.cpu().numpy(), f.B.cpu().numpy()
+    listed = np.zeros((64, 64, 64), bool)
+    for (i, j, k) in origins:
+        listed[k:k + 16, j:j + 16, i:i + 16] = True
+    assert np.all(U[:, listed] == sentinel)                      # listed cells untouched
+    box = np.zeros((64, 64, 64), bool)
+    for (i, j, k) in origins:
+        box[k - 4:k + 21, j - 4:j + 21, i - 4:i + 21] = True
+    ghost = box & ~listed
+    assert np.allclose(U[:, ghost], Uf_all[:, ghost], rtol=1e-14)
+    assert np.all(U[:, ~box] == sentinel)                        # outside the halos untouched
+    # x-faces between a listed cell and a ghost cell keep their value
+    assert B[0, 20, 20, 48] == sentinel and B[0, 20, 20, 16] == sentinel
+
+
+def test_three_level_hierarchy_runs_and_stays_solenoidal():
+    h = Hierarchy(32, [7, 20], prec="f64", noise=0.1, seed=1)
+    assert h.cells_per_level() == [32 ** 3, 7 * 16 ** 3, 20 * 16 ** 3]
+    for _ in range(4):
+        h.step()
+    h.stream.synchronize()
+    for lvl_i, lv in enumerate(h.levels):
+        U = lv.U.cpu().numpy()
+        assert np.all(np.isfinite(U))
+        d = oracle.divb(lv.B.cpu().numpy(), lv.dx)
+        if lvl_i == 0:
+            assert np.abs(d).max() * lv.dx < 1e-12
+        else:
+            mask = np.zeros(d.shape, bool)
+            for (i, j, k) in h.groups[lvl_i - 1]:
+                mask[k:k + 16, j:j + 16, i:i + 16] = True
+            assert np.abs(d[mask]).max() * lv.dx < 1e-12
+
+
+def test_hierarchy_graph_replay_matches_eager():
+    h1 = Hierarchy(32, [5, 9], prec="f32", seed=2)
+    h2 = Hierarchy(32, [5, 9], prec="f32", seed=2)
+    g = h1.capture()
+    h2.step()
+    for rep in range(3):
+        g.replay()
+        h2.step()
+        h1.stream.synchronize()
+        h2.stream.synchronize()
+        for a, b in zip(h1.levels, h2.levels):
+            assert torch.equal(a.U, b.U) and torch.equal(a.B, b.B), rep
+
+
+def test_nested_groups_are_octree_consistent():
+    gs = nested_groups(128, [64, 511], edge=16, seed=3)
+    assert len(gs[0]) == 64 and len(gs[1]) == 511
+    parents = {tuple(x // 16) for x in gs[0]}
+    for x in gs[1]:
+        assert tuple((x // 16) // 2) in parents
+    assert len({tuple(x) for x in gs[1]}) == 511

@@ -1,0 +1,205 @@
+"""GPU tests of the learned interface flux against the FP64 reference with
+the kernels' BF16 rounding points reproduced (oracle/mlp.py).
+
+Bars: normwise relative error <= 1e-3 for forward, backward and an Adam
+step (BF16 operands, FP32 accumulation); learned-flux faces that fall back
+use HLLD to FP32 round-off; with negative thresholds the MLP form
+reproduces the HLLD form bit for bit.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from oracle import mlp as omlp  # noqa: E402
+from paper_1804_03479_amd import inputs  # noqa: E402
+from paper_1804_03479_amd import surrogate  # noqa: E402
+from paper_1804_03479_amd.mhd import Level, MlpOps, Solver  # noqa: E402
+
+
+def nrel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.fixture(scope="module")
+def ops():
+    s = Solver("ctu", "ppm", "mlp", "f32")
+    return MlpOps(s)
+
+
+@pytest.fixture(scope="module")
+def theta():
+    rng = np.random.default_rng(5)
+    return (omlp.init_params(3) + 0.05 * rng.standard_normal(omlp.NPARAM)).astype(np.float32).astype(np.float64)
+
+
+def test_param_count(ops):
+    assert ops.nparam == omlp.NPARAM == 5639
+
+
+@pytest.mark.parametrize("n", [1, 37, 1000])
+def test_forward_matches_oracle(ops, theta, n):
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, 15)).astype(np.float32).astype(np.float64)
+    Y = ops.forward(dev(theta), dev(X)).cpu().numpy()
+    Yo, _ = omlp.forward(theta, X, bf16_ops=True)
+    assert nrel(Y, Yo) <= 1e-3
+
+
+@pytest.mark.parametrize("n", [16, 513])
+def test_backward_matches_oracle(ops, theta, n):
+    rng = np.random.default_rng(100 + n)
+    X = rng.standard_normal((n, 15)).astype(np.float32).astype(np.float64)
+    dY = rng.standard_normal((n, 7)).astype(np.float32).astype(np.float64)
+    G = ops.backward(dev(theta), dev(X), dev(dY)).cpu().numpy()
+    _, cache = omlp.forward(theta, X, bf16_ops=True)
+    Go = omlp.backward(theta, cache, dY, bf16_ops=True)
+    for a, b in zip(omlp.unpack(G), omlp.unpack(Go)):
+        assert nrel(a, b) <= 1e-3
+
+
+def test_train_step_matches_oracle(ops, theta):
+    rng = np.random.default_rng(7)
+    n = 300
+    X = rng.standard_normal((n, 15)).astype(np.float32).astype(np.float64)
+    T = rng.standard_normal((n, 7)).astype(np.float32).astype(np.float64)
+    p = dev(theta)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    g = torch.zeros_like(p)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ops.train_step(p, m, v, g, 1, dev(X), dev(T), 1e-3, loss)
+    lo, go = omlp.mse_grad(theta, X, T, bf16_ops=True)
+    to, _, _ = omlp.adam(theta, np.zeros_like(theta), np.zeros_like(theta), go, 1, 1e-3)
+    assert abs(loss.item() - lo) <= 1e-3 * lo
+    # first Adam step moves every parameter by about lr * sign(g)
+    assert nrel(p.cpu().numpy() - theta, to - theta) <= 2e-2
+    assert nrel(g.cpu().numpy(), go) <= 1e-3
+
+
+def smooth_states(rng, n, jump):
+    wl = np.stack([rng.uniform(0.5, 2, n), rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(-1, 1, n),
+                   rng.uniform(0.5, 2, n), rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)], axis=1)
+    wr = wl * (1 + jump * rng.uniform(-1, 1, (n, 7)))
+    bn = rng.uniform(-1, 1, n)
+    return wl.astype(np.float32).astype(np.float64), wr.astype(np.float32).astype(np.float64), \
+        bn.astype(np.float32).astype(np.float64)
+
+
+def test_face_flux_network_and_fallback(ops, theta):
+    rng = np.random.default_rng(8)
+    n = 700
+    wl, wr, bn = smooth_states(rng, n, 0.5)
+    ops.set_weights(dev(theta))
+    S = np.concatenate([wl, wr, bn[:, None]], axis=1)
+    F, used = ops.face_flux(dev(S))
+    F, used = F.cpu().numpy(), used.cpu().numpy().astype(bool)
+    fall = omlp.fallback(wl, wr)
+    assert np.array_equal(used, fall)
+    assert 0 < fall.sum() < n
+    Fo = omlp.surrogate_flux(theta, wl[~fall], wr[~fall], bn[~fall], bf16_ops=True)
+    assert nrel(F[~fall], Fo) <= 1e-3
+    for i in np.flatnonzero(fall)[:40]:
+        fo, _ = oracle.riemann(oracle.HLLD, wl[i], wr[i], bn[i])
+        assert np.allclose(F[i], fo, rtol=2e-5, atol=2e-5 * np.abs(fo).max())
+
+
+def abc_level(s, n, noise, seed):
+    p = inputs.abc_problem(n, noise, seed=seed)
+    W5 = torch.from_numpy(np.stack([p["rho"], p["vx"], p["vy"], p["vz"], p["p"]]))
+    B = torch.from_numpy(np.stack([p["bx"], p["by"], p["bz"]]))
+    return s.level_from_primitives(W5, B, p["dx"])
+
+
+def test_negative_threshold_equals_hlld_bitwise(theta):
+    # a negative threshold sends every face to HLLD, equal states included
+    a = Solver("ctu", "ppm", "hlld", "f32")
+    b = Solver("ctu", "ppm", "mlp", "f32", mlp_dp=-1.0, mlp_drho=-1.0)
+    MlpOps(b).set_weights(dev(theta))
+    la, lb = abc_level(a, 32, 0.1, 0), abc_level(b, 32, 0.1, 0)
+    b.fallback_count()
+    for _ in range(3):
+        dt = a.cfl_dt(la)
+        a.step(la, dt)
+        b.step(lb, dt)
+    torch.cuda.synchronize()
+    assert b.fallback_count() == 3 * 2 * 3 * 32 ** 3   # every face of both Riemann stages
+    # the same HLLD source inlined into another kernel may contract its
+    # multiply-adds differently: FP32 round-off, not bits
+    Ua, Ub = la.U.double().cpu().numpy(), lb.U.double().cpu().numpy()
+    Ba, Bb = la.B.double().cpu().numpy(), lb.B.double().cpu().numpy()
+    assert nrel(Ub, Ua) <= 1e-6 and nrel(Bb, Ba) <= 1e-6
+
+
+def test_prepare_matches_oracle_features_and_targets(ops):
+    samples = surrogate.capture(n=16, steps=1, noise=0.1, seed=2, stride=7, cap=100000)
+    X, T, flags = ops.prepare(samples)
+    S = samples.cpu().numpy().astype(np.float64)
+    wl, wr, bn, F = S[:, :7], S[:, 7:14], S[:, 14], S[:, 15:]
+    fl = flags.cpu().numpy()
+    assert np.array_equal((fl & 1) != 0, omlp.fallback(wl, wr))
+    assert np.array_equal((fl & 2) != 0, omlp.jump_size(wl, wr) < 1e-4)
+    Xo = omlp.features(wl, wr, bn)
+    assert np.allclose(X.cpu().numpy(), Xo, rtol=1e-5, atol=1e-5)
+    ok = (fl & 2) == 0
+    To = omlp.targets(wl[ok], wr[ok], bn[ok], F[ok])
+    # the float flux difference loses ~ulp(|F|) / (s * scale): bound per entry
+    cn = np.abs(omlp.central_flux(wl[ok], wr[ok], bn[ok]) / omlp.flux_scales(wl[ok], wr[ok]))
+    bound = 1e-6 * (1.0 + cn) / omlp.jump_size(wl[ok], wr[ok])[:, None] + 1e-5
+    assert np.all(np.abs(T.cpu().numpy()[ok] - To) <= bound)
+
+
+def test_capture_records_hlld_faces():
+    samples = surrogate.capture(n=16, steps=1, noise=0.1, seed=1, stride=5, cap=100000)
+    nfaces = 2 * 3 * 16 ** 3                    # both Riemann stages of one step
+    assert samples.shape[0] == len(range(0, 3 * 16 ** 3, 5)) * 2 or samples.shape[0] <= nfaces
+    S = samples.cpu().numpy().astype(np.float64)
+    for r in S[:: max(1, len(S) // 30)]:
+        fo, _ = oracle.riemann(oracle.HLLD, r[:7], r[7:14], r[14])
+        assert np.allclose(r[15:], fo, rtol=2e-5, atol=2e-5 * np.abs(fo).max())
+
+
+def run_pair(a, b, n, steps):
+    la, lb = abc_level(a, n, 0.1, 0), abc_level(b, n, 0.1, 0)
+    for _ in range(steps):
+        dt = a.cfl_dt(la)
+        a.step(la, dt)
+        b.step(lb, dt)
+    torch.cuda.synchronize()
+    Ua, Ub = la.U.double().cpu().numpy(), lb.U.double().cpu().numpy()
+    return [float(np.abs(Ub[m] - Ua[m]).mean() / np.abs(Ua[m]).mean()) for m in range(5)], lb
+
+
+def test_trained_network_gain():
+    """The trained surrogate against the pure-HLLD run after 10 steps of the
+    32^3 ABC box.  Bar: in every conserved component the L1 distance to HLLD
+    is at most a fifth of the distance between the Roe and HLLD runs (two
+    valid solvers of the paper); the fallback fraction and CT's div B are
+    reported and checked."""
+    samples = surrogate.capture(n=32, steps=6, noise=0.1, seed=3, stride=1, cap=2_000_000)
+    s = Solver("ctu", "ppm", "mlp", "f32")
+    ops = MlpOps(s)
+    X, T, info = surrogate.training_set(ops, samples, 2_000_000, seed=0)
+    params, hist = surrogate.train(ops, X, T, epochs=60, batch=4096, lr0=3e-3, seed=0)
+    assert hist[-1]["val_loss"] < 0.2 * hist[0]["val_loss"]
+    ops.set_weights(params)
+    s.fallback_count()
+    l1_mlp, lm = run_pair(Solver("ctu", "ppm", "hlld", "f32"), s, 32, 10)
+    frac = s.fallback_count() / (10 * 2 * 3 * 32 ** 3)
+    l1_roe, _ = run_pair(Solver("ctu", "ppm", "hlld", "f32"), Solver("ctu", "ppm", "roe", "f32"), 32, 10)
+    print(f"\nsurrogate: val_loss {hist[-1]['val_loss']:.3e}, fallback fraction {frac:.4f}\n"
+          f"  L1 vs HLLD after 10 steps (rho, Mx, My, Mz, E): {['%.2e' % x for x in l1_mlp]}\n"
+          f"  Roe vs HLLD:                                    {['%.2e' % x for x in l1_roe]}")
+    for a, b in zip(l1_mlp, l1_roe):
+        assert a <= 0.2 * b
+    mx, _ = s.divb(lm)
+    assert mx * lm.dx <= 1e-5          # CT keeps div B at round-off with any flux
