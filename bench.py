@@ -8,9 +8,20 @@ CTU + PPM + HLLD + CT, Courant 1/2 (summed over directions), gamma = 5/3,
 timed in FP64 and FP32 side by side.  One step = CFL reduction + full update
 (mhd_advance), state resident in HBM.  The headline value is the FP32 form.
 
-Also timed: the paper's own benchmark scheme (VL + PLM + Roe + CT, noise
-0.01), for which the paper quotes 1.2e8 (FP32) and 5.5e7 (FP64)
-cell-updates/s on one Tesla P100 (Sec. 4.2(i)).
+Also timed, under "forms":
+  * the FP32 form with double energy and low-beta double pressure recovery
+    (f32_mixed), and the L1 distance of the FP32 and mixed forms from the
+    FP64 form after --l1-steps steps;
+  * the paper's own benchmark scheme (VL + PLM + Roe + CT, noise 0.01), for
+    which the paper quotes 1.2e8 (FP32) and 5.5e7 (FP64) cell-updates/s on
+    one Tesla P100 (Sec. 4.2(i));
+  * the learned-flux form: a surrogate trained here on the GPU from captured
+    interfaces, timed on the same box, with its L1 distance from the pure-HLLD
+    run after --mlp-l1-steps steps (and the Roe run's, for scale), the HLLD
+    fallback fraction and the MFMA rate of its flux stage;
+  * the batched AMR form: the 128^3 root plus two refined levels of uneven
+    group counts, shared dt, ghost refill, update and restriction of all
+    levels replayed from one HIP graph, launch shapes autotuned per level.
 
 Prints one JSON line.
 """
@@ -28,6 +39,8 @@ sys.path.insert(0, ROOT)
 PAPER_F32 = 1.2e8   # cell-updates/s, Tesla P100, VL+PLM+Roe, FP32 (paper Sec. 4.2(i))
 PAPER_F64 = 5.5e7   # same, FP64
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK = 2500.0                          # TFLOP/s, dense BF16
+MLP_FLOP_PER_FACE = 2 * (15 * 64 + 64 * 64 + 64 * 7)   # one 15-64-64-7 inference
 
 # Algorithmic words per cell of each stage kernel: every array element the
 # stage must read or write, counted once (neighbour re-reads excluded).
@@ -55,21 +68,30 @@ WORKLOADS = {
 }
 
 
-def run_form(wl: dict, prec: str, n: int, steps: int, warmup: int, seed: int, profile: bool):
+def abc_level(s, n: int, noise: float, seed: int):
     import numpy as np
     import torch
     from paper_1804_03479_amd import inputs
-    from paper_1804_03479_amd.mhd import Solver
-    p = inputs.abc_problem(n, wl["noise"], seed=seed)
-    s = Solver(wl["scheme"], wl["recon"], wl["riemann"], prec)
+    p = inputs.abc_problem(n, noise, seed=seed)
     W5 = torch.from_numpy(np.stack([p["rho"], p["vx"], p["vy"], p["vz"], p["p"]]))
     B = torch.from_numpy(np.stack([p["bx"], p["by"], p["bz"]]))
-    lv = s.level_from_primitives(W5, B, p["dx"])
+    return s.level_from_primitives(W5, B, p["dx"]), p["dx"]
+
+
+def run_form(wl: dict, prec: str, n: int, steps: int, warmup: int, seed: int, profile: bool,
+             riemann: str | None = None, setup=None):
+    import torch
+    from paper_1804_03479_amd.mhd import Solver
+    s = Solver(wl["scheme"], wl["recon"], riemann or wl["riemann"], prec)
+    if setup is not None:
+        setup(s)
+    lv, dx = abc_level(s, n, wl["noise"], seed)
     t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         s.advance(lv, t_dev=t_dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+    s.fallback_count()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -81,12 +103,125 @@ def run_form(wl: dict, prec: str, n: int, steps: int, warmup: int, seed: int, pr
     s.sync()
     cells = n ** 3
     out = dict(ms_per_step=ms / steps, value=cells * steps / (ms * 1e-3))
+    if (riemann or wl["riemann"]) in ("roe", "mlp"):
+        out["fallback_faces_per_step"] = s.fallback_count() / steps
     if profile:
         out["stages"] = s.profile_step(lv, nrep=5)
     mx, _ = s.divb(lv)
-    out["max_divb_dx"] = mx * p["dx"]
+    out["max_divb_dx"] = mx * dx
     s.close()
     return out
+
+
+def l1_gpu_pair(wl: dict, n: int, seed: int, nsteps: int, ref: tuple, test: tuple, setup=None):
+    """Relative L1 (rho, e, B) of form `test` against form `ref` (each a
+    (prec, riemann) pair) after nsteps in lockstep on the GPU, both taking the
+    reference's time step."""
+    import numpy as np
+    import torch
+    from paper_1804_03479_amd.mhd import Solver
+    a = Solver(wl["scheme"], wl["recon"], ref[1], ref[0])
+    b = Solver(wl["scheme"], wl["recon"], test[1], test[0])
+    if setup is not None:
+        setup(b)
+    la, dx = abc_level(a, n, wl["noise"], seed)
+    lb, _ = abc_level(b, n, wl["noise"], seed)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    b.fallback_count()
+    for _ in range(nsteps):
+        a.cfl_dt_device(la, dt)
+        a.step_devdt(la, dt)
+        b.step_devdt(lb, dt)
+    torch.cuda.synchronize()
+    nfb = b.fallback_count()
+    Ua, Ub = la.U.double().cpu().numpy(), lb.U.double().cpu().numpy()
+    if lb.E64 is not None:
+        Ub[4] = lb.E64.cpu().numpy()
+    Ba, Bb = la.B.double().cpu().numpy(), lb.B.double().cpu().numpy()
+    mx, _ = b.divb(lb)
+    out = {"steps": nsteps, "vs": f"{ref[1]} {ref[0]}",
+           "rho": float(np.abs(Ub[0] - Ua[0]).mean() / np.abs(Ua[0]).mean()),
+           "e": float(np.abs(Ub[4] - Ua[4]).mean() / np.abs(Ua[4]).mean()),
+           "B": float(np.abs(Bb - Ba).mean() / np.abs(Ba).mean()),
+           "M": float(np.abs(Ub[1:4] - Ua[1:4]).mean() / np.abs(Ua[1:4]).mean()),
+           "max_divb_dx": mx * dx, "fallback_faces": nfb}
+    a.close()
+    b.close()
+    return out
+
+
+def train_surrogate(n_capture: int, seed: int, n_samples: int, epochs: int):
+    """Interface samples from CTU+PPM+HLLD runs of the ABC box, then Adam on
+    the GPU (the library's own forward/backward kernels); returns weights."""
+    import time as _t
+    import torch
+    from paper_1804_03479_amd import surrogate
+    from paper_1804_03479_amd.mhd import MlpOps, Solver
+    t0 = _t.perf_counter()
+    stride = max(1, (6 * n_capture ** 3 * 4) // (2 * n_samples))
+    samples = surrogate.capture(n=n_capture, steps=4, noise=0.1, seed=seed + 1, stride=stride,
+                                cap=2 * n_samples)
+    s = Solver("ctu", "ppm", "mlp", "f32")
+    ops = MlpOps(s)
+    X, T, info = surrogate.training_set(ops, samples, n_samples, seed=seed)
+    params, hist = surrogate.train(ops, X, T, epochs=epochs, batch=4096, lr0=3e-3, seed=seed)
+    torch.cuda.synchronize()
+    s.close()
+    return params, {"samples": n_samples, "captured": int(samples.shape[0]), "epochs": epochs,
+                    "val_loss": hist[-1]["val_loss"], "val_loss_first_epoch": hist[0]["val_loss"],
+                    "seconds": round(_t.perf_counter() - t0, 2), "mix": info}
+
+
+def run_amr(n_root: int, counts, steps: int, warmup: int, seed: int, tune: bool):
+    """Root + refined levels, shared dt, ghost refill, update, restriction,
+    all levels of a step replayed from one HIP graph."""
+    import gc
+    import torch
+    from paper_1804_03479_amd import autotune
+    from paper_1804_03479_amd.amr import Hierarchy
+    tuned = None
+    if tune:
+        h = Hierarchy(n_root, counts, prec="f32", seed=seed)
+        tuned = autotune.tune(h, reps=3)
+        h.close()
+        del h
+        gc.collect()
+        torch.cuda.empty_cache()
+    h = Hierarchy(n_root, counts, prec="f32", seed=seed)
+    if tuned:
+        h.set_launch(tuned["shapes"])
+    st = h.stream
+    cells = h.cells_per_level()
+
+    def timed(fn, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(k):
+            fn()
+        e1.record(st)
+        st.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    for _ in range(warmup):
+        h.step()
+    ms_eager = timed(h.step, steps)
+    g = h.capture()
+    for _ in range(warmup):
+        h.replay(g)
+    ms_graph = timed(lambda: h.replay(g), steps)
+    per_level = [autotune.time_level(h, lvl, reps=3) for lvl in range(len(h.levels))]
+    divb = []
+    for sv, lv in zip(h.solvers, h.levels):
+        mx, _ = sv.divb(lv)
+        divb.append(mx * lv.dx)
+    h.close()
+    return {"counts": list(counts), "cells_per_level": cells, "ms_per_step_graph": ms_graph,
+            "ms_per_step_eager": ms_eager, "value": sum(cells) / (ms_graph * 1e-3),
+            "per_level_ms": per_level,
+            "per_level_value": [c / (t * 1e-3) for c, t in zip(cells, per_level)],
+            "launch_blocks_per_cu": None if not tuned else tuned["shapes"],
+            "autotune_ms": None if not tuned else tuned["ms"], "candidates": autotune.CANDIDATES,
+            "max_divb_dx_listed": divb}
 
 
 def l1_vs_oracle(wl: dict, n: int, seed: int, nsteps: int, precs):
@@ -113,12 +248,15 @@ def l1_vs_oracle(wl: dict, n: int, seed: int, nsteps: int, precs):
     for prec in precs:
         dtype = torch.float64 if prec == "f64" else torch.float32
         s = Solver(wl["scheme"], wl["recon"], wl["riemann"], prec)
+        E64 = torch.from_numpy(U[4].copy()).to("cuda") if prec == "f32_mixed" else None
         lv = Level(torch.from_numpy(U).to("cuda", dtype).contiguous(),
-                   torch.from_numpy(B).to("cuda", dtype).contiguous(), dx)
+                   torch.from_numpy(B).to("cuda", dtype).contiguous(), dx, E64=E64)
         for _ in range(nsteps):
             s.advance(lv)
         torch.cuda.synchronize()
         Ug, Bg = lv.U.double().cpu().numpy(), lv.B.double().cpu().numpy()
+        if E64 is not None:
+            Ug[4] = E64.cpu().numpy()
         out[prec] = {
             "steps": nsteps,
             "rho": float(np.abs(Ug[0] - Uo[0]).mean() / np.abs(Uo[0]).mean()),
@@ -165,7 +303,15 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain device-to-device copy run first (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["ctu", "vl"], default=None, help="time one workload only")
+    ap.add_argument("--only", choices=["ctu", "vl", "mlp", "amr"], default=None, help="time one workload only")
+    ap.add_argument("--l1-steps", type=int, default=200,
+                    help="steps of the FP32 / mixed forms against the FP64 form (precision form)")
+    ap.add_argument("--mlp-l1-steps", type=int, default=500, help="steps of the MLP form against pure HLLD")
+    ap.add_argument("--mlp-samples", type=int, default=2_000_000)
+    ap.add_argument("--mlp-epochs", type=int, default=60)
+    ap.add_argument("--amr-counts", default="511,1024",
+                    help="patch groups (16^3 cells) of each refined level; also runs 7,64")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -187,38 +333,81 @@ def main():
         del src, dst
     n = args.n
     cells = n ** 3
+    todo = ["ctu", "vl", "mlp", "amr"] if args.only is None else [args.only]
     results = {}
-    for key in (["ctu", "vl"] if args.only is None else [args.only]):
-        wl = WORKLOADS[key]
-        results[key] = {prec: run_form(wl, prec, n, args.steps, args.warmup, args.seed, profile=(prec == "f32"))
-                        for prec in ("f64", "f32")}
-    head_key = "ctu" if "ctu" in results else "vl"
-    head = results[head_key]["f32"]
-    words = CTU_WORDS if head_key == "ctu" else STAGE_WORDS
-    roofline = roofline_of(head["stages"], words, 4, cells, WORKLOADS[head_key]["name"].format(n=n))
+    forms = {}
+    if "ctu" in todo:
+        precs = ("f64", "f32", "f32_mixed")
+        results["ctu"] = {prec: run_form(WORKLOADS["ctu"], prec, n, args.steps, args.warmup, args.seed,
+                                         profile=(prec == "f32")) for prec in precs}
+    if "vl" in todo:
+        results["vl"] = {prec: run_form(WORKLOADS["vl"], prec, n, args.steps, args.warmup, args.seed,
+                                        profile=(prec == "f32")) for prec in ("f64", "f32")}
+    head_key = "ctu" if "ctu" in results else ("vl" if "vl" in results else None)
 
     cpu = None
     l1 = {}
-    if not args.no_cpu:
+    if not args.no_cpu and head_key is not None:
         import oracle
         wl = WORKLOADS[head_key]
-        l1[head_key], t_cpu = l1_vs_oracle(wl, n, args.seed, args.cpu_steps, ("f64", "f32"))
+        precs = ("f64", "f32", "f32_mixed") if head_key == "ctu" else ("f64", "f32")
+        l1[head_key], t_cpu = l1_vs_oracle(wl, n, args.seed, args.cpu_steps, precs)
         cpu = {"value": cells * args.cpu_steps / t_cpu, "unit": "cell-updates/s", "cores": oracle.get_threads(),
                "kind": "oracle",
                "sample": f"{n}^3 ABC box, {wl['label']} FP64, {args.cpu_steps} steps incl. CFL"}
 
-    forms = {}
     for key, r in results.items():
         wl = WORKLOADS[key]
         for prec, v in r.items():
             e = {"workload": wl["name"].format(n=n), "value": v["value"], "ms_per_step": v["ms_per_step"],
                  "max_divb_dx": v["max_divb_dx"], "l1_vs_oracle": l1.get(key, {}).get(prec)}
+            if "fallback_faces_per_step" in v:
+                e["fallback_faces_per_step"] = v["fallback_faces_per_step"]
             if key == "vl":
                 e["vs_paper"] = v["value"] / (PAPER_F32 if prec == "f32" else PAPER_F64)
+            if key == "ctu" and prec != "f64" and args.l1_steps > 0:
+                e["l1_vs_f64_form"] = l1_gpu_pair(wl, n, args.seed, args.l1_steps, ("f64", "hlld"), (prec, "hlld"))
             forms[f"{key}_{prec}"] = e
         if key != head_key and "stages" in r["f32"]:
             forms[f"{key}_f32"]["stage_ms"] = {k: round(x, 4) for k, x in r["f32"]["stages"].items()}
 
+    if "mlp" in todo:
+        from paper_1804_03479_amd.mhd import MlpOps
+        params, tinfo = train_surrogate(n, args.seed, args.mlp_samples, args.mlp_epochs)
+        setup = lambda s: MlpOps(s).set_weights(params)  # noqa: E731
+        wl = WORKLOADS["ctu"]
+        r = run_form(wl, "f32", n, args.steps, args.warmup, args.seed, profile=True, riemann="mlp", setup=setup)
+        e = {"workload": f"abc{n}_ctu_ppm_mlp_hlld_fallback_ct", "value": r["value"], "ms_per_step": r["ms_per_step"],
+             "max_divb_dx": r["max_divb_dx"], "fallback_faces_per_step": r["fallback_faces_per_step"],
+             "fallback_fraction": r["fallback_faces_per_step"] / (6 * cells), "training": tinfo,
+             "stage_ms": {k: round(x, 4) for k, x in r["stages"].items()}}
+        if args.mlp_l1_steps > 0:
+            e["l1_vs_hlld"] = l1_gpu_pair(wl, n, args.seed, args.mlp_l1_steps, ("f32", "hlld"), ("f32", "mlp"),
+                                          setup=setup)
+            e["l1_roe_vs_hlld"] = l1_gpu_pair(wl, n, args.seed, args.mlp_l1_steps, ("f32", "hlld"), ("f32", "roe"))
+        if "ctu" in results:
+            e["speed_vs_hlld_f32"] = r["value"] / results["ctu"]["f32"]["value"]
+        # the network's MFMA work in the predictor flux stage: 3 faces per cell
+        t_flux = r["stages"]["flux_predict"] * 1e-3
+        flops = 3 * cells * MLP_FLOP_PER_FACE
+        e["mfma"] = {"kernel": "flux_predict", "achieved": round(flops / t_flux / 1e12, 2), "peak": MFMA_BF16_PEAK,
+                     "unit": "TFLOP/s", "frac": round(flops / t_flux / 1e12 / MFMA_BF16_PEAK, 5),
+                     "flop_per_face": MLP_FLOP_PER_FACE}
+        forms["ctu_f32_mlp"] = e
+
+    if "amr" in todo:
+        counts = [int(x) for x in args.amr_counts.split(",")]
+        for cs in (counts, [7, 64]):
+            r = run_amr(n, cs, args.steps, args.warmup, args.seed, tune=not args.no_tune)
+            r["workload"] = f"abc{n}_root_plus_{len(cs)}_levels_ctu_ppm_hlld_ct_f32"
+            forms["amr_f32_" + "_".join(map(str, cs))] = r
+
+    if head_key is None:
+        print(json.dumps({"forms": forms}))
+        return
+    head = results[head_key]["f32"]
+    words = CTU_WORDS if head_key == "ctu" else STAGE_WORDS
+    roofline = roofline_of(head["stages"], words, 4, cells, WORKLOADS[head_key]["name"].format(n=n))
     wl = WORKLOADS[head_key]
     line = {
         "metric": "cell-updates/s/GPU: FP64 vs FP32 vs MLP-flux at fixed L1 err; HBM GB/s",

@@ -47,28 +47,37 @@ def nested_groups(n_root: int, counts, edge: int = 16, seed: int = 0):
 
 
 class Hierarchy:
+    """Root level plus refined levels, one libmhd context per level (each level
+    keeps its own launch shape and scratch), all on one stream."""
+
     def __init__(self, n_root: int, counts, scheme="ctu", recon="ppm", riemann="hlld", prec="f32",
                  noise: float = 0.1, seed: int = 0, edge: int = 16, stream: torch.cuda.Stream | None = None):
         self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.groups = nested_groups(n_root, counts, edge, seed)
         with torch.cuda.stream(self.stream):
-            self.s = Solver(scheme, recon, riemann, prec, stream=self.stream)
+            self.solvers = [Solver(scheme, recon, riemann, prec, stream=self.stream)
+                            for _ in range(len(self.groups) + 1)]
+            s0 = self.solvers[0]
             p = inputs.abc_problem(n_root, noise, seed=seed)
             W5 = torch.from_numpy(np.stack([p["rho"], p["vx"], p["vy"], p["vz"], p["p"]]))
             B = torch.from_numpy(np.stack([p["bx"], p["by"], p["bz"]]))
-            root = self.s.level_from_primitives(W5, B, p["dx"])
+            root = s0.level_from_primitives(W5, B, p["dx"])
             self.levels = [root]
-            self.groups = nested_groups(n_root, counts, edge, seed)
             for lvl, g in enumerate(self.groups, start=1):
                 n = n_root << lvl
-                U = torch.empty((5, n, n, n), dtype=self.s.dtype, device="cuda")
-                Bf = torch.empty((3, n, n, n), dtype=self.s.dtype, device="cuda")
+                U = torch.empty((5, n, n, n), dtype=s0.dtype, device="cuda")
+                Bf = torch.empty((3, n, n, n), dtype=s0.dtype, device="cuda")
                 fine = Level(U, Bf, p["dx"] / (1 << lvl))
-                self.s.prolong(self.levels[-1], fine)          # whole level, initial data
+                self.solvers[lvl].prolong(self.levels[-1], fine)     # whole level, initial data
                 fine.set_groups(torch.from_numpy(g).cuda())
                 fine.group_edge = edge
                 self.levels.append(fine)
             self.dt = torch.zeros(1, dtype=torch.float64, device="cuda")
         self.stream.synchronize()
+
+    @property
+    def s(self):
+        return self.solvers[0]
 
     def cells_per_level(self):
         out = [int(np.prod(self.levels[0].shape))]
@@ -76,25 +85,49 @@ class Hierarchy:
             out.append(len(g) * lv.group_edge ** 3)
         return out
 
-    def step(self):
-        """One shared-dt step of all levels (asynchronous on self.stream)."""
-        s = self.s
+    def set_launch(self, shapes):
+        """Blocks per CU of each level's persistent launches (0 = one item per thread)."""
+        for s, b in zip(self.solvers, shapes):
+            s.set_launch(int(b))
+
+    def shared_dt(self):
         with torch.cuda.stream(self.stream):
             self.dt.fill_(float("inf"))
-            for lv in self.levels:
+            for s, lv in zip(self.solvers, self.levels):
                 s.cfl_dt_min(lv, self.dt)
-            for lvl, lv in enumerate(self.levels):
-                if lvl > 0:
-                    s.prolong(self.levels[lvl - 1], lv, halo=4)
-                s.step_devdt(lv, self.dt)
+
+    def update_level(self, lvl: int):
+        """Ghost refill from the parent (refined levels) and the update of level lvl."""
+        s, lv = self.solvers[lvl], self.levels[lvl]
+        if lvl > 0:
+            s.prolong(self.levels[lvl - 1], lv, halo=4)
+        s.step_devdt(lv, self.dt)
+
+    def step(self):
+        """One shared-dt step of all levels (asynchronous on self.stream)."""
+        with torch.cuda.stream(self.stream):
+            self.shared_dt()
+            for lvl in range(len(self.levels)):
+                self.update_level(lvl)
             for lvl in range(len(self.levels) - 1, 0, -1):
-                s.restrict(self.levels[lvl], self.levels[lvl - 1])
+                self.solvers[lvl].restrict(self.levels[lvl], self.levels[lvl - 1])
 
     def capture(self):
-        """Capture one step() into a CUDA/HIP graph; returns it."""
+        """Capture one step() into a HIP graph (torch.cuda.CUDAGraph); returns it.
+        Replay it with replay(), which launches it on the hierarchy's stream."""
         self.step()                       # allocations and first-use set-up happen eagerly
         self.stream.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=self.stream):
             self.step()
         return g
+
+    def replay(self, g):
+        """One replay of a captured step, ordered on the hierarchy's stream
+        (CUDAGraph.replay launches on the current stream)."""
+        with torch.cuda.stream(self.stream):
+            g.replay()
+
+    def close(self):
+        for s in self.solvers:
+            s.close()

@@ -39,6 +39,7 @@ struct mhd_ctx_s {
   void* QL;               // CTU: 21 * cap, states below each face
   void* QR;               // CTU: 21 * cap, states above each face
   void* F2;               // CTU: 21 * cap, corrector fluxes
+  void* Qc;               // learned flux: 14 * cap, corrected states of one direction
   double* parts;          // reduction partials
   double* dres;           // 8 device doubles of reduction results
   unsigned long long* smax;
@@ -107,7 +108,7 @@ int check_level(const mhd_ctx_s* ctx, const mhd_level* lv) {
   } while (0)
 
 void free_scratch(mhd_ctx_s* c) {
-  void** bufs[] = {&c->W, &c->Bh, &c->F, &c->E, &c->QL, &c->QR, &c->F2};
+  void** bufs[] = {&c->W, &c->Bh, &c->F, &c->E, &c->QL, &c->QR, &c->F2, &c->Qc};
   for (void** b : bufs) {
     hipFree(*b);
     *b = nullptr;
@@ -124,6 +125,7 @@ int ensure_capacity(mhd_ctx_s* c, long long cells) {
   if (ok && c->cfg.scheme == MHD_CTU)
     ok = hipMalloc(&c->QL, 21 * cells * e) == hipSuccess && hipMalloc(&c->QR, 21 * cells * e) == hipSuccess &&
          hipMalloc(&c->F2, 21 * cells * e) == hipSuccess;
+  if (ok && c->cfg.riemann == MHD_MLP) ok = hipMalloc(&c->Qc, 14 * cells * e) == hipSuccess;
   if (!ok) {
     free_scratch(c);
     return MHD_ERR_OUT_OF_MEMORY;
@@ -300,19 +302,29 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
   mark(2);
   constexpr bool kMlp = S == 3 && std::is_same<T, float>::value;
   const float dp = (float)c->cfg.mlp_dp, drho = (float)c->cfg.mlp_drho;
-  if constexpr (kMlp)
-    k_flux_q_mlp<<<sblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb);
-  else
+  if constexpr (kMlp) {
+    const unsigned nb = sblocks(wf1);
+    const long long n7 = 7LL * wf1.N;
+    k_flux_dir_mlp<0><<<nb, kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb);
+    k_flux_dir_mlp<1><<<nb, kBlock, 0, st>>>(wf1, QL + n7, QR + n7, B, F1, gam, c->mlpw, dp, drho, c->nfb);
+    k_flux_dir_mlp<2><<<nb, kBlock, 0, st>>>(wf1, QL + 2 * n7, QR + 2 * n7, B, F1, gam, c->mlpw, dp, drho, c->nfb);
+  } else
     k_flux_q<T, S><<<sblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->nfb, c->capture);
   mark(3);
   k_emf<T><<<sblocks(we1), kBlock, 0, st>>>(we1, F1, W, E);
   mark(4);
   k_half<T, MIX><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F1, E, dts, inv_dx, gam, W, Bh);
   mark(5);
-  if constexpr (kMlp)
-    k_ctu_correct_mlp<<<sblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->mlpw, dp,
-                                                       drho, c->nfb);
-  else
+  if constexpr (kMlp) {
+    float* Qc = (float*)c->Qc;
+    const unsigned nb = sblocks(wf2);
+    k_ctu_correct_dir<0><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
+    k_flux_dir_mlp<0><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.N, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
+    k_ctu_correct_dir<1><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
+    k_flux_dir_mlp<1><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.N, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
+    k_ctu_correct_dir<2><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
+    k_flux_dir_mlp<2><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.N, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
+  } else
     k_ctu_correct<T, S><<<sblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->nfb,
                                                          c->capture);
   mark(6);

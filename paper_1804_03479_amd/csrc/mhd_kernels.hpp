@@ -607,43 +607,6 @@ __global__ void __launch_bounds__(kBlock) k_flux_q(Work w, const T* __restrict__
   if (SOLVER == 0) block_count_atomic(fb, nfb);
 }
 
-// Step 2 with the learned flux (HLLD at strong jumps); counts HLLD faces
-__global__ void __launch_bounds__(kBlock) k_flux_q_mlp(Work w, const float* __restrict__ QL,
-                                                       const float* __restrict__ QR, const float* __restrict__ B,
-                                                       float* __restrict__ F, float gam, const MlpWeights* mw,
-                                                       float dp, float drho, unsigned long long* nfb) {
-  __shared__ MlpShared sh;
-  mlp_load_weights(sh, mw);
-  const long long N = w.N;
-  const long long nitems = work_items(w);
-  int fb = 0;
-  // block-uniform trips: the network uses block barriers
-  for (long long base = block_linear_id() - threadIdx.x; base < nitems; base += item_stride()) {
-    const long long t = base + threadIdx.x;
-    const bool active = t < nitems;
-    int i = 0, j = 0, k = 0;
-    if (active) cell_of(w, t, i, j, k);
-    const long long p = active ? lin(w, i, j, k) : 0;
-    for (int d = 0; d < 3; ++d) {
-      float wl[7], wr[7], f[7];
-      float bn = 1.0f;
-#pragma unroll
-      for (int m = 0; m < 7; ++m) {
-        wl[m] = active ? QL[((long long)d * 7 + m) * N + p] : 1.0f;
-        wr[m] = active ? QR[((long long)d * 7 + m) * N + p] : 1.0f;
-      }
-      if (active) bn = B[d * N + p];
-      fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
-      if (active) {
-        if (d == 0) store_flux<float, 0>(F, N, p, f);
-        else if (d == 1) store_flux<float, 1>(F, N, p, f);
-        else store_flux<float, 2>(F, N, p, f);
-      }
-    }
-  }
-  block_count_atomic(fb, nfb);
-}
-
 // Step 5: transverse correction of a state of direction D that comes from
 // cell (ci, cj, ck) and sits on a face with time-n normal field bn.  Hydro
 // variables: minus dt/2 times the transverse flux differences of step 2 in
@@ -754,44 +717,61 @@ __global__ void __launch_bounds__(kBlock) k_ctu_correct(Work w, const T* __restr
   if (SOLVER == 0) block_count_atomic(fb, nfb);
 }
 
-// Steps 5-6 with the learned flux (HLLD at strong jumps); counts HLLD faces
-__global__ void __launch_bounds__(kBlock) k_ctu_correct_mlp(Work w, const float* __restrict__ QL,
+// Learned-flux form of steps 5-6, one direction D per launch pair: the
+// corrected states of the D-faces go to Qc (14 words per cell: L then R),
+// then the network (or HLLD at strong jumps) turns them into fluxes.  Split
+// so that neither kernel holds the correction and the network at once.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_ctu_correct_dir(Work w, const float* __restrict__ QL,
                                                             const float* __restrict__ QR, const float* __restrict__ F1,
                                                             const float* __restrict__ E1, const float* __restrict__ B,
-                                                            const float* __restrict__ Bh, float* __restrict__ F2,
-                                                            DtSrc dts, float inv_dx, float gam, const MlpWeights* mw,
-                                                            float dp, float drho, unsigned long long* nfb) {
+                                                            float* __restrict__ Qc, DtSrc dts, float inv_dx,
+                                                            float gam) {
+  const float hr = float(0.5 * get_dt(dts)) * inv_dx;
+  const long long N = w.N;
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
+    const long long p = lin(w, i, j, k);
+    float wl[7], wr[7];
+    corrected_states<float, D>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      Qc[(long long)m * N + p] = wl[m];
+      Qc[(long long)(7 + m) * N + p] = wr[m];
+    }
+  }
+}
+
+// Learned flux (HLLD at strong jumps) of the D-faces from states
+// L[m * N + p], R[m * N + p] (m = 0..6) and normal field Bn[D * N + p].
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __restrict__ L,
+                                                         const float* __restrict__ R, const float* __restrict__ Bn,
+                                                         float* __restrict__ F, float gam, const MlpWeights* mw,
+                                                         float dp, float drho, unsigned long long* nfb) {
   __shared__ MlpShared sh;
   mlp_load_weights(sh, mw);
   const long long N = w.N;
-  const float hr = float(0.5 * get_dt(dts)) * inv_dx;
   const long long nitems = work_items(w);
   int fb = 0;
+  // block-uniform trips: every lane of a wave takes part in the network
   for (long long base = block_linear_id() - threadIdx.x; base < nitems; base += item_stride()) {
-  const long long t = base + threadIdx.x;
-  const bool active = t < nitems;
-  int i = 0, j = 0, k = 0;
-  if (active) cell_of(w, t, i, j, k);
-  const long long p = active ? lin(w, i, j, k) : 0;
-  for (int d = 0; d < 3; ++d) {
+    const long long t = base + threadIdx.x;
+    const bool active = t < nitems;
+    int i = 0, j = 0, k = 0;
+    if (active) cell_of(w, t, i, j, k);
+    const long long p = active ? lin(w, i, j, k) : 0;
     float wl[7], wr[7], f[7];
     float bn = 1.0f;
-    if (active) {
-      if (d == 0) corrected_states<float, 0>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
-      else if (d == 1) corrected_states<float, 1>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
-      else corrected_states<float, 2>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
-      bn = Bh[d * N + p];
-    } else {
 #pragma unroll
-      for (int m = 0; m < 7; ++m) wl[m] = wr[m] = 1.0f;
+    for (int m = 0; m < 7; ++m) {
+      wl[m] = active ? L[(long long)m * N + p] : 1.0f;
+      wr[m] = active ? R[(long long)m * N + p] : 1.0f;
     }
+    if (active) bn = Bn[D * N + p];
     fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
-    if (active) {
-      if (d == 0) store_flux<float, 0>(F2, N, p, f);
-      else if (d == 1) store_flux<float, 1>(F2, N, p, f);
-      else store_flux<float, 2>(F2, N, p, f);
-    }
-  }
+    if (active) store_flux<float, D>(F, N, p, f);
   }
   block_count_atomic(fb, nfb);
 }

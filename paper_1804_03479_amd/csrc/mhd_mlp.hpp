@@ -42,14 +42,18 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-__device__ __forceinline__ float gelu(float x) {
-  const float c = 0.7978845608028654f;  // sqrt(2/pi)
-  return 0.5f * x * (1.0f + tanhf(c * (x + 0.044715f * x * x * x)));
+// GELU, tanh form: 0.5 x (1 + tanh u) = x s with s = 1 / (1 + exp(-2u)),
+// u = sqrt(2/pi) (x + 0.044715 x^3); the derivative is
+// s + 2 x s (1 - s) du/dx.
+__device__ __forceinline__ float gelu_u2(float x) {
+  const float c2 = 1.5957691216057308f;  // 2 sqrt(2/pi)
+  return c2 * (x + 0.044715f * x * x * x);
 }
+__device__ __forceinline__ float gelu(float x) { return __fdividef(x, 1.0f + __expf(-gelu_u2(x))); }
 __device__ __forceinline__ float gelu_prime(float x) {
-  const float c = 0.7978845608028654f;
-  const float t = tanhf(c * (x + 0.044715f * x * x * x));
-  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * x * x);
+  const float sg = __fdividef(1.0f, 1.0f + __expf(-gelu_u2(x)));
+  const float du = 0.7978845608028654f * (1.0f + 3.0f * 0.044715f * x * x);
+  return sg + 2.0f * x * sg * (1.0f - sg) * du;
 }
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
@@ -88,20 +92,32 @@ __global__ void __launch_bounds__(256) k_mlp_pack(const float* __restrict__ P, M
   if (t < 16) out->b3[t] = t < kNout ? P[ob3 + t] : 0.0f;
 }
 
-// Shared memory of one 256-thread block for wave-cooperative inference.
+// Per-wave LDS staging of inference: the BF16 features of the wave's 64
+// faces (one row per lane) and the 8 padded outputs of each face.
+struct MlpStage {
+  unsigned short X[64 * 16];
+  float Y[64 * 8];
+};
+// LDS of one 256-thread block: the inference weights and four wave stages.
 struct MlpShared {
   MlpWeights w;
-  unsigned short X[4][16 * 16];   // per wave: one 16-face row tile of features
-  unsigned short H1[4][16 * 64];
-  unsigned short H2[4][16 * 64];
-  float Y[4][16 * 16];
+  MlpStage st[4];
 };
 
+// Block-wide copy of the weights into LDS (a block barrier: every thread of
+// the block calls it once, before any inference).
 __device__ __forceinline__ void mlp_load_weights(MlpShared& sh, const MlpWeights* __restrict__ g) {
-  const unsigned* src = reinterpret_cast<const unsigned*>(g);
-  unsigned* dst = reinterpret_cast<unsigned*>(&sh.w);
-  for (int t = threadIdx.x; t < (int)(sizeof(MlpWeights) / 4); t += blockDim.x) dst[t] = src[t];
+  const uint4* src = reinterpret_cast<const uint4*>(g);
+  uint4* dst = reinterpret_cast<uint4*>(&sh.w);
+  for (int t = threadIdx.x; t < (int)(sizeof(MlpWeights) / 16); t += blockDim.x) dst[t] = src[t];
   __syncthreads();
+}
+
+// ordering of LDS traffic between the lanes of one wave
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Normalised features of one interface (face frame) and the scales the
@@ -138,88 +154,73 @@ __device__ __forceinline__ void mlp_features(const float wl[7], const float wr[7
   osc[4] = sj * p0 * v0; osc[5] = sj * b0 * v0; osc[6] = sj * b0 * v0;
 }
 
-// Network output for the faces of one wave.  Every lane of the block must
-// call this together (it uses block barriers); lanes with use == false pass
-// dummy inputs and ignore y.
+// Network output for the 64 faces of one wave (one face per lane).  All
+// lanes of the wave call this together; lanes without a face pass zeros.
+// The network runs transposed (H^T = W^T X^T): the weights are the A operand
+// (lane (li, lk) reads W^T[16 t + li][16 s + 4 lk + 0..3] from LDS), so the
+// accumulator tile of one layer is already the B operand of the next, and
+// GELU and the BF16 rounding of each hidden layer act on it in registers.
+// Per 16-face tile: 4 + 16 + 4 MFMA 16x16x16.
 __device__ __forceinline__ void mlp_forward_wave(MlpShared& sh, const float x[16], float y[7]) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  unsigned short* X = sh.X[wv];
-  unsigned short* H1 = sh.H1[wv];
-  unsigned short* H2 = sh.H2[wv];
-  float* Y = sh.Y[wv];
-  for (int rt = 0; rt < 4; ++rt) {
-    // the 16 lanes of row tile rt store their features
-    if ((lane >> 4) == rt) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  MlpStage& S = sh.st[threadIdx.x >> 6];
+  const MlpWeights& g = sh.w;
+  {
+    unsigned pk[8];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) X[li * 16 + k] = f2bf(x[k]);
-    }
-    __syncthreads();
-    // layer 1: [16 x 16] . [16 x 64]
-    bf16x4 a;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = (short)X[li * 16 + 4 * lk + q];
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      bf16x4 b;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) b[q] = (short)sh.w.W1t[(16 * ct + li) * 16 + 4 * lk + q];
-      f32x4 c = {0.f, 0.f, 0.f, 0.f};
-      c = mfma16(a, b, c);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = 4 * lk + q, col = 16 * ct + li;
-        H1[row * 64 + col] = f2bf(gelu(c[q] + sh.w.b1[col]));
-      }
-    }
-    __syncthreads();
-    // layer 2: [16 x 64] . [64 x 64]
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        bf16x4 a2, b2;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          a2[q] = (short)H1[li * 64 + 16 * ks + 4 * lk + q];
-          b2[q] = (short)sh.w.W2t[(16 * ct + li) * 64 + 16 * ks + 4 * lk + q];
-        }
-        c = mfma16(a2, b2, c);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = 4 * lk + q, col = 16 * ct + li;
-        H2[row * 64 + col] = f2bf(gelu(c[q] + sh.w.b2[col]));
-      }
-    }
-    __syncthreads();
-    // layer 3: [16 x 64] . [64 x 16]
-    {
-      f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        bf16x4 a3, b3;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          a3[q] = (short)H2[li * 64 + 16 * ks + 4 * lk + q];
-          b3[q] = (short)sh.w.W3t[li * 64 + 16 * ks + 4 * lk + q];
-        }
-        c = mfma16(a3, b3, c);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = 4 * lk + q, col = li;
-        Y[row * 16 + col] = c[q] + sh.w.b3[col];
-      }
-    }
-    __syncthreads();
-    if ((lane >> 4) == rt) {
-#pragma unroll
-      for (int m = 0; m < 7; ++m) y[m] = Y[li * 16 + m];
-    }
-    __syncthreads();
+    for (int m = 0; m < 8; ++m) pk[m] = (unsigned)f2bf(x[2 * m]) | ((unsigned)f2bf(x[2 * m + 1]) << 16);
+    uint4* dst = reinterpret_cast<uint4*>(S.X + lane * 16);
+    dst[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    dst[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
   }
+  wave_sync();
+#pragma unroll 1
+  for (int ft = 0; ft < 4; ++ft) {
+    const bf16x4 xf = *reinterpret_cast<const bf16x4*>(S.X + (16 * ft + li) * 16 + 4 * lk);
+    bf16x4 h1[4], h2[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bf16x4 wa = *reinterpret_cast<const bf16x4*>(g.W1t + (16 * t + li) * 16 + 4 * lk);
+      const f32x4 z = mfma16(wa, xf, f32x4{0.f, 0.f, 0.f, 0.f});
+      const float4 bb = *reinterpret_cast<const float4*>(g.b1 + 16 * t + 4 * lk);
+      h1[t][0] = (short)f2bf(gelu(z[0] + bb.x));
+      h1[t][1] = (short)f2bf(gelu(z[1] + bb.y));
+      h1[t][2] = (short)f2bf(gelu(z[2] + bb.z));
+      h1[t][3] = (short)f2bf(gelu(z[3] + bb.w));
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bf16x4 wa = *reinterpret_cast<const bf16x4*>(g.W2t + (16 * t + li) * 64 + 16 * ks + 4 * lk);
+        z = mfma16(wa, h1[ks], z);
+      }
+      const float4 bb = *reinterpret_cast<const float4*>(g.b2 + 16 * t + 4 * lk);
+      h2[t][0] = (short)f2bf(gelu(z[0] + bb.x));
+      h2[t][1] = (short)f2bf(gelu(z[1] + bb.y));
+      h2[t][2] = (short)f2bf(gelu(z[2] + bb.z));
+      h2[t][3] = (short)f2bf(gelu(z[3] + bb.w));
+    }
+    f32x4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const bf16x4 wa = *reinterpret_cast<const bf16x4*>(g.W3t + li * 64 + 16 * ks + 4 * lk);
+      o = mfma16(wa, h2[ks], o);
+    }
+    // lane (li, lk) holds outputs 4 lk + 0..3 of face 16 ft + li
+    if (lk < 2) {
+      const float4 b3 = *reinterpret_cast<const float4*>(g.b3 + 4 * lk);
+      *reinterpret_cast<float4*>(S.Y + (16 * ft + li) * 8 + 4 * lk) =
+          make_float4(o[0] + b3.x, o[1] + b3.y, o[2] + b3.z, o[3] + b3.w);
+    }
+  }
+  wave_sync();
+  const float4 y0 = *reinterpret_cast<const float4*>(S.Y + lane * 8);
+  const float4 y1 = *reinterpret_cast<const float4*>(S.Y + lane * 8 + 4);
+  y[0] = y0.x; y[1] = y0.y; y[2] = y0.z; y[3] = y0.w;
+  y[4] = y1.x; y[5] = y1.y; y[6] = y1.z;
+  wave_sync();   // the stage is rewritten by the next call
 }
 
 // Learned flux with HLLD fallback for one face per lane.  Returns 1 when the
@@ -241,8 +242,9 @@ __device__ __forceinline__ int mlp_or_hlld(MlpShared& sh, bool active, const flo
 #pragma unroll
     for (int m = 0; m < 7; ++m) sc[m] = 0.0f;
   }
-  float y[7];
-  mlp_forward_wave(sh, x, y);
+  float y[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // the network runs when any lane of the wave needs it (wave-uniform test)
+  if (__ballot(active && !fall) != 0ull) mlp_forward_wave(sh, x, y);
   if (!active) return 0;
   if (fall) {
     riemann_hlld(wl, wr, bn, gam, f);

@@ -155,7 +155,7 @@ def test_hierarchy_graph_replay_matches_eager():
     g = h1.capture()
     h2.step()
     for rep in range(3):
-        g.replay()
+        h1.replay(g)
         h2.step()
         h1.stream.synchronize()
         h2.stream.synchronize()
@@ -170,3 +170,25 @@ def test_nested_groups_are_octree_consistent():
     for x in gs[1]:
         assert tuple((x // 16) // 2) in parents
     assert len({tuple(x) for x in gs[1]}) == 511
+
+
+def test_autotuner_picks_a_candidate_and_shapes_keep_results(tmp_path):
+    from paper_1804_03479_amd import autotune
+    h = Hierarchy(32, [5, 9], prec="f32", seed=4)
+    r = autotune.tune(h, candidates=(0, 1, 4), reps=2, cache=str(tmp_path / "tune.json"))
+    assert len(r["shapes"]) == 3 and all(b in (0, 1, 4) for b in r["shapes"])
+    assert all(len(ms) == 3 and min(ms) > 0 for ms in r["ms"])
+    again = autotune.tune(h, candidates=(0, 1, 4), cache=str(tmp_path / "tune.json"), use_cache=True)
+    assert again["shapes"] == r["shapes"]
+    h.close()
+    # the tuned shapes give the same bits as the default shape
+    a = Hierarchy(32, [5, 9], prec="f32", seed=4)
+    b = Hierarchy(32, [5, 9], prec="f32", seed=4)
+    b.set_launch([1, 4, 1])
+    for _ in range(2):
+        a.step()
+        b.step()
+    a.stream.synchronize()
+    b.stream.synchronize()
+    for x, y in zip(a.levels, b.levels):
+        assert torch.equal(x.U, y.U) and torch.equal(x.B, y.B)
