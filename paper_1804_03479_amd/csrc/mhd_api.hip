@@ -170,6 +170,31 @@ Work make_work(const mhd_level* lv, int lo, int hi) {
   w.occ = nullptr;
   w.n_dev = (lv->groups && lv->n_groups > 0) ? lv->n_groups_dev : nullptr;
   w.oshift = 0;
+  w.NS = w.N;
+  w.sb = 0;
+  w.soff = 0;
+  return w;
+}
+
+// Work of an update stage whose items reach lo / hi cells below / above each
+// group; with a group list the stage scratch is addressed per group, in boxes
+// of edge + 2 ghost cells (ghost >= lo, hi).
+long long scratch_box(const mhd_level* lv, int ghost) { return (long long)lv->group_edge + 2 * ghost; }
+bool list_mode(const mhd_level* lv) { return lv->groups && lv->n_groups > 0; }
+
+long long scratch_cells(const mhd_level* lv, int ghost) {
+  if (!list_mode(lv)) return (long long)lv->nx * lv->ny * lv->nz;
+  const long long sb = scratch_box(lv, ghost);
+  return ((long long)lv->n_groups + 2) * sb * sb * sb;
+}
+
+Work stage_work(const mhd_level* lv, int lo, int hi, int ghost) {
+  Work w = make_work(lv, lo, hi);
+  if (list_mode(lv)) {
+    w.sb = (int)scratch_box(lv, ghost);
+    w.NS = scratch_cells(lv, ghost);
+    w.soff = ghost - lo;
+  }
   return w;
 }
 
@@ -215,8 +240,8 @@ const char* stage_name(const mhd_ctx_s* c, int s) {
 }
 
 // ev (optional): kNumStages + 1 events recorded around the stage kernels
-template <typename T, int S, bool MIX>
-void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev = nullptr) {
+template <typename T, int S, bool MIX, bool L>
+void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
   const Mix mix{MIX ? lv->E64 : nullptr, c->cfg.beta_fp64};
   hipStream_t st = c->stream;
   T* U = (T*)lv->U;
@@ -227,9 +252,10 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
   T* E = (T*)c->E;
   const T gam = (T)c->cfg.gamma;
   const T inv_dx = (T)(1.0 / lv->dx);
-  const Work wp = make_work(lv, 3, 3), wf1 = make_work(lv, 3, 3), we1 = make_work(lv, 2, 3);
-  const Work wh = make_work(lv, 2, 2), wf2 = make_work(lv, 1, 1), we2 = make_work(lv, 0, 1);
-  Work wu = make_work(lv, 0, 0);
+  constexpr int G = 3;   // ghost cells of VL + PLM
+  const Work wp = stage_work(lv, 3, 3, G), wf1 = stage_work(lv, 3, 3, G), we1 = stage_work(lv, 2, 3, G);
+  const Work wh = stage_work(lv, 2, 2, G), wf2 = stage_work(lv, 1, 1, G), we2 = stage_work(lv, 0, 1, G);
+  Work wu = stage_work(lv, 0, 0, G);
   wu.occ = c->occ;
   auto mark = [&](int s) {
     if (ev) (void)hipEventRecord(ev[s], st);
@@ -237,22 +263,22 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
   mark(0);
   if (cfl) {
     k_reset_smax<<<1, 1, 0, st>>>(c->smax);
-    k_prim<T, true, MIX><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
+    k_prim<T, true, MIX, L><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   } else {
-    k_prim<T, false, MIX><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
+    k_prim<T, false, MIX, L><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   }
   mark(1);
-  k_flux<T, 0, S><<<sblocks(wf1), kBlock, 0, st>>>(wf1, W, B, F, gam, c->nfb);
+  k_flux<T, 0, S, L><<<sblocks(wf1), kBlock, 0, st>>>(wf1, W, B, F, gam, c->nfb);
   mark(2);
-  k_emf<T><<<sblocks(we1), kBlock, 0, st>>>(we1, F, W, E);
+  k_emf<T, L><<<sblocks(we1), kBlock, 0, st>>>(we1, F, W, E);
   mark(3);
-  k_half<T, MIX><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F, E, dts, inv_dx, gam, W, Bh);
+  k_half<T, MIX, L><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F, E, dts, inv_dx, gam, W, Bh);
   mark(4);
-  k_flux<T, 1, S><<<sblocks(wf2), kBlock, 0, st>>>(wf2, W, Bh, F, gam, c->nfb);
+  k_flux<T, 1, S, L><<<sblocks(wf2), kBlock, 0, st>>>(wf2, W, Bh, F, gam, c->nfb);
   mark(5);
-  k_emf<T><<<sblocks(we2), kBlock, 0, st>>>(we2, F, W, E);
+  k_emf<T, L><<<sblocks(we2), kBlock, 0, st>>>(we2, F, W, E);
   mark(6);
-  k_final<T, MIX><<<sblocks(wu), kBlock, 0, st>>>(wu, U, B, mix, F, E, dts, inv_dx);
+  k_final<T, MIX, L><<<sblocks(wu), kBlock, 0, st>>>(wu, U, B, mix, F, E, dts, inv_dx);
   mark(7);
 }
 
@@ -267,7 +293,7 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
 //   k_final        U^n, B^n, F2, E      -> U^{n+1}, B^{n+1}   step 8
 // Group halos (cells below, above each group): 4,4 / 2,2 / 2,2 / 1,2 / 1,1 /
 // 1,1 / 0,1 / 0,0, i.e. 4 ghost cells of U^n.
-template <typename T, int S, int R, bool MIX>
+template <typename T, int S, int R, bool MIX, bool L>
 void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
   const Mix mix{MIX ? lv->E64 : nullptr, c->cfg.beta_fp64};
   hipStream_t st = c->stream;
@@ -282,10 +308,11 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
   T* QR = (T*)c->QR;
   const T gam = (T)c->cfg.gamma;
   const T inv_dx = (T)(1.0 / lv->dx);
-  const Work wp = make_work(lv, 4, 4), wq = make_work(lv, 2, 2), wf1 = make_work(lv, 2, 2);
-  const Work we1 = make_work(lv, 1, 2), wh = make_work(lv, 1, 1), wf2 = make_work(lv, 1, 1);
-  const Work we2 = make_work(lv, 0, 1);
-  Work wu = make_work(lv, 0, 0);
+  constexpr int G = 4;   // ghost cells of CTU + PPM
+  const Work wp = stage_work(lv, 4, 4, G), wq = stage_work(lv, 2, 2, G), wf1 = stage_work(lv, 2, 2, G);
+  const Work we1 = stage_work(lv, 1, 2, G), wh = stage_work(lv, 1, 1, G), wf2 = stage_work(lv, 1, 1, G);
+  const Work we2 = stage_work(lv, 0, 1, G);
+  Work wu = stage_work(lv, 0, 0, G);
   wu.occ = c->occ;
   auto mark = [&](int s) {
     if (ev) (void)hipEventRecord(ev[s], st);
@@ -293,58 +320,65 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
   mark(0);
   if (cfl) {
     k_reset_smax<<<1, 1, 0, st>>>(c->smax);
-    k_prim<T, true, MIX><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
+    k_prim<T, true, MIX, L><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   } else {
-    k_prim<T, false, MIX><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
+    k_prim<T, false, MIX, L><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   }
   mark(1);
-  k_ctu_states<T, R><<<sblocks(wq), kBlock, 0, st>>>(wq, W, B, QL, QR, dts, inv_dx, gam);
+  k_ctu_states<T, R, L><<<sblocks(wq), kBlock, 0, st>>>(wq, W, B, QL, QR, dts, inv_dx, gam);
   mark(2);
   constexpr bool kMlp = S == 3 && std::is_same<T, float>::value;
   const float dp = (float)c->cfg.mlp_dp, drho = (float)c->cfg.mlp_drho;
   if constexpr (kMlp) {
     const unsigned nb = sblocks(wf1);
-    const long long n7 = 7LL * wf1.N;
-    k_flux_dir_mlp<0><<<nb, kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb);
-    k_flux_dir_mlp<1><<<nb, kBlock, 0, st>>>(wf1, QL + n7, QR + n7, B, F1, gam, c->mlpw, dp, drho, c->nfb);
-    k_flux_dir_mlp<2><<<nb, kBlock, 0, st>>>(wf1, QL + 2 * n7, QR + 2 * n7, B, F1, gam, c->mlpw, dp, drho, c->nfb);
+    const long long n7 = 7LL * wf1.NS;
+    k_flux_dir_mlp<0, false, L><<<nb, kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb);
+    k_flux_dir_mlp<1, false, L><<<nb, kBlock, 0, st>>>(wf1, QL + n7, QR + n7, B, F1, gam, c->mlpw, dp, drho, c->nfb);
+    k_flux_dir_mlp<2, false, L><<<nb, kBlock, 0, st>>>(wf1, QL + 2 * n7, QR + 2 * n7, B, F1, gam, c->mlpw, dp, drho, c->nfb);
   } else
-    k_flux_q<T, S><<<sblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->nfb, c->capture);
+    k_flux_q<T, S, L><<<sblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->nfb, c->capture);
   mark(3);
-  k_emf<T><<<sblocks(we1), kBlock, 0, st>>>(we1, F1, W, E);
+  k_emf<T, L><<<sblocks(we1), kBlock, 0, st>>>(we1, F1, W, E);
   mark(4);
-  k_half<T, MIX><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F1, E, dts, inv_dx, gam, W, Bh);
+  k_half<T, MIX, L><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F1, E, dts, inv_dx, gam, W, Bh);
   mark(5);
   if constexpr (kMlp) {
     float* Qc = (float*)c->Qc;
     const unsigned nb = sblocks(wf2);
-    k_ctu_correct_dir<0><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
-    k_flux_dir_mlp<0><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.N, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
-    k_ctu_correct_dir<1><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
-    k_flux_dir_mlp<1><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.N, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
-    k_ctu_correct_dir<2><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
-    k_flux_dir_mlp<2><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.N, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
+    k_ctu_correct_dir<0, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
+    k_flux_dir_mlp<0, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
+    k_ctu_correct_dir<1, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
+    k_flux_dir_mlp<1, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
+    k_ctu_correct_dir<2, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
+    k_flux_dir_mlp<2, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
   } else
-    k_ctu_correct<T, S><<<sblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->nfb,
-                                                         c->capture);
+    k_ctu_correct<T, S, L><<<sblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam,
+                                                             c->nfb, c->capture);
   mark(6);
-  k_emf<T><<<sblocks(we2), kBlock, 0, st>>>(we2, F2, W, E);
+  k_emf<T, L><<<sblocks(we2), kBlock, 0, st>>>(we2, F2, W, E);
   mark(7);
-  k_final<T, MIX><<<sblocks(wu), kBlock, 0, st>>>(wu, U, B, mix, F2, E, dts, inv_dx);
+  k_final<T, MIX, L><<<sblocks(wu), kBlock, 0, st>>>(wu, U, B, mix, F2, E, dts, inv_dx);
   mark(8);
 }
 
-template <typename T, int S, bool MIX>
-void launch_scheme(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
+template <typename T, int S, bool MIX, bool L>
+void launch_method(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
   if constexpr (S == 3) {
     // learned flux: CTU only (validated at mhd_init)
-    if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX>(c, lv, dts, cfl, ev);
-    else launch_ctu<T, S, 0, MIX>(c, lv, dts, cfl, ev);
+    if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX, L>(c, lv, dts, cfl, ev);
+    else launch_ctu<T, S, 0, MIX, L>(c, lv, dts, cfl, ev);
     return;
   }
-  if (c->cfg.scheme == MHD_VL) launch_step<T, S, MIX>(c, lv, dts, cfl, ev);
-  else if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX>(c, lv, dts, cfl, ev);
-  else launch_ctu<T, S, 0, MIX>(c, lv, dts, cfl, ev);
+  if (c->cfg.scheme == MHD_VL) launch_step<T, S, MIX, L>(c, lv, dts, cfl, ev);
+  else if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX, L>(c, lv, dts, cfl, ev);
+  else launch_ctu<T, S, 0, MIX, L>(c, lv, dts, cfl, ev);
+}
+
+// group lists use per-group scratch boxes, whole grids the level's addressing
+template <typename T, int S, bool MIX>
+void launch_scheme(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
+  if (list_mode(lv)) launch_method<T, S, MIX, true>(c, lv, dts, cfl, ev);
+  else launch_method<T, S, MIX, false>(c, lv, dts, cfl, ev);
 }
 
 template <typename T, bool MIX>
@@ -361,7 +395,7 @@ int do_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* 
   int rc = check_level(c, lv);
   if (rc) return rc;
   if (c->cfg.riemann == MHD_MLP && !c->mlp_ready) return MHD_ERR_INVALID_ARG;
-  rc = ensure_capacity(c, (long long)lv->nx * lv->ny * lv->nz);
+  rc = ensure_capacity(c, scratch_cells(lv, c->cfg.scheme == MHD_CTU ? 4 : 3));
   if (rc) return rc;
   rc = build_occupancy(c, lv);
   if (rc) return rc;
@@ -593,7 +627,7 @@ int mhd_advance_graph(mhd_ctx c, const mhd_level* lv, double* dt_dev, double* t_
   if (!same) {
     drop_graph(c);
     // allocations happen before the capture
-    rc = ensure_capacity(c, (long long)lv->nx * lv->ny * lv->nz);
+    rc = ensure_capacity(c, scratch_cells(lv, c->cfg.scheme == MHD_CTU ? 4 : 3));
     if (rc) return rc;
     if (lv->groups && lv->n_groups > 0) {
       const long long ng =

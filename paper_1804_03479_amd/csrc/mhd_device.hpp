@@ -258,7 +258,11 @@ __device__ __forceinline__ void hlld_star(const T w[7], const T u[7], T bn, T S,
   const T q = d * sv * sm;
   const T den = q - bn * bn;
   T v1, v2, b1, b2;
-  if (dabs(den) <= T(1e-12) * (dabs(q) + bn * bn)) {
+  // degenerate switch (S = S*, Miyoshi & Kusano 2005): set well above the
+  // arithmetic's rounding level, which q - bn^2 inherits from S and SM -- in
+  // float a relative 1e-12 is below the noise and the division amplifies it
+  const T eps = sizeof(T) == 4 ? T(1e-5) : T(1e-12);
+  if (dabs(den) <= eps * (dabs(q) + bn * bn)) {
     v1 = w[2]; v2 = w[3]; b1 = w[5]; b2 = w[6];
   } else {
     const T iden = T(1) / den;

@@ -42,6 +42,22 @@ struct Work {
   int gnx, gny, gnz;    // groups per dimension
   const int* n_dev;     // list mode: number of groups read from device memory, or nullptr
   int oshift;           // list mode: group origins are divided by 2^oshift (coarse footprint)
+  // Stage scratch (W, F, E, Q, Bh, ...) addressing.  Whole grid: like the
+  // level (slot = cell index, stride N).  Group list: each group owns a
+  // contiguous box of sb^3 slots (its cells plus sb/2 - edge/2 ghost layers),
+  // group g at slot (g + 1) sb^3, with one unused box before and after so
+  // stencil reads past a box edge stay inside the allocation.
+  long long NS;         // component stride of the scratch arrays
+  int sb;               // scratch box edge (0: scratch addressed like the level)
+  int soff;             // offset of this stage's item box inside the scratch box
+};
+
+// A work item's cell: global coordinates, level index p and scratch slot s;
+// (a, b, c) is its position inside the stage's item box.
+struct Site {
+  int i, j, k;
+  int a, b, c;
+  long long p, s;
 };
 
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -55,14 +71,16 @@ __device__ __forceinline__ long long nbr(const Work& w, int i, int j, int k, int
   return lin(w, wrapc(i + di, w.nx), wrapc(j + dj, w.ny), wrapc(k + dk, w.nz));
 }
 
-__device__ __forceinline__ long long block_linear_id() {
+// Blocks are dispatched to the 8 XCDs round-robin (block b to XCD b % 8);
+// the rank remaps them so each XCD gets a contiguous range of ranks.
+__device__ __forceinline__ unsigned block_rank() {
   const unsigned nb = gridDim.x;
   const unsigned b = blockIdx.x;
   const unsigned q = nb >> 3;
-  unsigned r = b;
-  if (b < (q << 3)) r = (b & 7u) * q + (b >> 3);  // XCD b%8 gets a contiguous range
-  return (long long)r * kBlock + threadIdx.x;
+  return b < (q << 3) ? (b & 7u) * q + (b >> 3) : b;
 }
+
+__device__ __forceinline__ long long block_linear_id() { return (long long)block_rank() * kBlock + threadIdx.x; }
 
 // Persistent launches: a grid of at most a tuned number of blocks walks the
 // work items with a grid-wide stride; the item count of a group list may be
@@ -102,6 +120,45 @@ __device__ __forceinline__ void cell_of(const Work& w, long long t, int& i, int&
 __device__ __forceinline__ void cell_of(const Work& w, long long t, int& i, int& j, int& k) {
   int a, b, c;
   cell_of(w, t, i, j, k, a, b, c);
+}
+
+// L: list mode with per-group scratch boxes (compile time, so the
+// whole-grid kernels carry no list arithmetic)
+template <bool L>
+__device__ __forceinline__ Site site_of(const Work& w, long long t) {
+  Site st;
+  cell_of(w, t, st.i, st.j, st.k, st.a, st.b, st.c);
+  st.p = lin(w, st.i, st.j, st.k);
+  if constexpr (L) {
+    const long long per = (long long)w.box * w.box * w.box;
+    const long long g = t / per;
+    const long long sb = w.sb;
+    st.s = (g + 1) * sb * sb * sb + ((long long)(st.c + w.soff) * sb + (st.b + w.soff)) * sb + (st.a + w.soff);
+  } else {
+    st.s = st.p;
+  }
+  return st;
+}
+
+// scratch slot of the cell (di, dj, dk) away
+template <bool L>
+__device__ __forceinline__ long long snb(const Work& w, const Site& st, int di, int dj, int dk) {
+  if constexpr (L) return st.s + di + (long long)dj * w.sb + (long long)dk * w.sb * w.sb;
+  else return nbr(w, st.i, st.j, st.k, di, dj, dk);
+}
+
+// the neighbouring cell as a site (level index and scratch slot)
+template <bool L>
+__device__ __forceinline__ Site site_nb(const Work& w, const Site& st, int di, int dj, int dk) {
+  Site n;
+  n.i = wrapc(st.i + di, w.nx);
+  n.j = wrapc(st.j + dj, w.ny);
+  n.k = wrapc(st.k + dk, w.nz);
+  n.a = st.a + di; n.b = st.b + dj; n.c = st.c + dk;
+  n.p = lin(w, n.i, n.j, n.k);
+  if constexpr (L) n.s = st.s + di + (long long)dj * w.sb + (long long)dk * w.sb * w.sb;
+  else n.s = n.p;
+  return n;
 }
 
 // loop over this thread's work items
@@ -211,19 +268,17 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* s
 
 // Primitive state of every cell; optionally the CFL maximum signal speed and
 // the sticky non-physical flag.
-template <typename T, bool CFL, bool MIX>
+template <typename T, bool CFL, bool MIX, bool L>
 __global__ void __launch_bounds__(kBlock) k_prim(Work w, const T* __restrict__ U, const T* __restrict__ B, Mix mix,
                                                  T* __restrict__ W, T gam, unsigned long long* smax,
                                                  int* flag) {
   double s = 0.0;
   FOR_ITEMS(w, t) {
-    int i, j, k;
-    cell_of(w, t, i, j, k);
+    const Site st = site_of<L>(w, t);
     T q[8];
-    cell_prims<T, MIX>(w, U, B, mix, i, j, k, gam, q);
-    const long long p = lin(w, i, j, k);
+    cell_prims<T, MIX>(w, U, B, mix, st.i, st.j, st.k, gam, q);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) W[m * w.N + p] = q[m];
+    for (int m = 0; m < 8; ++m) W[m * w.NS + st.s] = q[m];
     if (!(q[0] > T(0)) || !(q[4] > T(0))) atomicOr(flag, 1);
     else if (CFL) s = fmax(s, signal_speed(q, gam));
   }
@@ -274,22 +329,24 @@ __device__ __forceinline__ void load_w1d(const T* __restrict__ W, long long N, l
   w[6] = W[(5 + t2) * N + q];
 }
 
-// RECON: 0 = first order (cell states), 1 = PLM with minmod on primitives
-template <typename T, int D, int RECON, int SOLVER>
-__device__ __forceinline__ int face_flux(const Work& w, const T* __restrict__ W, const T* __restrict__ B,
-                                         T* __restrict__ F, int i, int j, int k, T gam) {
-  const long long N = w.N;
-  const long long pR = lin(w, i, j, k);
-  const long long pL = nbr(w, i, j, k, D == 0 ? -1 : 0, D == 1 ? -1 : 0, D == 2 ? -1 : 0);
+// RECON: 0 = first order (cell states), 1 = PLM with minmod on primitives.
+// The normal field Bn is the level's B (predictor: Bn[D N + p]) or the
+// half-step scratch Bh (corrector: Bn[D NS + s]); RECON 1 is the corrector.
+template <typename T, int D, int RECON, int SOLVER, bool L>
+__device__ __forceinline__ int face_flux(const Work& w, const T* __restrict__ W, const T* __restrict__ Bn,
+                                         T* __restrict__ F, const Site& st, T gam) {
+  const long long NS = w.NS;
+  const long long pR = st.s;
+  const long long pL = snb<L>(w, st, D == 0 ? -1 : 0, D == 1 ? -1 : 0, D == 2 ? -1 : 0);
   T wl[7], wr[7];
-  load_w1d<T, D>(W, N, pL, wl);
-  load_w1d<T, D>(W, N, pR, wr);
+  load_w1d<T, D>(W, NS, pL, wl);
+  load_w1d<T, D>(W, NS, pR, wr);
   if (RECON == 1) {
-    const long long pLL = nbr(w, i, j, k, D == 0 ? -2 : 0, D == 1 ? -2 : 0, D == 2 ? -2 : 0);
-    const long long pRR = nbr(w, i, j, k, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0);
+    const long long pLL = snb<L>(w, st, D == 0 ? -2 : 0, D == 1 ? -2 : 0, D == 2 ? -2 : 0);
+    const long long pRR = snb<L>(w, st, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0);
     T wll[7], wrr[7];
-    load_w1d<T, D>(W, N, pLL, wll);
-    load_w1d<T, D>(W, N, pRR, wrr);
+    load_w1d<T, D>(W, NS, pLL, wll);
+    load_w1d<T, D>(W, NS, pRR, wrr);
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
       const T sL = minmod(wl[m] - wll[m], wr[m] - wl[m]);
@@ -298,18 +355,18 @@ __device__ __forceinline__ int face_flux(const Work& w, const T* __restrict__ W,
       wr[m] = wr[m] - T(0.5) * sR;
     }
   }
-  const T bn = B[D * N + pR];
+  const T bn = RECON == 1 ? Bn[D * NS + st.s] : Bn[D * w.N + st.p];
   T f[7];
   const int fb = riemann<SOLVER>(wl, wr, bn, gam, f);
   constexpr int n = D, t1 = (D + 1) % 3, t2 = (D + 2) % 3;
-  T* Fd = F + (long long)D * 7 * N;
+  T* Fd = F + (long long)D * 7 * NS;
   Fd[pR] = f[0];
-  Fd[(1 + n) * N + pR] = f[1];
-  Fd[(1 + t1) * N + pR] = f[2];
-  Fd[(1 + t2) * N + pR] = f[3];
-  Fd[4 * N + pR] = f[4];
-  Fd[5 * N + pR] = f[6];    // E_t1 = F_n[B_t2]
-  Fd[6 * N + pR] = -f[5];   // E_t2 = -F_n[B_t1]
+  Fd[(1 + n) * NS + pR] = f[1];
+  Fd[(1 + t1) * NS + pR] = f[2];
+  Fd[(1 + t2) * NS + pR] = f[3];
+  Fd[4 * NS + pR] = f[4];
+  Fd[5 * NS + pR] = f[6];    // E_t1 = F_n[B_t2]
+  Fd[6 * NS + pR] = -f[5];   // E_t2 = -F_n[B_t1]
   return fb;
 }
 
@@ -327,16 +384,17 @@ __device__ __forceinline__ void block_count_atomic(int v, unsigned long long* co
   }
 }
 
-template <typename T, int RECON, int SOLVER>
+// VL flux stage; B is the level's field for RECON 0 and the half-step
+// scratch Bh for RECON 1 (see face_flux).
+template <typename T, int RECON, int SOLVER, bool L>
 __global__ void __launch_bounds__(kBlock) k_flux(Work w, const T* __restrict__ W, const T* __restrict__ B,
                                                  T* __restrict__ F, T gam, unsigned long long* nfb) {
   int fb = 0;
   FOR_ITEMS(w, t) {
-    int i, j, k;
-    cell_of(w, t, i, j, k);
-    fb += face_flux<T, 0, RECON, SOLVER>(w, W, B, F, i, j, k, gam);
-    fb += face_flux<T, 1, RECON, SOLVER>(w, W, B, F, i, j, k, gam);
-    fb += face_flux<T, 2, RECON, SOLVER>(w, W, B, F, i, j, k, gam);
+    const Site st = site_of<L>(w, t);
+    fb += face_flux<T, 0, RECON, SOLVER, L>(w, W, B, F, st, gam);
+    fb += face_flux<T, 1, RECON, SOLVER, L>(w, W, B, F, st, gam);
+    fb += face_flux<T, 2, RECON, SOLVER, L>(w, W, B, F, st, gam);
   }
   if (SOLVER == 0) block_count_atomic(fb, nfb);
 }
@@ -358,19 +416,19 @@ __device__ __forceinline__ T upwind(T m, T pos, T neg) {
 // Gardiner & Stone 2005): each face value is extrapolated to the edge with
 // the derivative taken in the upwind cell (sign of the face mass flux), and
 // the four extrapolations are averaged.
-template <typename T, int A>
+template <typename T, int A, bool L>
 __device__ __forceinline__ T edge_emf(const Work& w, const T* __restrict__ F, const T* __restrict__ W,
-                                      int i, int j, int k) {
+                                      const Site& st) {
   constexpr int b = (A + 1) % 3, c = (A + 2) % 3;
-  const long long N = w.N;
+  const long long N = w.NS;
   const T* Fb = F + (long long)b * 7 * N;
   const T* Fc = F + (long long)c * 7 * N;
   const int ob[3] = {b == 0 ? -1 : 0, b == 1 ? -1 : 0, b == 2 ? -1 : 0};
   const int oc[3] = {c == 0 ? -1 : 0, c == 1 ? -1 : 0, c == 2 ? -1 : 0};
-  const long long p = lin(w, i, j, k);
-  const long long pb = nbr(w, i, j, k, ob[0], ob[1], ob[2]);
-  const long long pc = nbr(w, i, j, k, oc[0], oc[1], oc[2]);
-  const long long pbc = nbr(w, i, j, k, ob[0] + oc[0], ob[1] + oc[1], ob[2] + oc[2]);
+  const long long p = st.s;
+  const long long pb = snb<L>(w, st, ob[0], ob[1], ob[2]);
+  const long long pc = snb<L>(w, st, oc[0], oc[1], oc[2]);
+  const long long pbc = snb<L>(w, st, ob[0] + oc[0], ob[1] + oc[1], ob[2] + oc[2]);
   const T eb0 = Fb[6 * N + pc], eb1 = Fb[6 * N + p];
   const T ec0 = Fc[5 * N + pb], ec1 = Fc[5 * N + p];
   const T mb0 = Fb[pc], mb1 = Fb[p], mc0 = Fc[pb], mc1 = Fc[p];
@@ -383,85 +441,82 @@ __device__ __forceinline__ T edge_emf(const Work& w, const T* __restrict__ F, co
   return T(0.25) * (eb0 + eb1 + ec0 + ec1) + T(0.25) * ((dc0 - dc1) + (db0 - db1));
 }
 
-template <typename T>
+template <typename T, bool L>
 __global__ void __launch_bounds__(kBlock) k_emf(Work w, const T* __restrict__ F, const T* __restrict__ W,
                                                 T* __restrict__ E) {
   FOR_ITEMS(w, t) {
-    int i, j, k;
-    cell_of(w, t, i, j, k);
-    const long long p = lin(w, i, j, k);
-    E[p] = edge_emf<T, 0>(w, F, W, i, j, k);
-    E[w.N + p] = edge_emf<T, 1>(w, F, W, i, j, k);
-    E[2 * w.N + p] = edge_emf<T, 2>(w, F, W, i, j, k);
+    const Site st = site_of<L>(w, t);
+    E[st.s] = edge_emf<T, 0, L>(w, F, W, st);
+    E[w.NS + st.s] = edge_emf<T, 1, L>(w, F, W, st);
+    E[2 * w.NS + st.s] = edge_emf<T, 2, L>(w, F, W, st);
   }
 }
 
 // ------------------------------------------------------------ updates
 // U - r div F (Eq. 10), differences applied in the order x, y, z.  In the
 // mixed form the energy is updated in double from E64 (returned in e64).
-template <typename T, bool MIX>
+template <typename T, bool MIX, bool L>
 __device__ __forceinline__ void cell_update(const Work& w, const T* __restrict__ U, const T* __restrict__ F,
-                                            const Mix& mix, int i, int j, int k, T r, T out[5], double& e64) {
-  const long long N = w.N;
-  const long long p = lin(w, i, j, k);
-  const long long px = nbr(w, i, j, k, 1, 0, 0), py = nbr(w, i, j, k, 0, 1, 0), pz = nbr(w, i, j, k, 0, 0, 1);
+                                            const Mix& mix, const Site& st, T r, T out[5], double& e64) {
+  const long long N = w.N, NS = w.NS;
+  const long long p = st.p, s = st.s;
+  const long long px = snb<L>(w, st, 1, 0, 0), py = snb<L>(w, st, 0, 1, 0), pz = snb<L>(w, st, 0, 0, 1);
   const T* Fx = F;
-  const T* Fy = F + 7 * N;
-  const T* Fz = F + 14 * N;
+  const T* Fy = F + 7 * NS;
+  const T* Fz = F + 14 * NS;
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     if (MIX && m == 4) {
       const double rd = (double)r;
       double v = mix.E64[p];
-      v -= rd * ((double)Fx[4 * N + px] - (double)Fx[4 * N + p]);
-      v -= rd * ((double)Fy[4 * N + py] - (double)Fy[4 * N + p]);
-      v -= rd * ((double)Fz[4 * N + pz] - (double)Fz[4 * N + p]);
+      v -= rd * ((double)Fx[4 * NS + px] - (double)Fx[4 * NS + s]);
+      v -= rd * ((double)Fy[4 * NS + py] - (double)Fy[4 * NS + s]);
+      v -= rd * ((double)Fz[4 * NS + pz] - (double)Fz[4 * NS + s]);
       e64 = v;
       out[4] = T(v);
       continue;
     }
     T v = U[m * N + p];
-    v -= r * (Fx[m * N + px] - Fx[m * N + p]);
-    v -= r * (Fy[m * N + py] - Fy[m * N + p]);
-    v -= r * (Fz[m * N + pz] - Fz[m * N + p]);
+    v -= r * (Fx[m * NS + px] - Fx[m * NS + s]);
+    v -= r * (Fy[m * NS + py] - Fy[m * NS + s]);
+    v -= r * (Fz[m * NS + pz] - Fz[m * NS + s]);
     out[m] = v;
   }
   if (!MIX) e64 = (double)out[4];
 }
 
 // CT update of the three lower faces of cell (i, j, k) (Eq. 13)
-template <typename T>
+template <typename T, bool L>
 __device__ __forceinline__ void face_update(const Work& w, const T* __restrict__ B, const T* __restrict__ E,
-                                            int i, int j, int k, T r, T out[3]) {
-  const long long N = w.N;
-  const long long p = lin(w, i, j, k);
-  const long long px = nbr(w, i, j, k, 1, 0, 0), py = nbr(w, i, j, k, 0, 1, 0), pz = nbr(w, i, j, k, 0, 0, 1);
+                                            const Site& st, T r, T out[3]) {
+  const long long N = w.N, NS = w.NS;
+  const long long p = st.p, s = st.s;
+  const long long px = snb<L>(w, st, 1, 0, 0), py = snb<L>(w, st, 0, 1, 0), pz = snb<L>(w, st, 0, 0, 1);
   const T* Ex = E;
-  const T* Ey = E + N;
-  const T* Ez = E + 2 * N;
-  out[0] = B[p] - r * (Ez[py] - Ez[p]) + r * (Ey[pz] - Ey[p]);
-  out[1] = B[N + p] - r * (Ex[pz] - Ex[p]) + r * (Ez[px] - Ez[p]);
-  out[2] = B[2 * N + p] - r * (Ey[px] - Ey[p]) + r * (Ex[py] - Ex[p]);
+  const T* Ey = E + NS;
+  const T* Ez = E + 2 * NS;
+  out[0] = B[p] - r * (Ez[py] - Ez[s]) + r * (Ey[pz] - Ey[s]);
+  out[1] = B[N + p] - r * (Ex[pz] - Ex[s]) + r * (Ez[px] - Ez[s]);
+  out[2] = B[2 * N + p] - r * (Ey[px] - Ey[s]) + r * (Ex[py] - Ex[s]);
 }
 
 // Half step over dt/2: U^{n+1/2} and face B^{n+1/2} from the predictor fluxes
 // and EMFs, written as primitives Wh (cell-centred field from the updated
 // faces, including the upper faces owned by the neighbours) and Bh.
-template <typename T, bool MIX>
+template <typename T, bool MIX, bool L>
 __global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U, const T* __restrict__ B, Mix mix,
                                                  const T* __restrict__ F, const T* __restrict__ E, DtSrc dts,
                                                  T inv_dx, T gam, T* __restrict__ Wh, T* __restrict__ Bh) {
   const T r = T(0.5 * get_dt(dts)) * inv_dx;
   FOR_ITEMS(w, t) {
-  int i, j, k;
-  cell_of(w, t, i, j, k);
+  const Site st = site_of<L>(w, t);
   T u[5], bl[3], bux[3], buy[3], buz[3];
   double eh;
-  cell_update<T, MIX>(w, U, F, mix, i, j, k, r, u, eh);
-  face_update(w, B, E, i, j, k, r, bl);
-  face_update(w, B, E, wrapc(i + 1, w.nx), j, k, r, bux);
-  face_update(w, B, E, i, wrapc(j + 1, w.ny), k, r, buy);
-  face_update(w, B, E, i, j, wrapc(k + 1, w.nz), r, buz);
+  cell_update<T, MIX, L>(w, U, F, mix, st, r, u, eh);
+  face_update<T, L>(w, B, E, st, r, bl);
+  face_update<T, L>(w, B, E, site_nb<L>(w, st, 1, 0, 0), r, bux);
+  face_update<T, L>(w, B, E, site_nb<L>(w, st, 0, 1, 0), r, buy);
+  face_update<T, L>(w, B, E, site_nb<L>(w, st, 0, 0, 1), r, buz);
   const T bx = T(0.5) * (bl[0] + bux[0]);
   const T by = T(0.5) * (bl[1] + buy[1]);
   const T bz = T(0.5) * (bl[2] + buz[2]);
@@ -471,8 +526,8 @@ __global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U
   T pr;
   if (MIX) pr = recover_pressure<T, true>(eh, d, vx, vy, vz, bx, by, bz, gam, mix.beta);
   else pr = (gam - T(1)) * (u[4] - T(0.5) * d * (vx * vx + vy * vy + vz * vz) - T(0.5) * (bx * bx + by * by + bz * bz));
-  const long long N = w.N;
-  const long long p = lin(w, i, j, k);
+  const long long N = w.NS;
+  const long long p = st.s;
   Wh[p] = d; Wh[N + p] = vx; Wh[2 * N + p] = vy; Wh[3 * N + p] = vz; Wh[4 * N + p] = pr;
   Wh[5 * N + p] = bx; Wh[6 * N + p] = by; Wh[7 * N + p] = bz;
   Bh[p] = bl[0]; Bh[N + p] = bl[1]; Bh[2 * N + p] = bl[2];
@@ -486,22 +541,22 @@ __global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U
 // the face it shares with the next cell when the next cell's group is not
 // listed (occupancy map), so every face of a listed group advances exactly
 // once and no face is read after another thread has written it.
-template <typename T, bool MIX>
+template <typename T, bool MIX, bool L>
 __global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* __restrict__ B, Mix mix,
                                                   const T* __restrict__ F, const T* __restrict__ E, DtSrc dts,
                                                   T inv_dx) {
   const T r = T(get_dt(dts)) * inv_dx;
   const long long N = w.N;
   FOR_ITEMS(w, t) {
-  int i, j, k, a, b, c;
-  cell_of(w, t, i, j, k, a, b, c);
+  const Site st = site_of<L>(w, t);
+  const int i = st.i, j = st.j, k = st.k, a = st.a, b = st.b, c = st.c;
   T u[5], bf[3];
   double e64;
-  cell_update<T, MIX>(w, U, F, mix, i, j, k, r, u, e64);
-  face_update(w, B, E, i, j, k, r, bf);
+  cell_update<T, MIX, L>(w, U, F, mix, st, r, u, e64);
+  face_update<T, L>(w, B, E, st, r, bf);
   T ux[3], uy[3], uz[3];
   bool ex = false, ey = false, ez = false;
-  if (w.groups) {
+  if constexpr (L) {
     const int gi = i / w.edge, gj = j / w.edge, gk = k / w.edge;
     auto listed = [&](int x, int y, int z) {
       return w.occ[((long long)wrapc(z, w.gnz) * w.gny + wrapc(y, w.gny)) * w.gnx + wrapc(x, w.gnx)] != 0;
@@ -510,10 +565,10 @@ __global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* 
     ey = b == w.edge - 1 && !listed(gi, gj + 1, gk);
     ez = c == w.edge - 1 && !listed(gi, gj, gk + 1);
   }
-  if (ex) face_update(w, B, E, wrapc(i + 1, w.nx), j, k, r, ux);
-  if (ey) face_update(w, B, E, i, wrapc(j + 1, w.ny), k, r, uy);
-  if (ez) face_update(w, B, E, i, j, wrapc(k + 1, w.nz), r, uz);
-  const long long p = lin(w, i, j, k);
+  if (ex) face_update<T, L>(w, B, E, site_nb<L>(w, st, 1, 0, 0), r, ux);
+  if (ey) face_update<T, L>(w, B, E, site_nb<L>(w, st, 0, 1, 0), r, uy);
+  if (ez) face_update<T, L>(w, B, E, site_nb<L>(w, st, 0, 0, 1), r, uz);
+  const long long p = st.p;
 #pragma unroll
   for (int m = 0; m < 5; ++m) U[m * N + p] = u[m];
   if (MIX) mix.E64[p] = e64;
@@ -529,39 +584,38 @@ __global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* 
 // direction.  Face-indexed outputs: QR[d][m][p] is the state above the lower
 // d-face of cell p (from cell p), QL[d][m][p] the state below it (from the
 // cell p - e_d; written by that cell as its upper-edge state).
-template <typename T, int D, int RECON>
+template <typename T, int D, int RECON, bool L>
 __device__ __forceinline__ void cell_states(const Work& w, const T* __restrict__ W, const T* __restrict__ B,
-                                            T* __restrict__ QL, T* __restrict__ QR, int i, int j, int k, T dtdx,
+                                            T* __restrict__ QL, T* __restrict__ QR, const Site& st, T dtdx,
                                             T gam) {
-  const long long N = w.N;
+  const long long N = w.N, NS = w.NS;
   T q[5][7];
 #pragma unroll
   for (int s = -2; s <= 2; ++s) {
-    const long long c = nbr(w, i, j, k, D == 0 ? s : 0, D == 1 ? s : 0, D == 2 ? s : 0);
-    load_w1d<T, D>(W, N, c, q[s + 2]);
+    const long long c = snb<L>(w, st, D == 0 ? s : 0, D == 1 ? s : 0, D == 2 ? s : 0);
+    load_w1d<T, D>(W, NS, c, q[s + 2]);
   }
-  const long long p = lin(w, i, j, k);
-  const long long pu = nbr(w, i, j, k, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0);
+  const long long pu = nbr(w, st.i, st.j, st.k, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0);
+  const long long su = snb<L>(w, st, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0);
   T sl[7], sr[7];
-  trace_cell<T, RECON>(q, B[D * N + p], B[D * N + pu], dtdx, gam, sl, sr);
+  trace_cell<T, RECON>(q, B[D * N + st.p], B[D * N + pu], dtdx, gam, sl, sr);
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
-    QR[((long long)D * 7 + m) * N + p] = sl[m];
-    QL[((long long)D * 7 + m) * N + pu] = sr[m];
+    QR[((long long)D * 7 + m) * NS + st.s] = sl[m];
+    QL[((long long)D * 7 + m) * NS + su] = sr[m];
   }
 }
 
-template <typename T, int RECON>
+template <typename T, int RECON, bool L>
 __global__ void __launch_bounds__(kBlock) k_ctu_states(Work w, const T* __restrict__ W, const T* __restrict__ B,
                                                        T* __restrict__ QL, T* __restrict__ QR, DtSrc dts,
                                                        T inv_dx, T gam) {
   const T dtdx = T(get_dt(dts)) * inv_dx;
   FOR_ITEMS(w, t) {
-    int i, j, k;
-    cell_of(w, t, i, j, k);
-    cell_states<T, 0, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
-    cell_states<T, 1, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
-    cell_states<T, 2, RECON>(w, W, B, QL, QR, i, j, k, dtdx, gam);
+    const Site st = site_of<L>(w, t);
+    cell_states<T, 0, RECON, L>(w, W, B, QL, QR, st, dtdx, gam);
+    cell_states<T, 1, RECON, L>(w, W, B, QL, QR, st, dtdx, gam);
+    cell_states<T, 2, RECON, L>(w, W, B, QL, QR, st, dtdx, gam);
   }
 }
 
@@ -579,29 +633,28 @@ __device__ __forceinline__ void store_flux(T* __restrict__ F, long long N, long 
 }
 
 // Step 2: Riemann fluxes from the stored states with the time-n normal field
-template <typename T, int SOLVER>
+template <typename T, int SOLVER, bool L>
 __global__ void __launch_bounds__(kBlock) k_flux_q(Work w, const T* __restrict__ QL, const T* __restrict__ QR,
                                                    const T* __restrict__ B, T* __restrict__ F, T gam,
                                                    unsigned long long* nfb, Capture cp) {
   int fb = 0;
   FOR_ITEMS(w, t) {
-    int i, j, k;
-    cell_of(w, t, i, j, k);
-    const long long N = w.N;
-    const long long p = lin(w, i, j, k);
+    const Site st = site_of<L>(w, t);
+    const long long N = w.N, NS = w.NS;
+    const long long p = st.p, s = st.s;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       T wl[7], wr[7], f[7];
 #pragma unroll
       for (int m = 0; m < 7; ++m) {
-        wl[m] = QL[((long long)d * 7 + m) * N + p];
-        wr[m] = QR[((long long)d * 7 + m) * N + p];
+        wl[m] = QL[((long long)d * 7 + m) * NS + s];
+        wr[m] = QR[((long long)d * 7 + m) * NS + s];
       }
       fb += riemann<SOLVER>(wl, wr, B[d * N + p], gam, f);
       if constexpr (sizeof(T) == 4) capture_face(cp, 3 * p + d, wl, wr, B[d * N + p], f);
-      if (d == 0) store_flux<T, 0>(F, N, p, f);
-      else if (d == 1) store_flux<T, 1>(F, N, p, f);
-      else store_flux<T, 2>(F, N, p, f);
+      if (d == 0) store_flux<T, 0>(F, NS, s, f);
+      else if (d == 1) store_flux<T, 1>(F, NS, s, f);
+      else store_flux<T, 2>(F, NS, s, f);
     }
   }
   if (SOLVER == 0) block_count_atomic(fb, nfb);
@@ -613,11 +666,11 @@ __global__ void __launch_bounds__(kBlock) k_flux_q(Work w, const T* __restrict__
 // that cell.  Transverse field: dt/2 times the transverse part of -curl E
 // with the step-3 edge EMFs E_D averaged to the cell's faces.  The normal
 // field of the conversion is kept.  Non-physical results keep the input.
-template <typename T, int D>
+template <typename T, int D, bool L>
 __device__ __forceinline__ void correct_state(const Work& w, const T* __restrict__ F1, const T* __restrict__ E1,
-                                              int ci, int cj, int ck, T bn, T hr, T gam, const T s[7], T out[7]) {
+                                              const Site& src, T bn, T hr, T gam, const T s[7], T out[7]) {
   constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
-  const long long N = w.N;
+  const long long N = w.NS;
   T v[3], b[3];
   v[D] = s[1]; v[t1] = s[2]; v[t2] = s[3];
   b[D] = bn; b[t1] = s[5]; b[t2] = s[6];
@@ -628,11 +681,11 @@ __device__ __forceinline__ void correct_state(const Work& w, const T* __restrict
   u[3] = s[0] * v[2];
   u[4] = s[4] / (gam - T(1)) + T(0.5) * s[0] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) +
          T(0.5) * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-  const long long c = lin(w, ci, cj, ck);
+  const long long c = src.s;
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt) {
     const int t = tt ? t2 : t1;
-    const long long cp = nbr(w, ci, cj, ck, t == 0, t == 1, t == 2);
+    const long long cp = snb<L>(w, src, t == 0, t == 1, t == 2);
     const T* Ft = F1 + (long long)t * 7 * N;
 #pragma unroll
     for (int m = 0; m < 5; ++m) u[m] -= hr * (Ft[m * N + cp] - Ft[m * N + c]);
@@ -642,9 +695,9 @@ __device__ __forceinline__ void correct_state(const Work& w, const T* __restrict
   for (int tt = 0; tt < 2; ++tt) {
     const int bax = tt ? t2 : t1;
     const int der = (bax == (D + 2) % 3) ? (D + 1) % 3 : (D + 2) % 3;
-    const long long e_der = nbr(w, ci, cj, ck, der == 0, der == 1, der == 2);
-    const long long e_b = nbr(w, ci, cj, ck, bax == 0, bax == 1, bax == 2);
-    const long long e_db = nbr(w, ci, cj, ck, (der == 0) + (bax == 0), (der == 1) + (bax == 1), (der == 2) + (bax == 2));
+    const long long e_der = snb<L>(w, src, der == 0, der == 1, der == 2);
+    const long long e_b = snb<L>(w, src, bax == 0, bax == 1, bax == 2);
+    const long long e_db = snb<L>(w, src, (der == 0) + (bax == 0), (der == 1) + (bax == 1), (der == 2) + (bax == 2));
     const T up = T(0.5) * (Ed[e_der] + Ed[e_db]);
     const T lo = T(0.5) * (Ed[c] + Ed[e_b]);
     const T sign = (D == (bax + 1) % 3) ? T(1) : T(-1);
@@ -663,43 +716,41 @@ __device__ __forceinline__ void correct_state(const Work& w, const T* __restrict
   }
 }
 
-template <typename T, int D>
+template <typename T, int D, bool L>
 __device__ __forceinline__ void corrected_states(const Work& w, const T* __restrict__ QL, const T* __restrict__ QR,
                                                  const T* __restrict__ F1, const T* __restrict__ E1,
-                                                 const T* __restrict__ B, int i, int j, int k, T hr, T gam, T wl[7],
+                                                 const T* __restrict__ B, const Site& st, T hr, T gam, T wl[7],
                                                  T wr[7]) {
-  const long long N = w.N;
-  const long long p = lin(w, i, j, k);
+  const long long NS = w.NS;
   T sl[7], sr[7];
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
-    sl[m] = QL[((long long)D * 7 + m) * N + p];
-    sr[m] = QR[((long long)D * 7 + m) * N + p];
+    sl[m] = QL[((long long)D * 7 + m) * NS + st.s];
+    sr[m] = QR[((long long)D * 7 + m) * NS + st.s];
   }
-  const T bn = B[D * N + p];
-  correct_state<T, D>(w, F1, E1, wrapc(i - (D == 0), w.nx), wrapc(j - (D == 1), w.ny), wrapc(k - (D == 2), w.nz), bn,
-                      hr, gam, sl, wl);
-  correct_state<T, D>(w, F1, E1, i, j, k, bn, hr, gam, sr, wr);
+  const T bn = B[D * w.N + st.p];
+  correct_state<T, D, L>(w, F1, E1, site_nb<L>(w, st, -(D == 0), -(D == 1), -(D == 2)), bn, hr, gam, sl, wl);
+  correct_state<T, D, L>(w, F1, E1, st, bn, hr, gam, sr, wr);
 }
 
-template <typename T, int D, int SOLVER>
+template <typename T, int D, int SOLVER, bool L>
 __device__ __forceinline__ int corrected_face_flux(const Work& w, const T* __restrict__ QL, const T* __restrict__ QR,
                                                    const T* __restrict__ F1, const T* __restrict__ E1,
                                                    const T* __restrict__ B, const T* __restrict__ Bh,
-                                                   T* __restrict__ F2, int i, int j, int k, T hr, T gam,
+                                                   T* __restrict__ F2, const Site& st, T hr, T gam,
                                                    const Capture& cp) {
-  const long long N = w.N;
-  const long long p = lin(w, i, j, k);
+  const long long NS = w.NS;
   T wl[7], wr[7], f[7];
-  corrected_states<T, D>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
-  const int fb = riemann<SOLVER>(wl, wr, Bh[D * N + p], gam, f);
-  if constexpr (sizeof(T) == 4) capture_face(cp, 3 * p + D, wl, wr, Bh[D * N + p], f);
-  store_flux<T, D>(F2, N, p, f);
+  corrected_states<T, D, L>(w, QL, QR, F1, E1, B, st, hr, gam, wl, wr);
+  const T bn = Bh[D * NS + st.s];
+  const int fb = riemann<SOLVER>(wl, wr, bn, gam, f);
+  if constexpr (sizeof(T) == 4) capture_face(cp, 3 * st.p + D, wl, wr, bn, f);
+  store_flux<T, D>(F2, NS, st.s, f);
   return fb;
 }
 
 // Steps 5-6: corrected states and Riemann fluxes with the half-step normal field
-template <typename T, int SOLVER>
+template <typename T, int SOLVER, bool L>
 __global__ void __launch_bounds__(kBlock) k_ctu_correct(Work w, const T* __restrict__ QL, const T* __restrict__ QR,
                                                         const T* __restrict__ F1, const T* __restrict__ E1,
                                                         const T* __restrict__ B, const T* __restrict__ Bh,
@@ -708,11 +759,10 @@ __global__ void __launch_bounds__(kBlock) k_ctu_correct(Work w, const T* __restr
   int fb = 0;
   const T hr = T(0.5 * get_dt(dts)) * inv_dx;
   FOR_ITEMS(w, t) {
-    int i, j, k;
-    cell_of(w, t, i, j, k);
-    fb += corrected_face_flux<T, 0, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam, cp);
-    fb += corrected_face_flux<T, 1, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam, cp);
-    fb += corrected_face_flux<T, 2, SOLVER>(w, QL, QR, F1, E1, B, Bh, F2, i, j, k, hr, gam, cp);
+    const Site st = site_of<L>(w, t);
+    fb += corrected_face_flux<T, 0, SOLVER, L>(w, QL, QR, F1, E1, B, Bh, F2, st, hr, gam, cp);
+    fb += corrected_face_flux<T, 1, SOLVER, L>(w, QL, QR, F1, E1, B, Bh, F2, st, hr, gam, cp);
+    fb += corrected_face_flux<T, 2, SOLVER, L>(w, QL, QR, F1, E1, B, Bh, F2, st, hr, gam, cp);
   }
   if (SOLVER == 0) block_count_atomic(fb, nfb);
 }
@@ -721,57 +771,59 @@ __global__ void __launch_bounds__(kBlock) k_ctu_correct(Work w, const T* __restr
 // corrected states of the D-faces go to Qc (14 words per cell: L then R),
 // then the network (or HLLD at strong jumps) turns them into fluxes.  Split
 // so that neither kernel holds the correction and the network at once.
-template <int D>
+template <int D, bool L>
 __global__ void __launch_bounds__(kBlock) k_ctu_correct_dir(Work w, const float* __restrict__ QL,
                                                             const float* __restrict__ QR, const float* __restrict__ F1,
                                                             const float* __restrict__ E1, const float* __restrict__ B,
                                                             float* __restrict__ Qc, DtSrc dts, float inv_dx,
                                                             float gam) {
   const float hr = float(0.5 * get_dt(dts)) * inv_dx;
-  const long long N = w.N;
+  const long long NS = w.NS;
   FOR_ITEMS(w, t) {
-    int i, j, k;
-    cell_of(w, t, i, j, k);
-    const long long p = lin(w, i, j, k);
+    const Site st = site_of<L>(w, t);
     float wl[7], wr[7];
-    corrected_states<float, D>(w, QL, QR, F1, E1, B, i, j, k, hr, gam, wl, wr);
+    corrected_states<float, D, L>(w, QL, QR, F1, E1, B, st, hr, gam, wl, wr);
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
-      Qc[(long long)m * N + p] = wl[m];
-      Qc[(long long)(7 + m) * N + p] = wr[m];
+      Qc[(long long)m * NS + st.s] = wl[m];
+      Qc[(long long)(7 + m) * NS + st.s] = wr[m];
     }
   }
 }
 
-// Learned flux (HLLD at strong jumps) of the D-faces from states
-// L[m * N + p], R[m * N + p] (m = 0..6) and normal field Bn[D * N + p].
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __restrict__ L,
-                                                         const float* __restrict__ R, const float* __restrict__ Bn,
+// Learned flux (HLLD at strong jumps) of the D-faces from scratch states
+// QLd[m * NS + s], QRd[m * NS + s] (m = 0..6) and the normal field: the level's
+// B[D * N + p] (predictor) or the half-step scratch Bh[D * NS + s] (BN_SCRATCH).
+template <int D, bool BN_SCRATCH, bool L>
+__global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __restrict__ QLd,
+                                                         const float* __restrict__ QRd, const float* __restrict__ Bn,
                                                          float* __restrict__ F, float gam, const MlpWeights* mw,
                                                          float dp, float drho, unsigned long long* nfb) {
   __shared__ MlpShared sh;
   mlp_load_weights(sh, mw);
-  const long long N = w.N;
+  const long long N = w.N, NS = w.NS;
   const long long nitems = work_items(w);
   int fb = 0;
   // block-uniform trips: every lane of a wave takes part in the network
   for (long long base = block_linear_id() - threadIdx.x; base < nitems; base += item_stride()) {
     const long long t = base + threadIdx.x;
     const bool active = t < nitems;
-    int i = 0, j = 0, k = 0;
-    if (active) cell_of(w, t, i, j, k);
-    const long long p = active ? lin(w, i, j, k) : 0;
+    long long p = 0, s = 0;
+    if (active) {
+      const Site st = site_of<L>(w, t);
+      p = st.p;
+      s = st.s;
+    }
     float wl[7], wr[7], f[7];
     float bn = 1.0f;
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
-      wl[m] = active ? L[(long long)m * N + p] : 1.0f;
-      wr[m] = active ? R[(long long)m * N + p] : 1.0f;
+      wl[m] = active ? QLd[(long long)m * NS + s] : 1.0f;
+      wr[m] = active ? QRd[(long long)m * NS + s] : 1.0f;
     }
-    if (active) bn = Bn[D * N + p];
+    if (active) bn = BN_SCRATCH ? Bn[D * NS + s] : Bn[D * N + p];
     fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
-    if (active) store_flux<float, D>(F, N, p, f);
+    if (active) store_flux<float, D>(F, NS, s, f);
   }
   block_count_atomic(fb, nfb);
 }

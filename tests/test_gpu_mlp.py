@@ -203,3 +203,44 @@ def test_trained_network_gain():
         assert a <= b / 3.0
     mx, _ = s.divb(lm)
     assert mx * lm.dx <= 1e-5          # CT keeps div B at round-off with any flux
+
+
+def near_degenerate_faces(rng, n):
+    """Faces next to HLLD's degenerate case: with zero transverse field,
+    equal normal velocity and pressure on both sides, B_n^2 > gamma p and
+    rho_R <= rho_L, S_M = u and rho_R (S_R - u)(S_R - S_M) = B_n^2 exactly;
+    small transverse fields and perturbations move the face off it by a
+    relative 1e-12 .. 1e-4."""
+    rho_l = rng.uniform(1.0, 1.1, n)
+    rho_r = rho_l * (1.0 - rng.uniform(0.0, 0.05, n))
+    u = rng.uniform(-0.05, 0.05, n)
+    pr = rng.uniform(0.9, 1.1, n)
+    bn = rng.uniform(1.45, 1.7, n) * np.sign(rng.uniform(-1, 1, n))
+    lam = 10.0 ** rng.uniform(-6, -2, n)
+    eps = 10.0 ** rng.uniform(-9, -5, (2, n))
+    wl = np.stack([rho_l, u * (1 + eps[0]), rng.uniform(-0.05, 0.05, n), rng.uniform(-0.05, 0.05, n), pr,
+                   lam * rng.uniform(-1, 1, n), lam * rng.uniform(-1, 1, n)], axis=1)
+    wr = np.stack([rho_r, u * (1 + eps[1]), rng.uniform(-0.05, 0.05, n), rng.uniform(-0.05, 0.05, n), pr,
+                   lam * rng.uniform(-1, 1, n), lam * rng.uniform(-1, 1, n)], axis=1)
+    return (wl.astype(np.float32).astype(np.float64), wr.astype(np.float32).astype(np.float64),
+            bn.astype(np.float32).astype(np.float64))
+
+
+def test_hlld_float_near_degenerate_faces():
+    """HLLD in float at faces close to its degenerate case (seeded synthetic
+    states): the float flux must stay within float round-off of the double
+    oracle's (regression: a relative switch of 1e-12 let float rounding
+    noise into the star-state division)."""
+    rng = np.random.default_rng(21)
+    wl, wr, bn = near_degenerate_faces(rng, 3000)
+    s = Solver("ctu", "ppm", "mlp", "f32", mlp_dp=-1.0, mlp_drho=-1.0)   # every face to HLLD
+    ops = MlpOps(s)
+    ops.set_weights(dev(omlp.init_params(0)))
+    F, used = ops.face_flux(dev(np.concatenate([wl, wr, bn[:, None]], axis=1)))
+    F = F.cpu().numpy()
+    assert used.cpu().numpy().all()
+    worst = 0.0
+    for i in range(len(bn)):
+        fo, _ = oracle.riemann(oracle.HLLD, wl[i], wr[i], bn[i])
+        worst = max(worst, np.abs(F[i] - fo).max() / (1.0 + np.abs(fo).max()))
+    assert worst <= 1e-4, worst
