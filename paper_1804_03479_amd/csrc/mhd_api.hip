@@ -837,19 +837,22 @@ int mhd_mlp_set_weights(mhd_ctx c, const float* params_dev) {
 namespace {
 // training workspace: Z1, H1, Z2, H2, dZ2, dZ1 (n x 64 each), Y, dY (n x 7),
 // loss partials
+constexpr int kSplitK = 256;            // batch rows per split-K chunk of a weight gradient
+constexpr int kGradParts = 64 * 64;     // largest weight-gradient tile set
+
 int ensure_mlp_ws(mhd_ctx_s* c, long long n) {
   if (n <= c->cap_mlp) return MHD_OK;
   hipFree(c->mlp_ws);
   c->mlp_ws = nullptr;
   c->cap_mlp = 0;
-  const long long words = 6 * 64 * n + 2 * 7 * n + (7 * n + 255) / 256 + 16;
+  const long long words = 6 * 64 * n + 2 * 7 * n + (7 * n + 255) / 256 + 16 + kGradParts * ((n + kSplitK - 1) / kSplitK);
   if (hipMalloc(&c->mlp_ws, words * sizeof(float)) != hipSuccess) return MHD_ERR_OUT_OF_MEMORY;
   c->cap_mlp = n;
   return MHD_OK;
 }
 
 struct MlpBufs {
-  float *Z1, *H1, *Z2, *H2, *dZ2, *dZ1, *Y, *dY, *part;
+  float *Z1, *H1, *Z2, *H2, *dZ2, *dZ1, *Y, *dY, *part, *gpart;
 };
 
 MlpBufs mlp_bufs(mhd_ctx_s* c) {
@@ -858,7 +861,18 @@ MlpBufs mlp_bufs(mhd_ctx_s* c) {
   MlpBufs m;
   m.Z1 = b; m.H1 = b + 64 * n; m.Z2 = b + 128 * n; m.H2 = b + 192 * n; m.dZ2 = b + 256 * n; m.dZ1 = b + 320 * n;
   m.Y = b + 384 * n; m.dY = b + 391 * n; m.part = b + 398 * n;
+  m.gpart = m.part + (7 * n + 255) / 256 + 16;
   return m;
+}
+
+// weight gradient C[M x N] = A^T B over the batch (K = n): split-K on MFMA
+// with an ordered sum of the chunks (deterministic), M, N <= 64
+void gemm_wgrad(hipStream_t st, int M, int N, int K, const float* A, long long sam, long long sak, const float* Bm,
+                long long sbk, long long sbn, float* C, int ldc, float* gpart) {
+  const int chunks = (K + kSplitK - 1) / kSplitK;
+  const long long waves = (long long)((M + 15) / 16) * ((N + 15) / 16) * chunks;
+  k_mlp_gemm_part<<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(M, N, K, kSplitK, A, sam, sak, Bm, sbk, sbn, gpart);
+  k_mlp_sum_parts<<<(unsigned)((M * N + 255) / 256), 256, 0, st>>>(M, N, chunks, gpart, C, ldc);
 }
 
 template <int EPI>
@@ -878,14 +892,14 @@ void mlp_forward(mhd_ctx_s* c, const float* P, const float* X, int n, const MlpB
 
 void mlp_backward(mhd_ctx_s* c, const float* P, const float* X, const float* dY, int n, const MlpBufs& b, float* G) {
   hipStream_t st = c->stream;
-  gemm<EPI_STORE>(st, kNh, kNout, n, b.H2, 1, kNh, dY, kNout, 1, nullptr, nullptr, G + oW3, nullptr, kNout);
+  gemm_wgrad(st, kNh, kNout, n, b.H2, 1, kNh, dY, kNout, 1, G + oW3, kNout, b.gpart);
   k_mlp_colsum<<<kNout, 256, 0, st>>>(n, kNout, dY, G + ob3);
   gemm<EPI_GELU_PRIME>(st, n, kNh, kNout, dY, kNout, 1, P + oW3, 1, kNout, nullptr, b.Z2, b.dZ2, nullptr, kNh);
   k_mlp_colsum<<<kNh, 256, 0, st>>>(n, kNh, b.dZ2, G + ob2);
-  gemm<EPI_STORE>(st, kNh, kNh, n, b.H1, 1, kNh, b.dZ2, kNh, 1, nullptr, nullptr, G + oW2, nullptr, kNh);
+  gemm_wgrad(st, kNh, kNh, n, b.H1, 1, kNh, b.dZ2, kNh, 1, G + oW2, kNh, b.gpart);
   gemm<EPI_GELU_PRIME>(st, n, kNh, kNh, b.dZ2, kNh, 1, P + oW2, 1, kNh, nullptr, b.Z1, b.dZ1, nullptr, kNh);
   k_mlp_colsum<<<kNh, 256, 0, st>>>(n, kNh, b.dZ1, G + ob1);
-  gemm<EPI_STORE>(st, kNin, kNh, n, X, 1, kNin, b.dZ1, kNh, 1, nullptr, nullptr, G + oW1, nullptr, kNh);
+  gemm_wgrad(st, kNin, kNh, n, X, 1, kNin, b.dZ1, kNh, 1, G + oW1, kNh, b.gpart);
 }
 }  // namespace
 

@@ -363,6 +363,51 @@ __global__ void __launch_bounds__(256) k_mlp_gemm(int M, int N, int K, const flo
   }
 }
 
+// Split-K form of EPI_STORE for the weight gradients (small M x N, K = the
+// batch): wave w computes tile w % tiles over rows [kc (w / tiles), + kc) of
+// K into part[chunk][M][N]; k_mlp_sum_parts adds the chunks in order.
+__global__ void __launch_bounds__(256) k_mlp_gemm_part(int M, int N, int K, int kc, const float* __restrict__ A,
+                                                       long long sam, long long sak, const float* __restrict__ Bm,
+                                                       long long sbk, long long sbn, float* __restrict__ part) {
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int tiles_n = (N + 15) / 16;
+  const int tiles = ((M + 15) / 16) * tiles_n;
+  const int chunks = (K + kc - 1) / kc;
+  if (wave >= tiles * chunks) return;
+  const int tile = wave % tiles, chunk = wave / tiles;
+  const int m0 = (tile / tiles_n) * 16, n0 = (tile % tiles_n) * 16;
+  const int kb = chunk * kc, ke = min(K, kb + kc);
+  f32x4 c = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 4 * lk + q;
+      const int m = m0 + li, n = n0 + li;
+      const float av = (m < M && k < ke) ? A[m * sam + k * sak] : 0.0f;
+      const float bv = (n < N && k < ke) ? Bm[k * sbk + n * sbn] : 0.0f;
+      a[q] = (short)f2bf(av);
+      b[q] = (short)f2bf(bv);
+    }
+    c = mfma16(a, b, c);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int m = m0 + 4 * lk + q, n = n0 + li;
+    if (m < M && n < N) part[((long long)chunk * M + m) * N + n] = c[q];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_sum_parts(int M, int N, int chunks, const float* __restrict__ part,
+                                                       float* __restrict__ C, int ldc) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= M * N) return;
+  float acc = 0.0f;
+  for (int ch = 0; ch < chunks; ++ch) acc += part[(long long)ch * M * N + i];
+  C[(long long)(i / N) * ldc + i % N] = acc;
+}
+
 // column sums of a [M x N] matrix (bias gradients), fixed order
 __global__ void __launch_bounds__(256) k_mlp_colsum(int M, int N, const float* __restrict__ S, float* __restrict__ out) {
   __shared__ float red[256];
