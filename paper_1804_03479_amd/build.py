@@ -14,6 +14,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed-FP32 instructions in generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # float division and square root as reciprocal / v_sqrt (a few ulp)
+         # instead of the correctly rounded multi-instruction sequences: the
+         # float stage kernels are bound by VALU issue; double is unaffected
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
          "-Wno-unused-result", "-Wno-unused-value",
          "-I" + os.path.join(ROOT, "include")]
 SOURCES = ["mhd_api.hip"]
