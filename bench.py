@@ -312,6 +312,9 @@ def main():
     ap.add_argument("--amr-counts", default="511,1024",
                     help="patch groups (16^3 cells) of each refined level; also runs 7,64")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line, print one line with cell-updates/s of the CTU form "
+                         "over grid sizes 32^3 .. 512^3 (FP32) and .. 384^3 (FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -331,6 +334,19 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.sweep:
+        sweep = {}
+        for prec, sizes in (("f32", (32, 64, 96, 128, 192, 256, 384, 512)), ("f64", (32, 64, 96, 128, 192, 256, 384))):
+            for key in ("ctu", "vl"):
+                for n_ in sizes:
+                    steps = max(5, min(args.steps, int(3e8 / n_ ** 3)))
+                    r = run_form(WORKLOADS[key], prec, n_, steps, args.warmup, args.seed, profile=False)
+                    sweep[f"{key}_{prec}_{n_}"] = {"n": n_, "steps": steps, "value": r["value"],
+                                                   "ms_per_step": r["ms_per_step"]}
+                    print(f"sweep {key} {prec} {n_}^3: {r['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
+        print(json.dumps({"metric": "cell-updates/s/GPU", "unit": "cell-updates/s", "sweep": sweep,
+                          "config": {"workloads": {k: WORKLOADS[k]["label"] for k in ("ctu", "vl")}}}))
+        return
     n = args.n
     cells = n ** 3
     todo = ["ctu", "vl", "mlp", "amr"] if args.only is None else [args.only]
