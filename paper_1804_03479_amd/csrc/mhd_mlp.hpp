@@ -34,11 +34,19 @@ constexpr int oW1 = 0, ob1 = 960, oW2 = 1024, ob2 = 5120, oW3 = 5184, ob3 = 5632
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// round to the nearest bfloat16, ties to even (finite inputs)
-__device__ __forceinline__ unsigned short f2bf(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+// round to the nearest bfloat16, ties to even (gfx950 converts in hardware,
+// two values per v_cvt_pk_bf16_f32)
+__device__ __forceinline__ unsigned short f2bf(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+__device__ __forceinline__ unsigned f2bf2(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{a, b}, bf16x2v));
+}
+// four floats to one MFMA BF16 operand fragment
+__device__ __forceinline__ bf16x4 f2bf4(float a, float b, float c, float d) {
+  return __builtin_bit_cast(bf16x4, u32x2{f2bf2(a, b), f2bf2(c, d)});
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
@@ -168,7 +176,7 @@ __device__ __forceinline__ void mlp_forward_wave(MlpShared& sh, const float x[16
   {
     unsigned pk[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) pk[m] = (unsigned)f2bf(x[2 * m]) | ((unsigned)f2bf(x[2 * m + 1]) << 16);
+    for (int m = 0; m < 8; ++m) pk[m] = f2bf2(x[2 * m], x[2 * m + 1]);
     uint4* dst = reinterpret_cast<uint4*>(S.X + lane * 16);
     dst[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     dst[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
@@ -183,10 +191,7 @@ __device__ __forceinline__ void mlp_forward_wave(MlpShared& sh, const float x[16
       const bf16x4 wa = *reinterpret_cast<const bf16x4*>(g.W1t + (16 * t + li) * 16 + 4 * lk);
       const f32x4 z = mfma16(wa, xf, f32x4{0.f, 0.f, 0.f, 0.f});
       const float4 bb = *reinterpret_cast<const float4*>(g.b1 + 16 * t + 4 * lk);
-      h1[t][0] = (short)f2bf(gelu(z[0] + bb.x));
-      h1[t][1] = (short)f2bf(gelu(z[1] + bb.y));
-      h1[t][2] = (short)f2bf(gelu(z[2] + bb.z));
-      h1[t][3] = (short)f2bf(gelu(z[3] + bb.w));
+      h1[t] = f2bf4(gelu(z[0] + bb.x), gelu(z[1] + bb.y), gelu(z[2] + bb.z), gelu(z[3] + bb.w));
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -197,10 +202,7 @@ __device__ __forceinline__ void mlp_forward_wave(MlpShared& sh, const float x[16
         z = mfma16(wa, h1[ks], z);
       }
       const float4 bb = *reinterpret_cast<const float4*>(g.b2 + 16 * t + 4 * lk);
-      h2[t][0] = (short)f2bf(gelu(z[0] + bb.x));
-      h2[t][1] = (short)f2bf(gelu(z[1] + bb.y));
-      h2[t][2] = (short)f2bf(gelu(z[2] + bb.z));
-      h2[t][3] = (short)f2bf(gelu(z[3] + bb.w));
+      h2[t] = f2bf4(gelu(z[0] + bb.x), gelu(z[1] + bb.y), gelu(z[2] + bb.z), gelu(z[3] + bb.w));
     }
     f32x4 o = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
