@@ -160,9 +160,30 @@ int mhd_cfl_dt_min(mhd_ctx ctx, const mhd_level* lv, double* dt_dev);
  * takes its value, a fine face inside a coarse cell the mean of the two coarse
  * faces bracketing it, so each fine cell's divergence equals its parent's.
  * mhd_restrict: coarse cells under the listed fine groups (all cells with no
- * list) take the mean of their eight children.  Not for MHD_F32_MIXED. */
+ * list) take the mean of their eight children, and the coarse faces of those
+ * cells, including the faces on the boundary of the refined region, the mean
+ * of the four fine faces on them.  Not for MHD_F32_MIXED. */
 int mhd_prolong(mhd_ctx ctx, const mhd_level* coarse, const mhd_level* fine, int halo);
 int mhd_restrict(mhd_ctx ctx, const mhd_level* fine, const mhd_level* coarse);
+
+/* Correction operation of paper Sec. 3.3 across a coarse-fine interface,
+ * after both levels were updated by one step of the same dt (*dt_dev, device
+ * double): a coarse cell outside the refined region that shares a face with
+ * it replaces the coarse flux through that face by the mean of the four fine
+ * fluxes; a coarse face with both cells outside takes the CT update of the
+ * EMF differences (mean of the two fine EMFs minus the coarse EMF) on its
+ * edges that touch the refined region.  Cells and faces inside the refined
+ * region are left to mhd_restrict (call it afterwards).  Then the coarse
+ * context's stored final fluxes and EMFs on the faces and edges of refined
+ * cells become the fine means, so that correcting the next coarser level
+ * across a shared interface uses the finest values (no proper-nesting
+ * requirement).  ctx_coarse and
+ * ctx_fine must be the contexts that ran those updates (their stage scratch
+ * holds the final fluxes and EMFs), on the same stream, with the same scheme
+ * and precision; the fine groups must lie inside listed coarse groups when
+ * the coarse level has a list.  Not for MHD_F32_MIXED. */
+int mhd_correct(mhd_ctx ctx_coarse, const mhd_level* coarse, mhd_ctx ctx_fine, const mhd_level* fine,
+                const double* dt_dev);
 
 /* Discrete divergence of Eq. 16 in double: max |div B| and the mean of
  * |div B| over the level's cells.  Synchronises. */

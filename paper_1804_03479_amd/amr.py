@@ -9,7 +9,10 @@ hierarchy (shared time step, no sub-cycling):
   for each level, coarse to fine:
       refill the ghost halos from the parent    (mhd_prolong, list mode)
       update the listed groups                  (mhd_step_devdt)
-  restrict each level onto its parent, fine to coarse (mhd_restrict)
+  for each level, fine to coarse:
+      correct the parent at the coarse-fine interface with the level's
+      fluxes and EMFs                           (mhd_correct)
+      restrict the level onto its parent        (mhd_restrict)
 
 Group lists are chosen with a seeded generator and are octree-consistent:
 every group of level l + 1 lies inside a group of level l.
@@ -51,8 +54,10 @@ class Hierarchy:
     keeps its own launch shape and scratch), all on one stream."""
 
     def __init__(self, n_root: int, counts, scheme="ctu", recon="ppm", riemann="hlld", prec="f32",
-                 noise: float = 0.1, seed: int = 0, edge: int = 16, stream: torch.cuda.Stream | None = None):
+                 noise: float = 0.1, seed: int = 0, edge: int = 16, stream: torch.cuda.Stream | None = None,
+                 correct: bool = True):
         self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.correct = correct
         self.groups = nested_groups(n_root, counts, edge, seed)
         with torch.cuda.stream(self.stream):
             self.solvers = [Solver(scheme, recon, riemann, prec, stream=self.stream)
@@ -110,6 +115,8 @@ class Hierarchy:
             for lvl in range(len(self.levels)):
                 self.update_level(lvl)
             for lvl in range(len(self.levels) - 1, 0, -1):
+                if self.correct:
+                    self.solvers[lvl - 1].correct(self.levels[lvl - 1], self.solvers[lvl], self.levels[lvl], self.dt)
                 self.solvers[lvl].restrict(self.levels[lvl], self.levels[lvl - 1])
 
     def capture(self):

@@ -724,7 +724,8 @@ void launch_prolong(mhd_ctx_s* c, const mhd_level* coarse, const mhd_level* fine
 
 template <typename T>
 void launch_restrict(mhd_ctx_s* c, const mhd_level* fine, const mhd_level* coarse) {
-  const Work wf = make_work(fine, 0, 0);
+  Work wf = make_work(fine, 0, 0);
+  wf.occ = c->occ;
   const mhd_level cw = whole_grid(coarse);
   Work wc = make_work(&cw, 0, 0);
   if (fine->groups && fine->n_groups > 0) {
@@ -738,7 +739,53 @@ void launch_restrict(mhd_ctx_s* c, const mhd_level* fine, const mhd_level* coars
     wc.gnx = wc.gny = wc.gnz = 0;
     wc.oshift = 1;
   }
-  k_restrict<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, (const T*)fine->U, (T*)coarse->U);
+  k_restrict<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, (const T*)fine->U, (T*)coarse->U, (const T*)fine->B,
+                                                         (T*)coarse->B);
+}
+
+// the stage scratch of context c as left by its last update of level lv
+LevelScratch level_scratch(mhd_ctx_s* c, const mhd_level* lv) {
+  const int ghost = c->cfg.scheme == MHD_CTU ? 4 : 3;
+  LevelScratch v;
+  v.F = c->cfg.scheme == MHD_CTU ? c->F2 : c->F;
+  v.E = c->E;
+  v.NS = scratch_cells(lv, ghost);
+  v.sb = list_mode(lv) ? (int)scratch_box(lv, ghost) : 0;
+  v.ghost = ghost;
+  v.occ = c->occ;
+  v.groups = lv->groups;
+  v.edge = lv->group_edge;
+  v.gnx = lv->nx / lv->group_edge;
+  v.gny = lv->ny / lv->group_edge;
+  v.gnz = lv->nz / lv->group_edge;
+  v.nx = lv->nx; v.ny = lv->ny; v.nz = lv->nz;
+  return v;
+}
+
+template <typename T>
+void launch_correct(mhd_ctx_s* cc, const mhd_level* coarse, mhd_ctx_s* cf, const mhd_level* fine, const double* dt) {
+  Work wc = make_work(coarse, 0, 0);
+  wc.occ = cc->occ;
+  Work wf = make_work(fine, 0, 0);
+  wf.occ = cf->occ;
+  const LevelScratch sc = level_scratch(cc, coarse), sf = level_scratch(cf, fine);
+  const T inv_dx = (T)(1.0 / coarse->dx);
+  k_correct_u<T><<<sblocks(wc), kBlock, 0, cc->stream>>>(wc, wf, sc, sf, (T*)coarse->U, dt, inv_dx);
+  k_correct_b<T><<<sblocks(wc), kBlock, 0, cc->stream>>>(wc, wf, sc, sf, (T*)coarse->B, dt, inv_dx);
+  // the coarse fluxes and EMFs on the refined region become the fine means
+  const mhd_level cw = whole_grid(coarse);
+  Work wcf = make_work(&cw, 0, 0);
+  if (list_mode(fine)) {
+    wcf.groups = fine->groups;
+    wcf.edge = fine->group_edge / 2;
+    wcf.halo = 0;
+    wcf.box = fine->group_edge / 2;
+    wcf.items = (long long)fine->n_groups * wcf.box * wcf.box * wcf.box;
+    wcf.n_dev = fine->n_groups_dev;
+    wcf.gnx = wcf.gny = wcf.gnz = 0;
+    wcf.oshift = 1;
+  }
+  k_correct_registers<T><<<sblocks(wcf), kBlock, 0, cc->stream>>>(wcf, wf, sc, sf);
 }
 }  // namespace
 
@@ -762,9 +809,36 @@ int mhd_restrict(mhd_ctx c, const mhd_level* fine, const mhd_level* coarse) {
   int rc = check_pair(c, coarse, fine);
   if (rc) return rc;
   if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
+  rc = build_occupancy(c, fine);
+  if (rc) return rc;
   g_max_blocks = c->max_blocks;
   if (c->cfg.prec == MHD_F64) launch_restrict<double>(c, fine, coarse);
   else launch_restrict<float>(c, fine, coarse);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_correct(mhd_ctx cc, const mhd_level* coarse, mhd_ctx cf, const mhd_level* fine, const double* dt_dev) {
+  if (!cc || !cf || !coarse || !fine || !dt_dev) return MHD_ERR_INVALID_ARG;
+  int rc = check_pair(cc, coarse, fine);
+  if (rc) return rc;
+  rc = check_level(cf, fine);
+  if (rc) return rc;
+  if (cc->cfg.prec != cf->cfg.prec || cc->cfg.scheme != cf->cfg.scheme || cc->stream != cf->stream)
+    return MHD_ERR_INVALID_ARG;
+  if (cc->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
+  const int ghost = cc->cfg.scheme == MHD_CTU ? 4 : 3;
+  // both contexts must hold the scratch of an update of these levels
+  if (cc->cap_cells < scratch_cells(coarse, ghost) || cf->cap_cells < scratch_cells(fine, ghost))
+    return MHD_ERR_INVALID_ARG;
+  rc = build_occupancy(cc, coarse);
+  if (rc) return rc;
+  rc = build_occupancy(cf, fine);
+  if (rc) return rc;
+  if (list_mode(coarse) && !cc->occ) return MHD_ERR_INVALID_ARG;
+  if (list_mode(fine) && !cf->occ) return MHD_ERR_INVALID_ARG;
+  g_max_blocks = cc->max_blocks;
+  if (cc->cfg.prec == MHD_F64) launch_correct<double>(cc, coarse, cf, fine, dt_dev);
+  else launch_correct<float>(cc, coarse, cf, fine, dt_dev);
   return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 

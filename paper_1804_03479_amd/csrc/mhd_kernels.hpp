@@ -840,7 +840,7 @@ __global__ void __launch_bounds__(kBlock) k_occ_set(int* occ, const int* groups,
   const int n = n_dev ? min(*n_dev, n_groups) : n_groups;
   if (g >= n) return;
   const int gi = groups[3 * g] / edge, gj = groups[3 * g + 1] / edge, gk = groups[3 * g + 2] / edge;
-  occ[((long long)gk * gny + gj) * gnx + gi] = 1;
+  occ[((long long)gk * gny + gj) * gnx + gi] = g + 1;   // 0: not listed, else group index + 1
 }
 
 // ------------------------------------------------------------ AMR support
@@ -927,10 +927,37 @@ __global__ void __launch_bounds__(kBlock) k_prolong_ghosts(Work wc, Work wf, con
   }
 }
 
+// Is coarse cell (ci, cj, ck) covered by the fine level?  Whole fine level:
+// always; group list: when the fine group holding its first child is listed.
+__device__ __forceinline__ bool refined(const Work& wf, int ci, int cj, int ck) {
+  if (!wf.groups) return true;
+  const int I = wrapc(2 * ci, wf.nx), J = wrapc(2 * cj, wf.ny), K = wrapc(2 * ck, wf.nz);
+  return wf.occ[((long long)(K / wf.edge) * wf.gny + J / wf.edge) * wf.gnx + I / wf.edge] != 0;
+}
+
+// mean of the four fine faces of direction A on the lower A-face of coarse
+// cell (i, j, k)
+template <typename T, int A>
+__device__ __forceinline__ T fine_face_mean(const Work& wf, const T* __restrict__ Bf, int i, int j, int k) {
+  constexpr int b = (A + 1) % 3, c = (A + 2) % 3;
+  T s = T(0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int f[3] = {2 * i, 2 * j, 2 * k};
+    f[b] += q & 1;
+    f[c] += q >> 1;
+    s += Bf[A * wf.N + lin(wf, wrapc(f[0], wf.nx), wrapc(f[1], wf.ny), wrapc(f[2], wf.nz))];
+  }
+  return T(0.25) * s;
+}
+
 // restriction (Sec. 3.3, correction operation): coarse cells under listed
-// fine groups take the volume average of their 8 children
+// fine groups take the volume average of their 8 children, and the coarse
+// faces of those cells (including the faces on the boundary of the refined
+// region) the area average of the 4 fine faces on them
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_restrict(Work wc, Work wf, const T* __restrict__ Uf, T* __restrict__ Uc) {
+__global__ void __launch_bounds__(kBlock) k_restrict(Work wc, Work wf, const T* __restrict__ Uf, T* __restrict__ Uc,
+                                                     const T* __restrict__ Bf, T* __restrict__ Bc) {
   // work items are coarse cells of the fine groups' footprints (edge/2)^3
   FOR_ITEMS(wc, t) {
     int i, j, k;
@@ -945,6 +972,284 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Work wc, Work wf, const T* 
         s += Uf[m * wf.N + lin(wf, I, J, K)];
       }
       Uc[m * wc.N + pc] = T(0.125) * s;
+    }
+    Bc[pc] = fine_face_mean<T, 0>(wf, Bf, i, j, k);
+    Bc[wc.N + pc] = fine_face_mean<T, 1>(wf, Bf, i, j, k);
+    Bc[2 * wc.N + pc] = fine_face_mean<T, 2>(wf, Bf, i, j, k);
+    // upper faces on the boundary of the refined region (owned by the
+    // unrefined neighbour)
+    if (!refined(wf, i + 1, j, k))
+      Bc[nbr(wc, i, j, k, 1, 0, 0)] = fine_face_mean<T, 0>(wf, Bf, wrapc(i + 1, wc.nx), j, k);
+    if (!refined(wf, i, j + 1, k))
+      Bc[wc.N + nbr(wc, i, j, k, 0, 1, 0)] = fine_face_mean<T, 1>(wf, Bf, i, wrapc(j + 1, wc.ny), k);
+    if (!refined(wf, i, j, k + 1))
+      Bc[2 * wc.N + nbr(wc, i, j, k, 0, 0, 1)] = fine_face_mean<T, 2>(wf, Bf, i, j, wrapc(k + 1, wc.nz));
+  }
+}
+
+// Where a level's last update left its final face fluxes and edge EMFs, and
+// how to address them (the stage scratch of its context).
+struct LevelScratch {
+  const void* F;        // [3][7] components of the final fluxes (store_flux order)
+  const void* E;        // [3] components of the final edge EMFs
+  long long NS;         // component stride
+  int sb, ghost;        // per-group boxes (sb = 0: addressed like the level)
+  const int* occ;       // group index + 1 per group of the level (list mode)
+  const int* groups;
+  int edge, gnx, gny, gnz, nx, ny, nz;
+};
+
+__device__ __forceinline__ int wrap_delta(int d, int n) { return d > n / 2 ? d - n : (d < -(n / 2) ? d + n : d); }
+
+// listed group holding cell (i, j, k) of the level, or -1
+__device__ __forceinline__ int group_at(const LevelScratch& v, int i, int j, int k) {
+  i = wrapc(i, v.nx); j = wrapc(j, v.ny); k = wrapc(k, v.nz);
+  return v.occ[((long long)(k / v.edge) * v.gny + j / v.edge) * v.gnx + i / v.edge] - 1;
+}
+
+// scratch slot of cell (i, j, k) inside the box of group g (list mode), or
+// its level index (whole grid)
+__device__ __forceinline__ long long slot_at(const LevelScratch& v, int i, int j, int k, int g) {
+  if (!v.sb) return ((long long)wrapc(k, v.nz) * v.ny + wrapc(j, v.ny)) * v.nx + wrapc(i, v.nx);
+  const int* o = v.groups + 3 * g;
+  const long long sb = v.sb;
+  const int a = wrap_delta(i - o[0], v.nx) + v.ghost, b = wrap_delta(j - o[1], v.ny) + v.ghost,
+            c = wrap_delta(k - o[2], v.nz) + v.ghost;
+  return (long long)(g + 1) * sb * sb * sb + ((long long)c * sb + b) * sb + a;
+}
+
+// Correction of conserved variables (Sec. 3.3): a coarse cell outside the
+// refined region that shares a face with it replaces the coarse flux through
+// that face by the mean of the four fine fluxes over the same step.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_correct_u(Work wc, Work wf, LevelScratch sc, LevelScratch sf,
+                                                      T* __restrict__ Uc, const double* dt, T inv_dx) {
+  const T r = T(*dt) * inv_dx;
+  const T* Fc = (const T*)sc.F;
+  const T* Ff = (const T*)sf.F;
+  FOR_ITEMS(wc, t) {
+    int i, j, k;
+    cell_of(wc, t, i, j, k);
+    if (refined(wf, i, j, k)) continue;
+    T du[5] = {T(0), T(0), T(0), T(0), T(0)};
+    const int C[3] = {i, j, k};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+#pragma unroll
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        int D[3] = {i, j, k};
+        D[a] += sgn;
+        if (!refined(wf, D[0], D[1], D[2])) continue;
+        // the face is the lower a-face of its owner O (D above, C below)
+        const int* O = sgn > 0 ? D : C;
+        const int gc = sc.sb ? group_at(sc, O[0], O[1], O[2]) : 0;
+        if (gc < 0) continue;
+        const long long qc = slot_at(sc, O[0], O[1], O[2], gc);
+        T ff[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int Of[3] = {2 * O[0], 2 * O[1], 2 * O[2]};
+          Of[b] += q & 1;
+          Of[c] += q >> 1;
+          int In[3] = {Of[0], Of[1], Of[2]};   // a fine cell on the refined side
+          if (sgn < 0) In[a] -= 1;
+          const int gf = sf.sb ? group_at(sf, In[0], In[1], In[2]) : 0;
+          const long long qf = slot_at(sf, Of[0], Of[1], Of[2], gf < 0 ? 0 : gf);
+#pragma unroll
+          for (int m = 0; m < 5; ++m) ff[m] += Ff[((long long)a * 7 + m) * sf.NS + qf];
+        }
+#pragma unroll
+        for (int m = 0; m < 5; ++m) du[m] += T(sgn) * r * (Fc[((long long)a * 7 + m) * sc.NS + qc] - T(0.25) * ff[m]);
+      }
+    }
+    const long long pc = lin(wc, i, j, k);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Uc[m * wc.N + pc] += du[m];
+  }
+}
+
+// EMF difference on the coarse edge along Q owned by coarse cell X (its
+// lower corner edge): mean of the two fine EMFs along it minus the coarse
+// EMF, when the edge touches the refined region, else 0.
+template <typename T, int Q>
+__device__ __forceinline__ T edge_emf_jump(const Work& wf, const LevelScratch& sc, const LevelScratch& sf,
+                                           const T* __restrict__ Ec, const T* __restrict__ Ef, int x, int y, int z) {
+  constexpr int q1 = (Q + 1) % 3, q2 = (Q + 2) % 3;
+  const int X[3] = {x, y, z};
+  int Y[3] = {0, 0, 0};
+  bool touch = false;
+#pragma unroll
+  for (int s = 0; s < 4 && !touch; ++s) {
+    int Z[3] = {X[0], X[1], X[2]};
+    Z[q1] -= s & 1;
+    Z[q2] -= s >> 1;
+    if (refined(wf, Z[0], Z[1], Z[2])) {
+      touch = true;
+      Y[0] = Z[0]; Y[1] = Z[1]; Y[2] = Z[2];
+    }
+  }
+  if (!touch) return T(0);
+  const int gc = sc.sb ? group_at(sc, Y[0], Y[1], Y[2]) : 0;
+  if (gc < 0) return T(0);
+  const T ec = Ec[(long long)Q * sc.NS + slot_at(sc, X[0], X[1], X[2], gc)];
+  T ef = T(0);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int Xf[3] = {2 * X[0], 2 * X[1], 2 * X[2]};
+    Xf[Q] += h;
+    // a refined fine cell next to the fine edge gives the group whose box holds it
+    int In[3] = {2 * Y[0], 2 * Y[1], 2 * Y[2]};
+    In[Q] = Xf[Q];
+    In[q1] = Y[q1] < X[q1] ? Xf[q1] - 1 : Xf[q1];
+    In[q2] = Y[q2] < X[q2] ? Xf[q2] - 1 : Xf[q2];
+    const int gf = sf.sb ? group_at(sf, In[0], In[1], In[2]) : 0;
+    ef += Ef[(long long)Q * sf.NS + slot_at(sf, Xf[0], Xf[1], Xf[2], gf < 0 ? 0 : gf)];
+  }
+  return T(0.5) * ef - ec;
+}
+
+template <typename T, int A>
+__device__ __forceinline__ T face_emf_correction(const Work& wf, const LevelScratch& sc, const LevelScratch& sf,
+                                                 const T* __restrict__ Ec, const T* __restrict__ Ef, int x, int y,
+                                                 int z, T r) {
+  // CT update of the lower A-face of cell (x, y, z) by the edge EMF jumps
+  // (same stencil as the update of Eq. 13)
+  constexpr int b = (A + 1) % 3, c = (A + 2) % 3;
+  int Pb[3] = {x, y, z}, Pc[3] = {x, y, z};
+  Pb[b] += 1;
+  Pc[c] += 1;
+  const T dc0 = edge_emf_jump<T, c>(wf, sc, sf, Ec, Ef, x, y, z);
+  const T dc1 = edge_emf_jump<T, c>(wf, sc, sf, Ec, Ef, Pb[0], Pb[1], Pb[2]);
+  const T db0 = edge_emf_jump<T, b>(wf, sc, sf, Ec, Ef, x, y, z);
+  const T db1 = edge_emf_jump<T, b>(wf, sc, sf, Ec, Ef, Pc[0], Pc[1], Pc[2]);
+  return -r * (dc1 - dc0) + r * (db1 - db0);
+}
+
+// After the corrections: the coarse level's final fluxes on every face, and
+// its final EMFs on every edge, of a refined coarse cell take the fine means,
+// so that a correction of the next coarser level across the same interface
+// uses the finest fluxes and EMFs (the hierarchy need not be properly
+// nested).  Items: the coarse footprints of the fine groups.  Faces and edges
+// shared by refined cells are written with the same value by each of them.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_correct_registers(Work wcf, Work wf, LevelScratch sc, LevelScratch sf) {
+  T* Fc = (T*)sc.F;
+  T* Ec = (T*)sc.E;
+  const T* Ff = (const T*)sf.F;
+  const T* Ef = (const T*)sf.E;
+  FOR_ITEMS(wcf, t) {
+    int i, j, k;
+    cell_of(wcf, t, i, j, k);
+    const int gc = sc.sb ? group_at(sc, i, j, k) : 0;
+    if (gc < 0) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      // the lower and the upper a-face of cell (i, j, k)
+#pragma unroll
+      for (int up = 0; up < 2; ++up) {
+        int O[3] = {i, j, k};
+        O[a] += up;
+        T ff[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int Of[3] = {2 * O[0], 2 * O[1], 2 * O[2]};
+          Of[b] += q & 1;
+          Of[c] += q >> 1;
+          int In[3] = {Of[0], Of[1], Of[2]};
+          if (up) In[a] -= 1;    // the refined fine cell below the face
+          const int gf = sf.sb ? group_at(sf, In[0], In[1], In[2]) : 0;
+          const long long qf = slot_at(sf, Of[0], Of[1], Of[2], gf < 0 ? 0 : gf);
+#pragma unroll
+          for (int m = 0; m < 7; ++m) ff[m] += Ff[((long long)a * 7 + m) * sf.NS + qf];
+        }
+        // every listed coarse group whose box holds the face keeps a copy
+        int L[3] = {O[0], O[1], O[2]};
+        L[a] -= 1;
+        const int gs[2] = {sc.sb ? group_at(sc, O[0], O[1], O[2]) : 0, sc.sb ? group_at(sc, L[0], L[1], L[2]) : 0};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (gs[u] < 0 || (u == 1 && gs[1] == gs[0])) continue;
+          const long long qc = slot_at(sc, O[0], O[1], O[2], gs[u]);
+#pragma unroll
+          for (int m = 0; m < 7; ++m) Fc[((long long)a * 7 + m) * sc.NS + qc] = T(0.25) * ff[m];
+        }
+      }
+      // the four a-edges of cell (i, j, k): owners (i, j, k) + {0, e_b} + {0, e_c}
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int X[3] = {i, j, k};
+        X[b] += e & 1;
+        X[c] += e >> 1;
+        T ef = T(0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          int Xf[3] = {2 * X[0], 2 * X[1], 2 * X[2]};
+          Xf[a] += h;
+          int In[3] = {Xf[0], Xf[1], Xf[2]};   // a fine child of (i, j, k) next to the fine edge
+          if (e & 1) In[b] -= 1;
+          if (e >> 1) In[c] -= 1;
+          const int gf = sf.sb ? group_at(sf, In[0], In[1], In[2]) : 0;
+          ef += Ef[(long long)a * sf.NS + slot_at(sf, Xf[0], Xf[1], Xf[2], gf < 0 ? 0 : gf)];
+        }
+        // every listed coarse group whose box holds the edge keeps a copy
+        int gs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          int Z[3] = {X[0], X[1], X[2]};
+          Z[b] -= u & 1;
+          Z[c] -= u >> 1;
+          gs[u] = sc.sb ? group_at(sc, Z[0], Z[1], Z[2]) : 0;
+          bool dup = gs[u] < 0;
+#pragma unroll
+          for (int v = 0; v < u; ++v) dup = dup || gs[v] == gs[u];
+          if (!dup) Ec[(long long)a * sc.NS + slot_at(sc, X[0], X[1], X[2], gs[u])] = T(0.5) * ef;
+        }
+      }
+    }
+  }
+}
+
+// Correction of the magnetic field (Sec. 3.3): coarse faces with both cells
+// outside the refined region take the CT update of the EMF differences on
+// their edges that lie on the coarse-fine interface.  Each listed coarse
+// cell owns its lower faces, and its upper faces where the next group is not
+// listed (as in the update itself).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_correct_b(Work wc, Work wf, LevelScratch sc, LevelScratch sf,
+                                                      T* __restrict__ Bc, const double* dt, T inv_dx) {
+  const T r = T(*dt) * inv_dx;
+  const T* Ec = (const T*)sc.E;
+  const T* Ef = (const T*)sf.E;
+  FOR_ITEMS(wc, t) {
+    int i, j, k, a0, b0, c0;
+    cell_of(wc, t, i, j, k, a0, b0, c0);
+    const int pos[3] = {a0, b0, c0};
+#pragma unroll
+    for (int A = 0; A < 3; ++A) {
+#pragma unroll
+      for (int up = 0; up < 2; ++up) {
+        int H[3] = {i, j, k};   // cell above the face (its owner)
+        if (up) {
+          if (!wc.groups || pos[A] != wc.edge - 1) continue;
+          int G[3] = {i / wc.edge, j / wc.edge, k / wc.edge};
+          G[A] += 1;
+          const bool listed = wc.occ[((long long)wrapc(G[2], wc.gnz) * wc.gny + wrapc(G[1], wc.gny)) * wc.gnx +
+                                     wrapc(G[0], wc.gnx)] != 0;
+          if (listed) continue;
+          H[A] += 1;
+        }
+        int L[3] = {H[0], H[1], H[2]};
+        L[A] -= 1;
+        if (refined(wf, L[0], L[1], L[2]) || refined(wf, H[0], H[1], H[2])) continue;
+        T db;
+        if (A == 0) db = face_emf_correction<T, 0>(wf, sc, sf, Ec, Ef, H[0], H[1], H[2], r);
+        else if (A == 1) db = face_emf_correction<T, 1>(wf, sc, sf, Ec, Ef, H[0], H[1], H[2], r);
+        else db = face_emf_correction<T, 2>(wf, sc, sf, Ec, Ef, H[0], H[1], H[2], r);
+        if (db != T(0))
+          Bc[A * wc.N + lin(wc, wrapc(H[0], wc.nx), wrapc(H[1], wc.ny), wrapc(H[2], wc.nz))] += db;
+      }
     }
   }
 }

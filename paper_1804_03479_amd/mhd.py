@@ -55,7 +55,7 @@ EXPORTS = ["mhd_abi_version", "mhd_strerror", "mhd_required_ghost", "mhd_init", 
            "mhd_advance", "mhd_divB", "mhd_sums", "mhd_fallback_count", "mhd_sync",
            "mhd_profile_step", "mhd_num_stages", "mhd_stage_name",
            "mhd_mlp_num_params", "mhd_mlp_set_weights", "mhd_mlp_forward", "mhd_mlp_backward",
-           "mhd_mlp_train_step", "mhd_mlp_prepare", "mhd_mlp_face_flux", "mhd_set_capture",
+           "mhd_mlp_train_step", "mhd_mlp_prepare", "mhd_mlp_face_flux", "mhd_set_capture", "mhd_correct",
            "mhd_advance_graph", "mhd_set_launch", "mhd_cfl_dt_min", "mhd_prolong", "mhd_restrict"]
 
 
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     lib.mhd_cfl_dt_min.argtypes = [P, ctypes.POINTER(LevelDesc), P]
     lib.mhd_prolong.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc), I]
     lib.mhd_restrict.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc)]
+    lib.mhd_correct.argtypes = [P, ctypes.POINTER(LevelDesc), P, ctypes.POINTER(LevelDesc), P]
     _lib = lib
     return lib
 
@@ -255,6 +256,12 @@ class Solver:
     def prolong(self, coarse: Level, fine: Level, halo: int = 4):
         dc, df = coarse.desc(), fine.desc()
         _check(self.lib.mhd_prolong(self.h, ctypes.byref(dc), ctypes.byref(df), int(halo)), "mhd_prolong")
+
+    def correct(self, coarse: Level, fine_solver: "Solver", fine: Level, dt_dev: torch.Tensor):
+        """Coarse-fine flux and EMF correction after both levels took the step dt_dev."""
+        dc, df = coarse.desc(), fine.desc()
+        _check(self.lib.mhd_correct(self.h, ctypes.byref(dc), fine_solver.h, ctypes.byref(df),
+                                    ctypes.c_void_p(dt_dev.data_ptr())), "mhd_correct")
 
     def restrict(self, fine: Level, coarse: Level):
         dc, df = coarse.desc(), fine.desc()

@@ -192,3 +192,39 @@ def test_autotuner_picks_a_candidate_and_shapes_keep_results(tmp_path):
     b.stream.synchronize()
     for x, y in zip(a.levels, b.levels):
         assert torch.equal(x.U, y.U) and torch.equal(x.B, y.B)
+
+
+def _root_totals(h):
+    s, lv = h.solvers[0], h.levels[0]
+    t = np.array(s.sums(lv)[:5])
+    U = lv.U.double().cpu().numpy()
+    scale = np.array([np.abs(U[m]).sum() for m in range(5)]) * lv.dx ** 3
+    return t, scale
+
+
+@pytest.mark.parametrize("counts", [[5], [5, 9]])
+def test_correction_conserves_root_totals_and_div_b(counts):
+    # Sec. 3.3 correction operation: with the coarse-fine flux and EMF
+    # corrections and restriction, the root's totals change only by
+    # round-off and its div B stays at round-off; without them they do not
+    h = Hierarchy(32, counts, prec="f64", noise=0.1, seed=1)
+    t0, scale = _root_totals(h)
+    for _ in range(3):
+        h.step()
+    h.stream.synchronize()
+    t1, _ = _root_totals(h)
+    drift = np.abs(t1 - t0) / scale
+    assert drift.max() <= 1e-13, drift
+    for lvl_i, lv in enumerate(h.levels):
+        mx, _ = h.solvers[lvl_i].divb(lv)
+        assert mx * lv.dx <= 1e-12, (lvl_i, mx)
+    h.close()
+    u = Hierarchy(32, counts, prec="f64", noise=0.1, seed=1, correct=False)
+    for _ in range(3):
+        u.step()
+    u.stream.synchronize()
+    t2, _ = _root_totals(u)
+    mxu, _ = u.solvers[0].divb(u.levels[0])
+    assert (np.abs(t2 - t0) / scale)[[0, 4]].max() > 1e-10
+    assert mxu * u.levels[0].dx > 1e-10
+    u.close()
