@@ -155,10 +155,14 @@ int mhd_cfl_dt_min(mhd_ctx ctx, const mhd_level* lv, double* dt_dev);
  * coarse one; with a list, fills the ghost halo (halo cells around each listed
  * group, plus one above) of the listed groups: cells outside every listed
  * group, and faces whose two cells are both outside.  Density and momentum are
- * injected (the children average to the parent), the energy is rebuilt from
- * the parent's pressure with the child's field; a fine face on a coarse face
- * takes its value, a fine face inside a coarse cell the mean of the two coarse
- * faces bracketing it, so each fine cell's divergence equals its parent's.
+ * injected; the energy is e_parent + (|b_child|^2 - <|b|^2>)/2 over the eight
+ * children (conservative; where the common child pressure would not be
+ * positive, the parent's pressure is kept).  Face field: Balsara's
+ * divergence-free reconstruction -- fine faces on a coarse face follow its
+ * MC-limited linear profile, fine faces inside a coarse cell the quadratic
+ * field matching the cell's six face profiles with no linear divergence
+ * terms -- so each fine cell's divergence equals its parent's and the fine
+ * faces on a coarse face average to it.
  * mhd_restrict: coarse cells under the listed fine groups (all cells with no
  * list) take the mean of their eight children, and the coarse faces of those
  * cells, including the faces on the boundary of the refined region, the mean

@@ -709,15 +709,26 @@ mhd_level whole_grid(const mhd_level* lv) {
 template <typename T>
 void launch_prolong(mhd_ctx_s* c, const mhd_level* coarse, const mhd_level* fine, int halo) {
   const mhd_level cw = whole_grid(coarse);
-  const Work wc = make_work(&cw, 0, 0);
+  Work wc = make_work(&cw, 0, 0);
+  Work wf = make_work(fine, 0, 0);
   if (fine->groups && fine->n_groups > 0) {
-    Work wf = make_work(fine, halo, halo + 1);
+    // items: the coarse cells over each fine group's halo box (fine cells
+    // [o - halo, o + edge + halo + 1) need coarse [o/2 - lo, o/2 + edge/2 + hi))
     wf.occ = c->occ;
-    k_prolong_ghosts<T><<<sblocks(wf), kBlock, 0, c->stream>>>(wc, wf, (const T*)coarse->U, (const T*)coarse->B,
+    wf.halo = halo;
+    const int lo = (halo + 1) / 2, hi = (halo + 2) / 2;
+    wc.groups = fine->groups;
+    wc.oshift = 1;
+    wc.edge = fine->group_edge / 2;
+    wc.halo = lo;
+    wc.box = fine->group_edge / 2 + lo + hi;
+    wc.items = (long long)fine->n_groups * wc.box * wc.box * wc.box;
+    wc.n_dev = fine->n_groups_dev;
+    wc.gnx = wc.gny = wc.gnz = 0;
+    k_prolong_ghosts<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, (const T*)coarse->U, (const T*)coarse->B,
                                                                (T*)fine->U, (T*)fine->B, (T)c->cfg.gamma);
   } else {
-    const Work wf = make_work(fine, 0, 0);
-    k_prolong_all<T><<<sblocks(wf), kBlock, 0, c->stream>>>(wc, wf, (const T*)coarse->U, (const T*)coarse->B,
+    k_prolong_all<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, (const T*)coarse->U, (const T*)coarse->B,
                                                             (T*)fine->U, (T*)fine->B, (T)c->cfg.gamma);
   }
 }

@@ -844,86 +844,180 @@ __global__ void __launch_bounds__(kBlock) k_occ_set(int* occ, const int* groups,
 }
 
 // ------------------------------------------------------------ AMR support
+__device__ __forceinline__ int wrap_delta(int d, int n) { return d > n / 2 ? d - n : (d < -(n / 2) ? d + n : d); }
+
 // Prolongation from a coarse level (nc) to a fine level (2 nc), paper
 // Sec. 3.3 (refinement operation).  Cell data: density and momentum are
 // injected (conservative: the 8 children average to the parent); the energy
 // is rebuilt from the parent's pressure and kinetic energy with the child's
-// own face field, which keeps the pressure positive.  Face field: a fine face
-// lying on a coarse face takes the coarse value; a fine face inside a coarse
-// cell takes the mean of the two coarse faces bracketing it.  Every fine
-// cell's discrete divergence then equals its parent's (zero for a solenoidal
-// coarse field) and the area average of fine faces equals the coarse face.
-// (A first-order, divergence-free stand-in for Balsara's second-order
-// reconstruction.)
+// own face field, which keeps the pressure positive.
+// Face field (Balsara's divergence-free reconstruction, in 3D): a coarse
+// face carries a linear profile B + S_t1 t1 + S_t2 t2 in its transverse
+// coordinates (coarse-cell units, t in [-1/2, 1/2]) with MC-limited slopes
+// of the same face component across its neighbouring coarse faces; fine
+// faces on it take the profile at their centres (t = -+1/4).  Inside the
+// coarse cell the field is the quadratic whose face profiles match the six
+// coarse faces and whose divergence has no linear terms; the fine faces on
+// the mid-planes take Bx(0, y, z) = a0 + ay y + az z with
+// a0 = (Bx- + Bx+)/2 - axx/4, axx = -(bxy + cxz)/2 (bxy, cxz: the jumps of
+// the x-slopes of By, Bz across the cell) and ay, az the mean transverse
+// slopes of the two x-faces (and cyclic).  Every fine cell's divergence
+// equals its parent's; the fine faces on a coarse face average to it.
+
+// MC-limited slope of coarse face component C at coarse cell (i, j, k) along axis X
+template <typename T, int C, int X>
+__device__ __forceinline__ T coarse_face_slope(const Work& wc, const T* __restrict__ Bc, int i, int j, int k) {
+  const T* Bcc = Bc + (long long)C * wc.N;
+  const T v = Bcc[lin(wc, wrapc(i, wc.nx), wrapc(j, wc.ny), wrapc(k, wc.nz))];
+  const T up = Bcc[lin(wc, wrapc(i + (X == 0), wc.nx), wrapc(j + (X == 1), wc.ny), wrapc(k + (X == 2), wc.nz))];
+  const T dn = Bcc[lin(wc, wrapc(i - (X == 0), wc.nx), wrapc(j - (X == 1), wc.ny), wrapc(k - (X == 2), wc.nz))];
+  return mc_slope(dn, v, up);
+}
+
 template <typename T, int A>
 __device__ __forceinline__ T prolong_face(const Work& wc, const T* __restrict__ Bc, int I, int J, int K) {
-  const int cf[3] = {I >> 1, J >> 1, K >> 1};
-  const int odd = (A == 0 ? I : (A == 1 ? J : K)) & 1;
-  const long long lo = lin(wc, cf[0], cf[1], cf[2]);
-  const T b0 = Bc[A * wc.N + lo];
-  if (!odd) return b0;
-  const long long hi = nbr(wc, cf[0], cf[1], cf[2], A == 0, A == 1, A == 2);
-  return T(0.5) * (b0 + Bc[A * wc.N + hi]);
+  constexpr int b = (A + 1) % 3, c = (A + 2) % 3;
+  const int f[3] = {I, J, K};
+  const int i = I >> 1, j = J >> 1, k = K >> 1;
+  const T tb = (f[b] & 1) ? T(0.25) : T(-0.25);
+  const T tc = (f[c] & 1) ? T(0.25) : T(-0.25);
+  const T* Ba = Bc + (long long)A * wc.N;
+  if (!(f[A] & 1)) {
+    // on the lower A-face of coarse cell (i, j, k)
+    return Ba[lin(wc, i, j, k)] + coarse_face_slope<T, A, b>(wc, Bc, i, j, k) * tb +
+           coarse_face_slope<T, A, c>(wc, Bc, i, j, k) * tc;
+  }
+  // on the mid-plane of coarse cell (i, j, k)
+  const int u[3] = {i + (A == 0), j + (A == 1), k + (A == 2)};     // cell above in A
+  const int ub[3] = {i + (b == 0), j + (b == 1), k + (b == 2)};    // cell above in b
+  const int uc[3] = {i + (c == 0), j + (c == 1), k + (c == 2)};    // cell above in c
+  const T lo = Ba[lin(wc, i, j, k)];
+  const T hi = Ba[lin(wc, wrapc(u[0], wc.nx), wrapc(u[1], wc.ny), wrapc(u[2], wc.nz))];
+  const T ab = T(0.5) * (coarse_face_slope<T, A, b>(wc, Bc, i, j, k) + coarse_face_slope<T, A, b>(wc, Bc, u[0], u[1], u[2]));
+  const T ac = T(0.5) * (coarse_face_slope<T, A, c>(wc, Bc, i, j, k) + coarse_face_slope<T, A, c>(wc, Bc, u[0], u[1], u[2]));
+  const T bxy = coarse_face_slope<T, b, A>(wc, Bc, ub[0], ub[1], ub[2]) - coarse_face_slope<T, b, A>(wc, Bc, i, j, k);
+  const T cxz = coarse_face_slope<T, c, A>(wc, Bc, uc[0], uc[1], uc[2]) - coarse_face_slope<T, c, A>(wc, Bc, i, j, k);
+  const T axx = T(-0.5) * (bxy + cxz);
+  const T a0 = T(0.5) * (lo + hi) - T(0.25) * axx;
+  return a0 + ab * tb + ac * tc;
 }
 
-// fill fine cell (I, J, K) and, where allowed, its three lower faces
+// The eight children of coarse cell (i, j, k): conservative cell data and
+// their lower faces, where allowed.  cell_ok[q] / face_ok[q][A] say which
+// child q = a + 2 b + 4 c (position (a, b, c) in the parent) and which of its
+// lower faces may be written.  The children's energies are
+// e_parent + (|b_child|^2 - <|b|^2>)/2 (they average to the parent's); where
+// the resulting common pressure would not be positive the parent's pressure
+// is kept instead.
 template <typename T>
-__device__ __forceinline__ void prolong_cell(const Work& wc, const Work& wf, const T* __restrict__ Uc,
-                                             const T* __restrict__ Bc, T* __restrict__ Uf, T* __restrict__ Bf,
-                                             int I, int J, int K, bool cell, const bool face[3], T gam) {
-  const long long pc = lin(wc, I >> 1, J >> 1, K >> 1);
-  const long long pf = lin(wf, I, J, K);
-  if (face[0]) Bf[pf] = prolong_face<T, 0>(wc, Bc, I, J, K);
-  if (face[1]) Bf[wf.N + pf] = prolong_face<T, 1>(wc, Bc, I, J, K);
-  if (face[2]) Bf[2 * wf.N + pf] = prolong_face<T, 2>(wc, Bc, I, J, K);
-  if (!cell) return;
-  const T bx = T(0.5) * (prolong_face<T, 0>(wc, Bc, I, J, K) + prolong_face<T, 0>(wc, Bc, wrapc(I + 1, wf.nx), J, K));
-  const T by = T(0.5) * (prolong_face<T, 1>(wc, Bc, I, J, K) + prolong_face<T, 1>(wc, Bc, I, wrapc(J + 1, wf.ny), K));
-  const T bz = T(0.5) * (prolong_face<T, 2>(wc, Bc, I, J, K) + prolong_face<T, 2>(wc, Bc, I, J, wrapc(K + 1, wf.nz)));
-  // parent's pressure (cell-centred parent field)
-  const int ci = I >> 1, cj = J >> 1, ck = K >> 1;
-  const T cbx = T(0.5) * (Bc[pc] + Bc[nbr(wc, ci, cj, ck, 1, 0, 0)]);
-  const T cby = T(0.5) * (Bc[wc.N + pc] + Bc[wc.N + nbr(wc, ci, cj, ck, 0, 1, 0)]);
-  const T cbz = T(0.5) * (Bc[2 * wc.N + pc] + Bc[2 * wc.N + nbr(wc, ci, cj, ck, 0, 0, 1)]);
-  const T d = Uc[pc], mx = Uc[wc.N + pc], my = Uc[2 * wc.N + pc], mz = Uc[3 * wc.N + pc];
+__device__ __forceinline__ void prolong_parent(const Work& wc, const Work& wf, const T* __restrict__ Uc,
+                                               const T* __restrict__ Bc, T* __restrict__ Uf, T* __restrict__ Bf,
+                                               int i, int j, int k, const bool cell_ok[8], const bool face_ok[8][3],
+                                               T gam) {
+  // fine faces of the parent: fx[p][q] on the x-plane 2i + p (p = 0, 1, 2), transverse child q = b + 2 c
+  T fx[3][4], fy[3][4], fz[3][4];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int u = q & 1, v = q >> 1;
+      // plane 2 is the next parent's lower face: periodic wrap of the fine index
+      fx[p][q] = prolong_face<T, 0>(wc, Bc, wrapc(2 * i + p, wf.nx), 2 * j + u, 2 * k + v);
+      fy[p][q] = prolong_face<T, 1>(wc, Bc, 2 * i + v, wrapc(2 * j + p, wf.ny), 2 * k + u);   // (z, x) transverse
+      fz[p][q] = prolong_face<T, 2>(wc, Bc, 2 * i + u, 2 * j + v, wrapc(2 * k + p, wf.nz));   // (x, y) transverse
+    }
+  T b2[8];
+  T bc[8][3];
+  T mean_b2 = T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+    bc[q][0] = T(0.5) * (fx[a][b + 2 * c] + fx[a + 1][b + 2 * c]);
+    bc[q][1] = T(0.5) * (fy[b][c + 2 * a] + fy[b + 1][c + 2 * a]);
+    bc[q][2] = T(0.5) * (fz[c][a + 2 * b] + fz[c + 1][a + 2 * b]);
+    b2[q] = bc[q][0] * bc[q][0] + bc[q][1] * bc[q][1] + bc[q][2] * bc[q][2];
+    mean_b2 += b2[q];
+  }
+  mean_b2 *= T(0.125);
+  const long long pc = lin(wc, i, j, k);
+  const T cbx = T(0.5) * (Bc[pc] + Bc[nbr(wc, i, j, k, 1, 0, 0)]);
+  const T cby = T(0.5) * (Bc[wc.N + pc] + Bc[wc.N + nbr(wc, i, j, k, 0, 1, 0)]);
+  const T cbz = T(0.5) * (Bc[2 * wc.N + pc] + Bc[2 * wc.N + nbr(wc, i, j, k, 0, 0, 1)]);
+  const T b2c = cbx * cbx + cby * cby + cbz * cbz;
+  const T d = Uc[pc], mx = Uc[wc.N + pc], my = Uc[2 * wc.N + pc], mz = Uc[3 * wc.N + pc], e = Uc[4 * wc.N + pc];
   const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / d;
-  const T pr = (gam - T(1)) * (Uc[4 * wc.N + pc] - ek - T(0.5) * (cbx * cbx + cby * cby + cbz * cbz));
-  Uf[pf] = d;
-  Uf[wf.N + pf] = mx;
-  Uf[2 * wf.N + pf] = my;
-  Uf[3 * wf.N + pf] = mz;
-  Uf[4 * wf.N + pf] = pr / (gam - T(1)) + ek + T(0.5) * (bx * bx + by * by + bz * bz);
+  const T pr = (gam - T(1)) * (e - ek - T(0.5) * b2c);
+  const bool conservative = pr - (gam - T(1)) * T(0.5) * (mean_b2 - b2c) > T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+    const long long pf = lin(wf, 2 * i + a, 2 * j + b, 2 * k + c);
+    if (cell_ok[q]) {
+      Uf[pf] = d;
+      Uf[wf.N + pf] = mx;
+      Uf[2 * wf.N + pf] = my;
+      Uf[3 * wf.N + pf] = mz;
+      Uf[4 * wf.N + pf] = conservative ? e + T(0.5) * (b2[q] - mean_b2) : pr / (gam - T(1)) + ek + T(0.5) * b2[q];
+    }
+    if (face_ok[q][0]) Bf[pf] = fx[a][b + 2 * c];
+    if (face_ok[q][1]) Bf[wf.N + pf] = fy[b][c + 2 * a];
+    if (face_ok[q][2]) Bf[2 * wf.N + pf] = fz[c][a + 2 * b];
+  }
 }
 
-// whole fine level from the coarse level
+// whole fine level from the coarse level: one coarse cell per item
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_all(Work wc, Work wf, const T* __restrict__ Uc,
                                                         const T* __restrict__ Bc, T* __restrict__ Uf,
                                                         T* __restrict__ Bf, T gam) {
-  const bool all3[3] = {true, true, true};
-  FOR_ITEMS(wf, t) {
-    int I, J, K;
-    cell_of(wf, t, I, J, K);
-    prolong_cell(wc, wf, Uc, Bc, Uf, Bf, I, J, K, true, all3, gam);
+  bool cell_ok[8], face_ok[8][3];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    cell_ok[q] = true;
+    face_ok[q][0] = face_ok[q][1] = face_ok[q][2] = true;
+  }
+  FOR_ITEMS(wc, t) {
+    int i, j, k;
+    cell_of(wc, t, i, j, k);
+    prolong_parent(wc, wf, Uc, Bc, Uf, Bf, i, j, k, cell_ok, face_ok, gam);
   }
 }
 
-// ghost halos of the listed fine groups: cells outside every listed group,
-// and faces whose two cells are both outside every listed group
+// ghost halos of the listed fine groups: items are the coarse cells over the
+// halo boxes; a child is written when it lies outside every listed group, a
+// child's lower face when both cells of that face do
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_ghosts(Work wc, Work wf, const T* __restrict__ Uc,
                                                            const T* __restrict__ Bc, T* __restrict__ Uf,
                                                            T* __restrict__ Bf, T gam) {
-  FOR_ITEMS(wf, t) {
-    int I, J, K;
-    cell_of(wf, t, I, J, K);
+  const long long per = (long long)wc.box * wc.box * wc.box;
+  FOR_ITEMS(wc, t) {
+    int i, j, k;
+    cell_of(wc, t, i, j, k);
     auto listed = [&](int x, int y, int z) {
       x = wrapc(x, wf.nx); y = wrapc(y, wf.ny); z = wrapc(z, wf.nz);
       return wf.occ[((long long)(z / wf.edge) * wf.gny + y / wf.edge) * wf.gnx + x / wf.edge] != 0;
     };
-    const bool ghost = !listed(I, J, K);
-    const bool face[3] = {ghost && !listed(I - 1, J, K), ghost && !listed(I, J - 1, K), ghost && !listed(I, J, K - 1)};
-    if (ghost) prolong_cell(wc, wf, Uc, Bc, Uf, Bf, I, J, K, true, face, gam);
+    // children inside the requested fine halo box [o - halo, o + edge + halo + 1) of this item's group
+    const int* o = wf.groups + 3 * (t / per);
+    auto in_box = [&](int x, int y, int z) {
+      const int dx = wrap_delta(x - o[0], wf.nx), dy = wrap_delta(y - o[1], wf.ny), dz = wrap_delta(z - o[2], wf.nz);
+      const int lo = -wf.halo, hi = wf.edge + wf.halo + 1;
+      return dx >= lo && dx < hi && dy >= lo && dy < hi && dz >= lo && dz < hi;
+    };
+    bool cell_ok[8], face_ok[8][3];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int I = 2 * i + (q & 1), J = 2 * j + ((q >> 1) & 1), K = 2 * k + (q >> 2);
+      const bool ghost = !listed(I, J, K) && in_box(I, J, K);
+      cell_ok[q] = ghost;
+      face_ok[q][0] = ghost && !listed(I - 1, J, K);
+      face_ok[q][1] = ghost && !listed(I, J - 1, K);
+      face_ok[q][2] = ghost && !listed(I, J, K - 1);
+      any = any || ghost;
+    }
+    if (any) prolong_parent(wc, wf, Uc, Bc, Uf, Bf, i, j, k, cell_ok, face_ok, gam);
   }
 }
 
@@ -999,7 +1093,6 @@ struct LevelScratch {
   int edge, gnx, gny, gnz, nx, ny, nz;
 };
 
-__device__ __forceinline__ int wrap_delta(int d, int n) { return d > n / 2 ? d - n : (d < -(n / 2) ? d + n : d); }
 
 // listed group holding cell (i, j, k) of the level, or -1
 __device__ __forceinline__ int group_at(const LevelScratch& v, int i, int j, int k) {
