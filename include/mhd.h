@@ -144,9 +144,16 @@ int mhd_advance_graph(mhd_ctx ctx, const mhd_level* lv, double* dt_dev, double* 
  * mhd_divB and mhd_sums keep their fixed shape (bitwise-stable results). */
 int mhd_set_launch(mhd_ctx ctx, int blocks_per_cu);
 
-/* Minimum of the level's CFL time step and *dt_dev, written to *dt_dev (a
- * shared step for several levels, without a host sync). */
-int mhd_cfl_dt_min(mhd_ctx ctx, const mhd_level* lv, double* dt_dev);
+/* Minimum of scale times the level's CFL time step and *dt_dev, written to
+ * *dt_dev, without a host sync: scale 1 on every level gives a shared step;
+ * scale 2^l on level l gives the root step of a hierarchy whose level l takes
+ * 2^l sub-steps (paper Sec. 3.3, adaptive time steps).  scale must be
+ * positive and finite. */
+int mhd_cfl_dt_min(mhd_ctx ctx, const mhd_level* lv, double scale, double* dt_dev);
+
+/* *dt_fine = *dt_coarse / parts on the device (the step of a level that
+ * sub-cycles parts times inside its parent's step); parts >= 1. */
+int mhd_dt_subdivide(mhd_ctx ctx, const double* dt_coarse, int parts, double* dt_fine);
 
 /* AMR support between a coarse level and a fine level of twice its cells per
  * dimension (paper Sec. 3.3).  The coarse level is read (prolong) or written
@@ -168,11 +175,36 @@ int mhd_cfl_dt_min(mhd_ctx ctx, const mhd_level* lv, double* dt_dev);
  * cells, including the faces on the boundary of the refined region, the mean
  * of the four fine faces on them.  Not for MHD_F32_MIXED. */
 int mhd_prolong(mhd_ctx ctx, const mhd_level* coarse, const mhd_level* fine, int halo);
+
+/* mhd_prolong from the coarse data interpolated linearly in time,
+ * old + alpha (new - old), with coarse_old the parent's state at the start of
+ * its step and coarse its state at the end: the ghosts of a fine level at an
+ * intermediate time of a sub-cycled step (paper Sec. 3.3: finer levels are
+ * evolved until they reach the parent's time).  alpha in [0, 1]; alpha = 0
+ * reads coarse_old alone, alpha = 1 coarse alone (coarse_old may then be
+ * NULL).  coarse_old must have coarse's shape and cell width; it is read
+ * only. */
+int mhd_prolong_time(mhd_ctx ctx, const mhd_level* coarse_old, const mhd_level* coarse, double alpha,
+                     const mhd_level* fine, int halo);
+
+/* Time-averaged coarse-fine registers of a sub-cycled level: R = weight S
+ * (reset != 0) or R + weight S, with S the final fluxes and EMFs of ctx's
+ * last update of lv, over the faces and edges of each listed group (every
+ * face and edge without a list).  After the sub-steps of one parent step
+ * (weight 1/parts each, the first with reset), mhd_correct with
+ * fine_registers = 1 corrects the parent with the time mean.  The registers
+ * live in ctx (21 + 3 arrays of its scratch size, allocated on the first
+ * reset call that needs them; a call with reset == 0 before that fails with
+ * MHD_ERR_INVALID_ARG).  Not for MHD_F32_MIXED. */
+int mhd_accumulate_registers(mhd_ctx ctx, const mhd_level* lv, double weight, int reset);
 int mhd_restrict(mhd_ctx ctx, const mhd_level* fine, const mhd_level* coarse);
 
 /* Correction operation of paper Sec. 3.3 across a coarse-fine interface,
- * after both levels were updated by one step of the same dt (*dt_dev, device
- * double): a coarse cell outside the refined region that shares a face with
+ * after the coarse level took one step *dt_dev (device double) and the fine
+ * level the same time span, in one step (fine_registers = 0: the fine
+ * values are those of ctx_fine's last update) or in sub-steps
+ * (fine_registers = 1: the time mean kept by mhd_accumulate_registers): a
+ * coarse cell outside the refined region that shares a face with
  * it replaces the coarse flux through that face by the mean of the four fine
  * fluxes; a coarse face with both cells outside takes the CT update of the
  * EMF differences (mean of the two fine EMFs minus the coarse EMF) on its
@@ -181,13 +213,14 @@ int mhd_restrict(mhd_ctx ctx, const mhd_level* fine, const mhd_level* coarse);
  * context's stored final fluxes and EMFs on the faces and edges of refined
  * cells become the fine means, so that correcting the next coarser level
  * across a shared interface uses the finest values (no proper-nesting
- * requirement).  ctx_coarse and
+ * requirement); a sub-cycled coarse level accumulates its registers after
+ * this call.  ctx_coarse and
  * ctx_fine must be the contexts that ran those updates (their stage scratch
  * holds the final fluxes and EMFs), on the same stream, with the same scheme
  * and precision; the fine groups must lie inside listed coarse groups when
  * the coarse level has a list.  Not for MHD_F32_MIXED. */
 int mhd_correct(mhd_ctx ctx_coarse, const mhd_level* coarse, mhd_ctx ctx_fine, const mhd_level* fine,
-                const double* dt_dev);
+                const double* dt_dev, int fine_registers);
 
 /* Discrete divergence of Eq. 16 in double: max |div B| and the mean of
  * |div B| over the level's cells.  Synchronises. */

@@ -2,17 +2,35 @@
 
 Each level l holds a dense (n 2^l)^3 grid in HBM; only the listed patch groups
 of a refined level are updated, and the cells around them are ghosts refilled
-from the coarser level before each update (paper Sec. 3.3).  One step of the
-hierarchy (shared time step, no sub-cycling):
+from the coarser level before each update (paper Sec. 3.3).
+
+Shared time step (subcycle=False), one step of every level:
 
   dt = min over levels of the CFL step          (mhd_cfl_dt_min, on device)
   for each level, coarse to fine:
       refill the ghost halos from the parent    (mhd_prolong, list mode)
-      update the listed groups                  (mhd_step_devdt)
+  for each level: update the listed groups      (mhd_step_devdt)
   for each level, fine to coarse:
       correct the parent at the coarse-fine interface with the level's
       fluxes and EMFs                           (mhd_correct)
       restrict the level onto its parent        (mhd_restrict)
+
+Sub-cycled (subcycle=True; Sec. 3.3's update of level l: update l, evolve
+l + 1 until it reaches l's time, correct l, here with a refinement ratio of
+2 in time): dt_0 = min over l of 2^l times level l's CFL step, dt_l =
+dt_{l-1} / 2, and
+
+  advance(l):
+      keep level l's state at the start of its step   (copy, levels with children)
+      update level l by dt_l
+      for the two sub-steps s = 0, 1 of level l + 1:
+          refill l + 1's ghosts from l at time fraction s/2
+              (old + s/2 (new - old); mhd_prolong_time)
+          advance(l + 1)
+          add half of l + 1's final fluxes and EMFs to its registers
+              (mhd_accumulate_registers)
+      correct l with the time-mean registers (mhd_correct, fine_registers)
+      restrict l + 1 onto l
 
 Group lists are chosen with a seeded generator and are octree-consistent:
 every group of level l + 1 lies inside a group of level l.
@@ -55,9 +73,10 @@ class Hierarchy:
 
     def __init__(self, n_root: int, counts, scheme="ctu", recon="ppm", riemann="hlld", prec="f32",
                  noise: float = 0.1, seed: int = 0, edge: int = 16, stream: torch.cuda.Stream | None = None,
-                 correct: bool = True):
+                 correct: bool = True, subcycle: bool = False):
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.correct = correct
+        self.subcycle = subcycle
         self.groups = nested_groups(n_root, counts, edge, seed)
         with torch.cuda.stream(self.stream):
             self.solvers = [Solver(scheme, recon, riemann, prec, stream=self.stream)
@@ -77,7 +96,14 @@ class Hierarchy:
                 fine.set_groups(torch.from_numpy(g).cuda())
                 fine.group_edge = edge
                 self.levels.append(fine)
-            self.dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+            # per-level steps (all equal without sub-cycling); dt is the root's
+            self.dts = torch.zeros(len(self.levels), dtype=torch.float64, device="cuda")
+            self.dt = self.dts[:1]
+            # a level's state at the start of its step, for its children's ghosts
+            self.old = []
+            if subcycle:
+                for lv in self.levels[:-1]:
+                    self.old.append(Level(torch.empty_like(lv.U), torch.empty_like(lv.B), lv.dx))
         self.stream.synchronize()
 
     @property
@@ -90,34 +116,72 @@ class Hierarchy:
             out.append(len(g) * lv.group_edge ** 3)
         return out
 
+    def updates_per_step(self):
+        """Cell updates of each level in one root step (2^l sub-steps on level l
+        when sub-cycling)."""
+        return [c << (l if self.subcycle else 0) for l, c in enumerate(self.cells_per_level())]
+
     def set_launch(self, shapes):
         """Blocks per CU of each level's persistent launches (0 = one item per thread)."""
         for s, b in zip(self.solvers, shapes):
             s.set_launch(int(b))
 
     def shared_dt(self):
+        """Device steps of all levels: the shared CFL minimum, or with
+        sub-cycling dt_0 = min_l 2^l dt_cfl(l) and dt_l = dt_0 / 2^l."""
         with torch.cuda.stream(self.stream):
-            self.dt.fill_(float("inf"))
-            for s, lv in zip(self.solvers, self.levels):
-                s.cfl_dt_min(lv, self.dt)
+            d0 = self.dts[:1]
+            d0.fill_(float("inf"))
+            for lvl, (s, lv) in enumerate(zip(self.solvers, self.levels)):
+                s.cfl_dt_min(lv, d0, scale=float(1 << lvl) if self.subcycle else 1.0)
+            for lvl in range(1, len(self.levels)):
+                self.s.dt_subdivide(self.dts[lvl - 1:lvl], 2 if self.subcycle else 1, self.dts[lvl:lvl + 1])
 
     def update_level(self, lvl: int):
         """Ghost refill from the parent (refined levels) and the update of level lvl."""
         s, lv = self.solvers[lvl], self.levels[lvl]
         if lvl > 0:
             s.prolong(self.levels[lvl - 1], lv, halo=4)
-        s.step_devdt(lv, self.dt)
+        s.step_devdt(lv, self.dts[lvl:lvl + 1])
+
+    def _close_level(self, lvl: int, registers: bool):
+        """Correction of level lvl - 1 by level lvl, then the restriction."""
+        if self.correct:
+            self.solvers[lvl - 1].correct(self.levels[lvl - 1], self.solvers[lvl], self.levels[lvl],
+                                          self.dts[lvl - 1:lvl], fine_registers=registers)
+        self.solvers[lvl].restrict(self.levels[lvl], self.levels[lvl - 1])
+
+    def _advance(self, lvl: int):
+        s, lv = self.solvers[lvl], self.levels[lvl]
+        last = lvl == len(self.levels) - 1
+        if not last:
+            old = self.old[lvl]
+            old.U.copy_(lv.U)
+            old.B.copy_(lv.B)
+        s.step_devdt(lv, self.dts[lvl:lvl + 1])
+        if last:
+            return
+        child, cs = self.levels[lvl + 1], self.solvers[lvl + 1]
+        for sub in range(2):
+            cs.prolong(lv, child, halo=4, coarse_old=self.old[lvl], alpha=0.5 * sub)
+            self._advance(lvl + 1)
+            if self.correct:
+                cs.accumulate_registers(child, 0.5, reset=sub == 0)
+        self._close_level(lvl + 1, registers=True)
 
     def step(self):
-        """One shared-dt step of all levels (asynchronous on self.stream)."""
+        """One root step of all levels (asynchronous on self.stream)."""
         with torch.cuda.stream(self.stream):
             self.shared_dt()
+            if self.subcycle:
+                self._advance(0)
+                return
+            for lvl in range(1, len(self.levels)):
+                self.solvers[lvl].prolong(self.levels[lvl - 1], self.levels[lvl], halo=4)
             for lvl in range(len(self.levels)):
-                self.update_level(lvl)
+                self.solvers[lvl].step_devdt(self.levels[lvl], self.dts[lvl:lvl + 1])
             for lvl in range(len(self.levels) - 1, 0, -1):
-                if self.correct:
-                    self.solvers[lvl - 1].correct(self.levels[lvl - 1], self.solvers[lvl], self.levels[lvl], self.dt)
-                self.solvers[lvl].restrict(self.levels[lvl], self.levels[lvl - 1])
+                self._close_level(lvl, registers=False)
 
     def capture(self):
         """Capture one step() into a HIP graph (torch.cuda.CUDAGraph); returns it.

@@ -40,6 +40,9 @@ struct mhd_ctx_s {
   void* QR;               // CTU: 21 * cap, states above each face
   void* F2;               // CTU: 21 * cap, corrector fluxes
   void* Qc;               // learned flux: 14 * cap, corrected states of one direction
+  void* RF;               // time-averaged final fluxes of a sub-cycled level: 21 * cap_reg
+  void* RE;               // time-averaged final EMFs: 3 * cap_reg
+  long long cap_reg;
   double* parts;          // reduction partials
   double* dres;           // 8 device doubles of reduction results
   unsigned long long* smax;
@@ -484,6 +487,8 @@ int mhd_finalize(mhd_ctx c) {
   free_scratch(c);
   hipFree(c->mlpw);
   hipFree(c->mlp_ws);
+  hipFree(c->RF);
+  hipFree(c->RE);
   hipFree(c->parts); hipFree(c->dres); hipFree(c->smax); hipFree(c->flag); hipFree(c->nfb); hipFree(c->occ);
   if (c->host) hipHostFree(c->host);
   delete c;
@@ -664,8 +669,8 @@ int mhd_advance_graph(mhd_ctx c, const mhd_level* lv, double* dt_dev, double* t_
   return hipGraphLaunch(c->graph_exec, c->stream) == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 
-int mhd_cfl_dt_min(mhd_ctx c, const mhd_level* lv, double* dt_dev) {
-  if (!c || !dt_dev) return MHD_ERR_INVALID_ARG;
+int mhd_cfl_dt_min(mhd_ctx c, const mhd_level* lv, double scale, double* dt_dev) {
+  if (!c || !dt_dev || !(scale > 0.0 && std::isfinite(scale))) return MHD_ERR_INVALID_ARG;
   int rc = check_level(c, lv);
   if (rc) return rc;
   const Work w = make_work(lv, 0, 0);
@@ -680,7 +685,7 @@ int mhd_cfl_dt_min(mhd_ctx c, const mhd_level* lv, double* dt_dev) {
   else
     k_cfl<float, true><<<nblocks(w), kBlock, 0, c->stream>>>(w, (const float*)lv->U, (const float*)lv->B, mix,
                                                               (float)c->cfg.gamma, c->smax, c->flag);
-  k_min_dt<<<1, 1, 0, c->stream>>>(c->smax, c->cfg.courant * lv->dx, dt_dev);
+  k_min_dt<<<1, 1, 0, c->stream>>>(c->smax, c->cfg.courant * lv->dx * scale, dt_dev);
   return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 
@@ -707,7 +712,13 @@ mhd_level whole_grid(const mhd_level* lv) {
 }
 
 template <typename T>
-void launch_prolong(mhd_ctx_s* c, const mhd_level* coarse, const mhd_level* fine, int halo) {
+void launch_prolong(mhd_ctx_s* c, const mhd_level* coarse_old, const mhd_level* coarse, double alpha,
+                    const mhd_level* fine, int halo) {
+  // alpha = 0: the old state alone; alpha = 1: the new state alone
+  const bool interp = coarse_old && alpha > 0.0 && alpha < 1.0;
+  const mhd_level* first = (coarse_old && alpha == 0.0) ? coarse_old : coarse;
+  const Coarse<T> Uc{(const T*)(interp ? coarse_old->U : first->U), interp ? (const T*)coarse->U : nullptr, (T)alpha};
+  const Coarse<T> Bc{(const T*)(interp ? coarse_old->B : first->B), interp ? (const T*)coarse->B : nullptr, (T)alpha};
   const mhd_level cw = whole_grid(coarse);
   Work wc = make_work(&cw, 0, 0);
   Work wf = make_work(fine, 0, 0);
@@ -725,11 +736,11 @@ void launch_prolong(mhd_ctx_s* c, const mhd_level* coarse, const mhd_level* fine
     wc.items = (long long)fine->n_groups * wc.box * wc.box * wc.box;
     wc.n_dev = fine->n_groups_dev;
     wc.gnx = wc.gny = wc.gnz = 0;
-    k_prolong_ghosts<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, (const T*)coarse->U, (const T*)coarse->B,
-                                                               (T*)fine->U, (T*)fine->B, (T)c->cfg.gamma);
+    k_prolong_ghosts<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, Uc, Bc, (T*)fine->U, (T*)fine->B,
+                                                               (T)c->cfg.gamma);
   } else {
-    k_prolong_all<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, (const T*)coarse->U, (const T*)coarse->B,
-                                                            (T*)fine->U, (T*)fine->B, (T)c->cfg.gamma);
+    k_prolong_all<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, Uc, Bc, (T*)fine->U, (T*)fine->B,
+                                                            (T)c->cfg.gamma);
   }
 }
 
@@ -774,12 +785,18 @@ LevelScratch level_scratch(mhd_ctx_s* c, const mhd_level* lv) {
 }
 
 template <typename T>
-void launch_correct(mhd_ctx_s* cc, const mhd_level* coarse, mhd_ctx_s* cf, const mhd_level* fine, const double* dt) {
+void launch_correct(mhd_ctx_s* cc, const mhd_level* coarse, mhd_ctx_s* cf, const mhd_level* fine, const double* dt,
+                    int fine_registers) {
   Work wc = make_work(coarse, 0, 0);
   wc.occ = cc->occ;
   Work wf = make_work(fine, 0, 0);
   wf.occ = cf->occ;
-  const LevelScratch sc = level_scratch(cc, coarse), sf = level_scratch(cf, fine);
+  const LevelScratch sc = level_scratch(cc, coarse);
+  LevelScratch sf = level_scratch(cf, fine);
+  if (fine_registers) {
+    sf.F = cf->RF;
+    sf.E = cf->RE;
+  }
   const T inv_dx = (T)(1.0 / coarse->dx);
   k_correct_u<T><<<sblocks(wc), kBlock, 0, cc->stream>>>(wc, wf, sc, sf, (T*)coarse->U, dt, inv_dx);
   k_correct_b<T><<<sblocks(wc), kBlock, 0, cc->stream>>>(wc, wf, sc, sf, (T*)coarse->B, dt, inv_dx);
@@ -802,16 +819,76 @@ void launch_correct(mhd_ctx_s* cc, const mhd_level* coarse, mhd_ctx_s* cf, const
 
 extern "C" {
 
-int mhd_prolong(mhd_ctx c, const mhd_level* coarse, const mhd_level* fine, int halo) {
+int mhd_prolong_time(mhd_ctx c, const mhd_level* coarse_old, const mhd_level* coarse, double alpha,
+                     const mhd_level* fine, int halo) {
   if (!c || !coarse || !fine || halo < 0 || halo > 8) return MHD_ERR_INVALID_ARG;
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return MHD_ERR_INVALID_ARG;
   int rc = check_pair(c, coarse, fine);
   if (rc) return rc;
+  if (coarse_old) {
+    rc = check_level(c, coarse_old);
+    if (rc) return rc;
+    if (coarse_old->nx != coarse->nx || coarse_old->ny != coarse->ny || coarse_old->nz != coarse->nz ||
+        coarse_old->dx != coarse->dx)
+      return MHD_ERR_INVALID_ARG;
+  }
   if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
   rc = build_occupancy(c, fine);
   if (rc) return rc;
   g_max_blocks = c->max_blocks;
-  if (c->cfg.prec == MHD_F64) launch_prolong<double>(c, coarse, fine, halo);
-  else launch_prolong<float>(c, coarse, fine, halo);
+  if (c->cfg.prec == MHD_F64) launch_prolong<double>(c, coarse_old, coarse, alpha, fine, halo);
+  else launch_prolong<float>(c, coarse_old, coarse, alpha, fine, halo);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_prolong(mhd_ctx c, const mhd_level* coarse, const mhd_level* fine, int halo) {
+  return mhd_prolong_time(c, nullptr, coarse, 1.0, fine, halo);
+}
+
+int mhd_accumulate_registers(mhd_ctx c, const mhd_level* lv, double weight, int reset) {
+  if (!c) return MHD_ERR_INVALID_ARG;
+  int rc = check_level(c, lv);
+  if (rc) return rc;
+  if (!std::isfinite(weight)) return MHD_ERR_INVALID_ARG;
+  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
+  const int ghost = c->cfg.scheme == MHD_CTU ? 4 : 3;
+  const long long ns = scratch_cells(lv, ghost);
+  if (c->cap_cells < ns) return MHD_ERR_INVALID_ARG;     // no update of this level has run
+  if (c->cap_reg < ns) {
+    if (!reset) return MHD_ERR_INVALID_ARG;             // nothing accumulated to add to
+    hipFree(c->RF);
+    hipFree(c->RE);
+    c->RF = c->RE = nullptr;
+    c->cap_reg = 0;
+    if (hipMalloc(&c->RF, 21 * ns * c->elem) != hipSuccess || hipMalloc(&c->RE, 3 * ns * c->elem) != hipSuccess) {
+      hipFree(c->RF);
+      hipFree(c->RE);
+      c->RF = c->RE = nullptr;
+      return MHD_ERR_OUT_OF_MEMORY;
+    }
+    c->cap_reg = ns;
+  }
+  const LevelScratch v = level_scratch(c, lv);
+  const long long m = lv->group_edge + 1;
+  const long long items = v.sb ? (long long)lv->n_groups * m * m * m : ns;
+  if (items == 0) return MHD_OK;
+  long long nb = (items + kBlock - 1) / kBlock;
+  const long long cap = 16LL * c->num_cu;
+  if (nb > cap) nb = cap;
+  if (c->cfg.prec == MHD_F64)
+    k_accumulate_registers<double><<<(unsigned)nb, kBlock, 0, c->stream>>>(
+        (const double*)v.F, (const double*)v.E, (double*)c->RF, (double*)c->RE, ns, v.sb, ghost, lv->group_edge,
+        items, weight, reset);
+  else
+    k_accumulate_registers<float><<<(unsigned)nb, kBlock, 0, c->stream>>>(
+        (const float*)v.F, (const float*)v.E, (float*)c->RF, (float*)c->RE, ns, v.sb, ghost, lv->group_edge,
+        items, (float)weight, reset);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_dt_subdivide(mhd_ctx c, const double* dt_coarse, int parts, double* dt_fine) {
+  if (!c || !dt_coarse || !dt_fine || parts < 1) return MHD_ERR_INVALID_ARG;
+  k_subdivide_dt<<<1, 1, 0, c->stream>>>(dt_coarse, parts, dt_fine);
   return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 
@@ -828,7 +905,8 @@ int mhd_restrict(mhd_ctx c, const mhd_level* fine, const mhd_level* coarse) {
   return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 
-int mhd_correct(mhd_ctx cc, const mhd_level* coarse, mhd_ctx cf, const mhd_level* fine, const double* dt_dev) {
+int mhd_correct(mhd_ctx cc, const mhd_level* coarse, mhd_ctx cf, const mhd_level* fine, const double* dt_dev,
+                int fine_registers) {
   if (!cc || !cf || !coarse || !fine || !dt_dev) return MHD_ERR_INVALID_ARG;
   int rc = check_pair(cc, coarse, fine);
   if (rc) return rc;
@@ -841,6 +919,7 @@ int mhd_correct(mhd_ctx cc, const mhd_level* coarse, mhd_ctx cf, const mhd_level
   // both contexts must hold the scratch of an update of these levels
   if (cc->cap_cells < scratch_cells(coarse, ghost) || cf->cap_cells < scratch_cells(fine, ghost))
     return MHD_ERR_INVALID_ARG;
+  if (fine_registers && (!cf->RF || cf->cap_reg < scratch_cells(fine, ghost))) return MHD_ERR_INVALID_ARG;
   rc = build_occupancy(cc, coarse);
   if (rc) return rc;
   rc = build_occupancy(cf, fine);
@@ -848,8 +927,8 @@ int mhd_correct(mhd_ctx cc, const mhd_level* coarse, mhd_ctx cf, const mhd_level
   if (list_mode(coarse) && !cc->occ) return MHD_ERR_INVALID_ARG;
   if (list_mode(fine) && !cf->occ) return MHD_ERR_INVALID_ARG;
   g_max_blocks = cc->max_blocks;
-  if (cc->cfg.prec == MHD_F64) launch_correct<double>(cc, coarse, cf, fine, dt_dev);
-  else launch_correct<float>(cc, coarse, cf, fine, dt_dev);
+  if (cc->cfg.prec == MHD_F64) launch_correct<double>(cc, coarse, cf, fine, dt_dev, fine_registers);
+  else launch_correct<float>(cc, coarse, cf, fine, dt_dev, fine_registers);
   return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 

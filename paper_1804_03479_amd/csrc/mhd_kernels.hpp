@@ -864,10 +864,22 @@ __device__ __forceinline__ int wrap_delta(int d, int n) { return d > n / 2 ? d -
 // slopes of the two x-faces (and cyclic).  Every fine cell's divergence
 // equals its parent's; the fine faces on a coarse face average to it.
 
+// Coarse data read by the prolongation: one state, or the linear
+// interpolation in time old + w (new - old) between a parent's states at the
+// start and at the end of its step (the ghosts of a sub-cycled fine level).
+template <typename T>
+struct Coarse {
+  const T* a;      // the state, or the old state
+  const T* b;      // the new state (nullptr: no interpolation)
+  T w;
+  __device__ __forceinline__ T operator[](long long i) const { return b ? a[i] + w * (b[i] - a[i]) : a[i]; }
+  __device__ __forceinline__ Coarse shift(long long o) const { return Coarse{a + o, b ? b + o : nullptr, w}; }
+};
+
 // MC-limited slope of coarse face component C at coarse cell (i, j, k) along axis X
 template <typename T, int C, int X>
-__device__ __forceinline__ T coarse_face_slope(const Work& wc, const T* __restrict__ Bc, int i, int j, int k) {
-  const T* Bcc = Bc + (long long)C * wc.N;
+__device__ __forceinline__ T coarse_face_slope(const Work& wc, const Coarse<T>& Bc, int i, int j, int k) {
+  const Coarse<T> Bcc = Bc.shift((long long)C * wc.N);
   const T v = Bcc[lin(wc, wrapc(i, wc.nx), wrapc(j, wc.ny), wrapc(k, wc.nz))];
   const T up = Bcc[lin(wc, wrapc(i + (X == 0), wc.nx), wrapc(j + (X == 1), wc.ny), wrapc(k + (X == 2), wc.nz))];
   const T dn = Bcc[lin(wc, wrapc(i - (X == 0), wc.nx), wrapc(j - (X == 1), wc.ny), wrapc(k - (X == 2), wc.nz))];
@@ -875,13 +887,13 @@ __device__ __forceinline__ T coarse_face_slope(const Work& wc, const T* __restri
 }
 
 template <typename T, int A>
-__device__ __forceinline__ T prolong_face(const Work& wc, const T* __restrict__ Bc, int I, int J, int K) {
+__device__ __forceinline__ T prolong_face(const Work& wc, const Coarse<T>& Bc, int I, int J, int K) {
   constexpr int b = (A + 1) % 3, c = (A + 2) % 3;
   const int f[3] = {I, J, K};
   const int i = I >> 1, j = J >> 1, k = K >> 1;
   const T tb = (f[b] & 1) ? T(0.25) : T(-0.25);
   const T tc = (f[c] & 1) ? T(0.25) : T(-0.25);
-  const T* Ba = Bc + (long long)A * wc.N;
+  const Coarse<T> Ba = Bc.shift((long long)A * wc.N);
   if (!(f[A] & 1)) {
     // on the lower A-face of coarse cell (i, j, k)
     return Ba[lin(wc, i, j, k)] + coarse_face_slope<T, A, b>(wc, Bc, i, j, k) * tb +
@@ -910,8 +922,8 @@ __device__ __forceinline__ T prolong_face(const Work& wc, const T* __restrict__ 
 // the resulting common pressure would not be positive the parent's pressure
 // is kept instead.
 template <typename T>
-__device__ __forceinline__ void prolong_parent(const Work& wc, const Work& wf, const T* __restrict__ Uc,
-                                               const T* __restrict__ Bc, T* __restrict__ Uf, T* __restrict__ Bf,
+__device__ __forceinline__ void prolong_parent(const Work& wc, const Work& wf, const Coarse<T>& Uc,
+                                               const Coarse<T>& Bc, T* __restrict__ Uf, T* __restrict__ Bf,
                                                int i, int j, int k, const bool cell_ok[8], const bool face_ok[8][3],
                                                T gam) {
   // fine faces of the parent: fx[p][q] on the x-plane 2i + p (p = 0, 1, 2), transverse child q = b + 2 c
@@ -967,8 +979,8 @@ __device__ __forceinline__ void prolong_parent(const Work& wc, const Work& wf, c
 
 // whole fine level from the coarse level: one coarse cell per item
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong_all(Work wc, Work wf, const T* __restrict__ Uc,
-                                                        const T* __restrict__ Bc, T* __restrict__ Uf,
+__global__ void __launch_bounds__(kBlock) k_prolong_all(Work wc, Work wf, Coarse<T> Uc,
+                                                        Coarse<T> Bc, T* __restrict__ Uf,
                                                         T* __restrict__ Bf, T gam) {
   bool cell_ok[8], face_ok[8][3];
 #pragma unroll
@@ -987,8 +999,8 @@ __global__ void __launch_bounds__(kBlock) k_prolong_all(Work wc, Work wf, const 
 // halo boxes; a child is written when it lies outside every listed group, a
 // child's lower face when both cells of that face do
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong_ghosts(Work wc, Work wf, const T* __restrict__ Uc,
-                                                           const T* __restrict__ Bc, T* __restrict__ Uf,
+__global__ void __launch_bounds__(kBlock) k_prolong_ghosts(Work wc, Work wf, Coarse<T> Uc,
+                                                           Coarse<T> Bc, T* __restrict__ Uf,
                                                            T* __restrict__ Bf, T gam) {
   const long long per = (long long)wc.box * wc.box * wc.box;
   FOR_ITEMS(wc, t) {
@@ -1346,6 +1358,40 @@ __global__ void __launch_bounds__(kBlock) k_correct_b(Work wc, Work wf, LevelScr
     }
   }
 }
+
+// Time-averaged registers of a sub-cycled level: R = (reset ? 0 : R) + w S
+// over the final fluxes and EMFs S of the level's last update.  Whole grid
+// (sb = 0): every slot; group list: the slots of each group's cells and of
+// its upper boundary faces and edges (box positions ghost .. ghost + edge).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_accumulate_registers(const T* __restrict__ F, const T* __restrict__ E,
+                                                                 T* __restrict__ RF, T* __restrict__ RE, long long NS,
+                                                                 int sb, int ghost, int edge, long long items, T w,
+                                                                 int reset) {
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < items; t += stride) {
+    long long q = t;
+    if (sb) {
+      const long long m = edge + 1, per = m * m * m;
+      const long long g = t / per, r = t - g * per;
+      const long long a = r % m, b = (r / m) % m, c = r / (m * m);
+      q = (g + 1) * sb * sb * sb + ((c + ghost) * sb + (b + ghost)) * sb + (a + ghost);
+    }
+#pragma unroll
+    for (int m = 0; m < 21; ++m) {
+      const long long o = (long long)m * NS + q;
+      RF[o] = reset ? w * F[o] : RF[o] + w * F[o];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const long long o = (long long)m * NS + q;
+      RE[o] = reset ? w * E[o] : RE[o] + w * E[o];
+    }
+  }
+}
+
+// the step of a sub-cycled finer level: *fine = *coarse / parts
+__global__ void k_subdivide_dt(const double* coarse, int parts, double* fine) { *fine = *coarse / parts; }
 
 // ------------------------------------------------------------ set-up
 template <typename T, bool MIX>

@@ -56,7 +56,8 @@ EXPORTS = ["mhd_abi_version", "mhd_strerror", "mhd_required_ghost", "mhd_init", 
            "mhd_profile_step", "mhd_num_stages", "mhd_stage_name",
            "mhd_mlp_num_params", "mhd_mlp_set_weights", "mhd_mlp_forward", "mhd_mlp_backward",
            "mhd_mlp_train_step", "mhd_mlp_prepare", "mhd_mlp_face_flux", "mhd_set_capture", "mhd_correct",
-           "mhd_advance_graph", "mhd_set_launch", "mhd_cfl_dt_min", "mhd_prolong", "mhd_restrict"]
+           "mhd_advance_graph", "mhd_set_launch", "mhd_cfl_dt_min", "mhd_prolong", "mhd_restrict",
+           "mhd_prolong_time", "mhd_accumulate_registers", "mhd_dt_subdivide"]
 
 
 def load(path: str = LIB_PATH):
@@ -97,10 +98,14 @@ def load(path: str = LIB_PATH):
     lib.mhd_set_capture.argtypes = [P, P, ctypes.c_longlong, P, I]
     lib.mhd_advance_graph.argtypes = [P, ctypes.POINTER(LevelDesc), P, P]
     lib.mhd_set_launch.argtypes = [P, I]
-    lib.mhd_cfl_dt_min.argtypes = [P, ctypes.POINTER(LevelDesc), P]
+    lib.mhd_cfl_dt_min.argtypes = [P, ctypes.POINTER(LevelDesc), D, P]
+    lib.mhd_dt_subdivide.argtypes = [P, P, I, P]
+    lib.mhd_prolong_time.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc), D,
+                                     ctypes.POINTER(LevelDesc), I]
+    lib.mhd_accumulate_registers.argtypes = [P, ctypes.POINTER(LevelDesc), D, I]
     lib.mhd_prolong.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc), I]
     lib.mhd_restrict.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc)]
-    lib.mhd_correct.argtypes = [P, ctypes.POINTER(LevelDesc), P, ctypes.POINTER(LevelDesc), P]
+    lib.mhd_correct.argtypes = [P, ctypes.POINTER(LevelDesc), P, ctypes.POINTER(LevelDesc), P, I]
     _lib = lib
     return lib
 
@@ -249,19 +254,39 @@ class Solver:
     def set_launch(self, blocks_per_cu: int):
         _check(self.lib.mhd_set_launch(self.h, int(blocks_per_cu)), "mhd_set_launch")
 
-    def cfl_dt_min(self, lv: Level, dt_dev: torch.Tensor):
+    def cfl_dt_min(self, lv: Level, dt_dev: torch.Tensor, scale: float = 1.0):
         d = lv.desc()
-        _check(self.lib.mhd_cfl_dt_min(self.h, ctypes.byref(d), ctypes.c_void_p(dt_dev.data_ptr())), "mhd_cfl_dt_min")
+        _check(self.lib.mhd_cfl_dt_min(self.h, ctypes.byref(d), float(scale), ctypes.c_void_p(dt_dev.data_ptr())),
+               "mhd_cfl_dt_min")
 
-    def prolong(self, coarse: Level, fine: Level, halo: int = 4):
+    def dt_subdivide(self, dt_coarse: torch.Tensor, parts: int, dt_fine: torch.Tensor):
+        _check(self.lib.mhd_dt_subdivide(self.h, ctypes.c_void_p(dt_coarse.data_ptr()), int(parts),
+                                         ctypes.c_void_p(dt_fine.data_ptr())), "mhd_dt_subdivide")
+
+    def prolong(self, coarse: Level, fine: Level, halo: int = 4, coarse_old: Level | None = None,
+                alpha: float = 1.0):
+        """Fine level (or its ghost halos) from the coarse level; with coarse_old,
+        from old + alpha (coarse - old)."""
         dc, df = coarse.desc(), fine.desc()
-        _check(self.lib.mhd_prolong(self.h, ctypes.byref(dc), ctypes.byref(df), int(halo)), "mhd_prolong")
+        if coarse_old is None and alpha == 1.0:
+            _check(self.lib.mhd_prolong(self.h, ctypes.byref(dc), ctypes.byref(df), int(halo)), "mhd_prolong")
+            return
+        do = None if coarse_old is None else ctypes.byref(coarse_old.desc())
+        _check(self.lib.mhd_prolong_time(self.h, do, ctypes.byref(dc), float(alpha), ctypes.byref(df), int(halo)),
+               "mhd_prolong_time")
 
-    def correct(self, coarse: Level, fine_solver: "Solver", fine: Level, dt_dev: torch.Tensor):
-        """Coarse-fine flux and EMF correction after both levels took the step dt_dev."""
+    def accumulate_registers(self, lv: Level, weight: float, reset: bool):
+        d = lv.desc()
+        _check(self.lib.mhd_accumulate_registers(self.h, ctypes.byref(d), float(weight), int(bool(reset))),
+               "mhd_accumulate_registers")
+
+    def correct(self, coarse: Level, fine_solver: "Solver", fine: Level, dt_dev: torch.Tensor,
+                fine_registers: bool = False):
+        """Coarse-fine flux and EMF correction after both levels covered the coarse
+        step dt_dev (fine_registers: the fine level sub-cycled and accumulated)."""
         dc, df = coarse.desc(), fine.desc()
         _check(self.lib.mhd_correct(self.h, ctypes.byref(dc), fine_solver.h, ctypes.byref(df),
-                                    ctypes.c_void_p(dt_dev.data_ptr())), "mhd_correct")
+                                    ctypes.c_void_p(dt_dev.data_ptr()), int(bool(fine_registers))), "mhd_correct")
 
     def restrict(self, fine: Level, coarse: Level):
         dc, df = coarse.desc(), fine.desc()

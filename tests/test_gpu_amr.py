@@ -149,9 +149,10 @@ def test_three_level_hierarchy_runs_and_stays_solenoidal():
             assert np.abs(d[mask]).max() * lv.dx < 1e-12
 
 
-def test_hierarchy_graph_replay_matches_eager():
-    h1 = Hierarchy(32, [5, 9], prec="f32", seed=2)
-    h2 = Hierarchy(32, [5, 9], prec="f32", seed=2)
+@pytest.mark.parametrize("subcycle", [False, True])
+def test_hierarchy_graph_replay_matches_eager(subcycle):
+    h1 = Hierarchy(32, [5, 9], prec="f32", seed=2, subcycle=subcycle)
+    h2 = Hierarchy(32, [5, 9], prec="f32", seed=2, subcycle=subcycle)
     g = h1.capture()
     h2.step()
     for rep in range(3):
@@ -202,12 +203,14 @@ def _root_totals(h):
     return t, scale
 
 
+@pytest.mark.parametrize("subcycle", [False, True])
 @pytest.mark.parametrize("counts", [[5], [5, 9]])
-def test_correction_conserves_root_totals_and_div_b(counts):
+def test_correction_conserves_root_totals_and_div_b(counts, subcycle):
     # Sec. 3.3 correction operation: with the coarse-fine flux and EMF
     # corrections and restriction, the root's totals change only by
-    # round-off and its div B stays at round-off; without them they do not
-    h = Hierarchy(32, counts, prec="f64", noise=0.1, seed=1)
+    # round-off and its div B stays at round-off; without them they do not.
+    # Sub-cycled: the corrections use the time mean of the fine sub-steps.
+    h = Hierarchy(32, counts, prec="f64", noise=0.1, seed=1, subcycle=subcycle)
     t0, scale = _root_totals(h)
     for _ in range(3):
         h.step()
@@ -219,7 +222,7 @@ def test_correction_conserves_root_totals_and_div_b(counts):
         mx, _ = h.solvers[lvl_i].divb(lv)
         assert mx * lv.dx <= 1e-12, (lvl_i, mx)
     h.close()
-    u = Hierarchy(32, counts, prec="f64", noise=0.1, seed=1, correct=False)
+    u = Hierarchy(32, counts, prec="f64", noise=0.1, seed=1, correct=False, subcycle=subcycle)
     for _ in range(3):
         u.step()
     u.stream.synchronize()
@@ -228,3 +231,82 @@ def test_correction_conserves_root_totals_and_div_b(counts):
     assert (np.abs(t2 - t0) / scale)[[0, 4]].max() > 1e-10
     assert mxu * u.levels[0].dx > 1e-10
     u.close()
+
+
+def test_prolong_time_interpolates_the_parent_states():
+    # ghosts of a sub-cycled level: prolongation of old + alpha (new - old);
+    # alpha = 0 and 1 read one state alone
+    po = inputs.smooth_problem(8, 6, 4, seed=9)
+    pn = inputs.smooth_problem(8, 6, 4, seed=10)
+    Uo, Bo = oracle.initial_state(po)
+    Un, Bn = oracle.initial_state(pn)
+    s = Solver("vl", "plm", "roe")
+    co, cn = lvl(Uo, Bo, po["dx"]), lvl(Un, Bn, po["dx"])
+
+    def fine():
+        return Level(torch.empty((5, 8, 12, 16), dtype=torch.float64, device="cuda"),
+                     torch.empty((3, 8, 12, 16), dtype=torch.float64, device="cuda"), po["dx"] / 2)
+
+    f_half, f0, f1, fo, fn = fine(), fine(), fine(), fine(), fine()
+    s.prolong(cn, f_half, coarse_old=co, alpha=0.5)
+    s.prolong(cn, f0, coarse_old=co, alpha=0.0)
+    s.prolong(cn, f1, coarse_old=co, alpha=1.0)
+    s.prolong(co, fo)
+    s.prolong(cn, fn)
+    torch.cuda.synchronize()
+    Uf, Bf = oamr.prolong(0.5 * (Uo + Un), 0.5 * (Bo + Bn))
+    assert np.allclose(f_half.U.cpu().numpy(), Uf, rtol=1e-13, atol=1e-13)
+    assert np.allclose(f_half.B.cpu().numpy(), Bf, rtol=1e-13, atol=1e-13)
+    assert torch.equal(f0.U, fo.U) and torch.equal(f0.B, fo.B)
+    assert torch.equal(f1.U, fn.U) and torch.equal(f1.B, fn.B)
+
+
+def test_subcycled_full_refinement_equals_uniform_fine_run():
+    # every level-1 group listed: the sub-cycled hierarchy evolves level 1
+    # exactly like a uniform grid taking two steps of dt_1 = dt_0 / 2 per root
+    # step (no ghosts, no interface), and the root is its restriction
+    h = Hierarchy(16, [8], prec="f64", noise=0.1, seed=3, subcycle=True)
+    h.stream.synchronize()
+    u = Solver("ctu", "ppm", "hlld")
+    ref = Level(h.levels[1].U.clone(), h.levels[1].B.clone(), h.levels[1].dx)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        h.step()
+        h.stream.synchronize()
+        dts = h.dts.cpu().numpy()
+        assert dts[1] == dts[0] / 2
+        d1 = h.dts[1:2].clone()
+        u.step_devdt(ref, d1)
+        u.step_devdt(ref, d1)
+        torch.cuda.synchronize()
+        assert torch.equal(ref.U, h.levels[1].U) and torch.equal(ref.B, h.levels[1].B)
+    Ur = oamr.restrict(ref.U.cpu().numpy())
+    assert np.allclose(h.levels[0].U.cpu().numpy(), Ur, rtol=1e-14, atol=1e-14)
+    h.close()
+
+
+def test_subcycled_steps_follow_the_scaled_cfl():
+    # dt_0 = min over l of 2^l dt_cfl(l), dt_l = dt_0 / 2^l
+    h = Hierarchy(32, [5, 9], prec="f64", noise=0.1, seed=1, subcycle=True)
+    cfl = [s.cfl_dt(lv) for s, lv in zip(h.solvers, h.levels)]
+    h.shared_dt()
+    h.stream.synchronize()
+    dts = h.dts.cpu().numpy()
+    assert dts[0] == min(c * 2 ** l for l, c in enumerate(cfl))
+    assert dts[1] == dts[0] / 2 and dts[2] == dts[0] / 4
+    assert h.updates_per_step() == [32 ** 3, 2 * 5 * 16 ** 3, 4 * 9 * 16 ** 3]
+    h.close()
+
+
+def test_accumulate_registers_needs_a_reset_first():
+    from paper_1804_03479_amd.mhd import MHDError
+    p = inputs.abc_problem(32, 0.1, seed=2)
+    U, B = oracle.initial_state(p)
+    s = Solver("ctu", "ppm", "hlld")
+    a = lvl(U, B, p["dx"])
+    s.advance(a)
+    with pytest.raises(MHDError):
+        s.accumulate_registers(a, 0.5, reset=False)
+    s.accumulate_registers(a, 0.5, reset=True)
+    s.accumulate_registers(a, 0.5, reset=False)
+    torch.cuda.synchronize()
