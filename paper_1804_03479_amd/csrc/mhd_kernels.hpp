@@ -848,9 +848,8 @@ __device__ __forceinline__ int wrap_delta(int d, int n) { return d > n / 2 ? d -
 
 // Prolongation from a coarse level (nc) to a fine level (2 nc), paper
 // Sec. 3.3 (refinement operation).  Cell data: density and momentum are
-// injected (conservative: the 8 children average to the parent); the energy
-// is rebuilt from the parent's pressure and kinetic energy with the child's
-// own face field, which keeps the pressure positive.
+// injected; the energy is shared out so that the children keep a common
+// pressure and average to the parent (conservative, see prolong_parent).
 // Face field (Balsara's divergence-free reconstruction, in 3D): a coarse
 // face carries a linear profile B + S_t1 t1 + S_t2 t2 in its transverse
 // coordinates (coarse-cell units, t in [-1/2, 1/2]) with MC-limited slopes
@@ -876,41 +875,54 @@ struct Coarse {
   __device__ __forceinline__ Coarse shift(long long o) const { return Coarse{a + o, b ? b + o : nullptr, w}; }
 };
 
-// MC-limited slope of coarse face component C at coarse cell (i, j, k) along axis X
-template <typename T, int C, int X>
-__device__ __forceinline__ T coarse_face_slope(const Work& wc, const Coarse<T>& Bc, int i, int j, int k) {
-  const Coarse<T> Bcc = Bc.shift((long long)C * wc.N);
-  const T v = Bcc[lin(wc, wrapc(i, wc.nx), wrapc(j, wc.ny), wrapc(k, wc.nz))];
-  const T up = Bcc[lin(wc, wrapc(i + (X == 0), wc.nx), wrapc(j + (X == 1), wc.ny), wrapc(k + (X == 2), wc.nz))];
-  const T dn = Bcc[lin(wc, wrapc(i - (X == 0), wc.nx), wrapc(j - (X == 1), wc.ny), wrapc(k - (X == 2), wc.nz))];
-  return mc_slope(dn, v, up);
-}
+// The parent's six faces and the MC-limited slopes of each along its two
+// in-face directions: everything its 36 fine faces depend on (30 loads).
+template <typename T>
+struct ParentFaces {
+  T v[3][2];        // component A on the lower (0) and upper (1) A-face
+  T s[3][2][2];     // its slope along (A + 1) % 3 (0) and (A + 2) % 3 (1)
+};
 
 template <typename T, int A>
-__device__ __forceinline__ T prolong_face(const Work& wc, const Coarse<T>& Bc, int I, int J, int K) {
+__device__ __forceinline__ void load_face_pair(const Work& wc, const Coarse<T>& Bc, int i, int j, int k,
+                                               ParentFaces<T>& P) {
   constexpr int b = (A + 1) % 3, c = (A + 2) % 3;
-  const int f[3] = {I, J, K};
-  const int i = I >> 1, j = J >> 1, k = K >> 1;
-  const T tb = (f[b] & 1) ? T(0.25) : T(-0.25);
-  const T tc = (f[c] & 1) ? T(0.25) : T(-0.25);
   const Coarse<T> Ba = Bc.shift((long long)A * wc.N);
-  if (!(f[A] & 1)) {
-    // on the lower A-face of coarse cell (i, j, k)
-    return Ba[lin(wc, i, j, k)] + coarse_face_slope<T, A, b>(wc, Bc, i, j, k) * tb +
-           coarse_face_slope<T, A, c>(wc, Bc, i, j, k) * tc;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    int C[3] = {i, j, k};
+    C[A] += s;
+    auto at = [&](int d, int o) {
+      int D[3] = {C[0], C[1], C[2]};
+      D[d] += o;
+      return Ba[lin(wc, wrapc(D[0], wc.nx), wrapc(D[1], wc.ny), wrapc(D[2], wc.nz))];
+    };
+    const T v = at(b, 0);
+    P.v[A][s] = v;
+    P.s[A][s][0] = mc_slope(at(b, -1), v, at(b, 1));
+    P.s[A][s][1] = mc_slope(at(c, -1), v, at(c, 1));
   }
-  // on the mid-plane of coarse cell (i, j, k)
-  const int u[3] = {i + (A == 0), j + (A == 1), k + (A == 2)};     // cell above in A
-  const int ub[3] = {i + (b == 0), j + (b == 1), k + (b == 2)};    // cell above in b
-  const int uc[3] = {i + (c == 0), j + (c == 1), k + (c == 2)};    // cell above in c
-  const T lo = Ba[lin(wc, i, j, k)];
-  const T hi = Ba[lin(wc, wrapc(u[0], wc.nx), wrapc(u[1], wc.ny), wrapc(u[2], wc.nz))];
-  const T ab = T(0.5) * (coarse_face_slope<T, A, b>(wc, Bc, i, j, k) + coarse_face_slope<T, A, b>(wc, Bc, u[0], u[1], u[2]));
-  const T ac = T(0.5) * (coarse_face_slope<T, A, c>(wc, Bc, i, j, k) + coarse_face_slope<T, A, c>(wc, Bc, u[0], u[1], u[2]));
-  const T bxy = coarse_face_slope<T, b, A>(wc, Bc, ub[0], ub[1], ub[2]) - coarse_face_slope<T, b, A>(wc, Bc, i, j, k);
-  const T cxz = coarse_face_slope<T, c, A>(wc, Bc, uc[0], uc[1], uc[2]) - coarse_face_slope<T, c, A>(wc, Bc, i, j, k);
+}
+
+// Fine face of component A on plane p of the parent (0: its lower A-face,
+// 1: the mid-plane, 2: its upper A-face) at transverse position q = u + 2 v
+// (u along (A + 1) % 3, v along (A + 2) % 3).
+template <typename T, int A>
+__device__ __forceinline__ T fine_face(const ParentFaces<T>& P, int p, int q) {
+  constexpr int b = (A + 1) % 3, c = (A + 2) % 3;
+  const T tb = (q & 1) ? T(0.25) : T(-0.25);
+  const T tc = (q >> 1) ? T(0.25) : T(-0.25);
+  if (p != 1) {
+    const int s = p >> 1;
+    return P.v[A][s] + P.s[A][s][0] * tb + P.s[A][s][1] * tc;
+  }
+  const T ab = T(0.5) * (P.s[A][0][0] + P.s[A][1][0]);
+  const T ac = T(0.5) * (P.s[A][0][1] + P.s[A][1][1]);
+  // jumps across the parent of the A-slopes of the two transverse components
+  const T bxy = P.s[b][1][1] - P.s[b][0][1];     // A = (b + 2) % 3
+  const T cxz = P.s[c][1][0] - P.s[c][0][0];     // A = (c + 1) % 3
   const T axx = T(-0.5) * (bxy + cxz);
-  const T a0 = T(0.5) * (lo + hi) - T(0.25) * axx;
+  const T a0 = T(0.5) * (P.v[A][0] + P.v[A][1]) - T(0.25) * axx;
   return a0 + ab * tb + ac * tc;
 }
 
@@ -926,35 +938,37 @@ __device__ __forceinline__ void prolong_parent(const Work& wc, const Work& wf, c
                                                const Coarse<T>& Bc, T* __restrict__ Uf, T* __restrict__ Bf,
                                                int i, int j, int k, const bool cell_ok[8], const bool face_ok[8][3],
                                                T gam) {
-  // fine faces of the parent: fx[p][q] on the x-plane 2i + p (p = 0, 1, 2), transverse child q = b + 2 c
-  T fx[3][4], fy[3][4], fz[3][4];
+  ParentFaces<T> P;
+  load_face_pair<T, 0>(wc, Bc, i, j, k, P);
+  load_face_pair<T, 1>(wc, Bc, i, j, k, P);
+  load_face_pair<T, 2>(wc, Bc, i, j, k, P);
+  // fine faces: F[A][p][q] on plane p of component A, transverse child q
+  T F[3][3][4];
 #pragma unroll
   for (int p = 0; p < 3; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int u = q & 1, v = q >> 1;
-      // plane 2 is the next parent's lower face: periodic wrap of the fine index
-      fx[p][q] = prolong_face<T, 0>(wc, Bc, wrapc(2 * i + p, wf.nx), 2 * j + u, 2 * k + v);
-      fy[p][q] = prolong_face<T, 1>(wc, Bc, 2 * i + v, wrapc(2 * j + p, wf.ny), 2 * k + u);   // (z, x) transverse
-      fz[p][q] = prolong_face<T, 2>(wc, Bc, 2 * i + u, 2 * j + v, wrapc(2 * k + p, wf.nz));   // (x, y) transverse
+      F[0][p][q] = fine_face<T, 0>(P, p, q);
+      F[1][p][q] = fine_face<T, 1>(P, p, q);
+      F[2][p][q] = fine_face<T, 2>(P, p, q);
     }
   T b2[8];
-  T bc[8][3];
   T mean_b2 = T(0);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
-    bc[q][0] = T(0.5) * (fx[a][b + 2 * c] + fx[a + 1][b + 2 * c]);
-    bc[q][1] = T(0.5) * (fy[b][c + 2 * a] + fy[b + 1][c + 2 * a]);
-    bc[q][2] = T(0.5) * (fz[c][a + 2 * b] + fz[c + 1][a + 2 * b]);
-    b2[q] = bc[q][0] * bc[q][0] + bc[q][1] * bc[q][1] + bc[q][2] * bc[q][2];
+    // child (a, b, c): x-faces at transverse (y, z) = (b, c), y-faces at (z, x) = (c, a), z-faces at (x, y) = (a, b)
+    const T bx = T(0.5) * (F[0][a][b + 2 * c] + F[0][a + 1][b + 2 * c]);
+    const T by = T(0.5) * (F[1][b][c + 2 * a] + F[1][b + 1][c + 2 * a]);
+    const T bz = T(0.5) * (F[2][c][a + 2 * b] + F[2][c + 1][a + 2 * b]);
+    b2[q] = bx * bx + by * by + bz * bz;
     mean_b2 += b2[q];
   }
   mean_b2 *= T(0.125);
   const long long pc = lin(wc, i, j, k);
-  const T cbx = T(0.5) * (Bc[pc] + Bc[nbr(wc, i, j, k, 1, 0, 0)]);
-  const T cby = T(0.5) * (Bc[wc.N + pc] + Bc[wc.N + nbr(wc, i, j, k, 0, 1, 0)]);
-  const T cbz = T(0.5) * (Bc[2 * wc.N + pc] + Bc[2 * wc.N + nbr(wc, i, j, k, 0, 0, 1)]);
+  const T cbx = T(0.5) * (P.v[0][0] + P.v[0][1]);
+  const T cby = T(0.5) * (P.v[1][0] + P.v[1][1]);
+  const T cbz = T(0.5) * (P.v[2][0] + P.v[2][1]);
   const T b2c = cbx * cbx + cby * cby + cbz * cbz;
   const T d = Uc[pc], mx = Uc[wc.N + pc], my = Uc[2 * wc.N + pc], mz = Uc[3 * wc.N + pc], e = Uc[4 * wc.N + pc];
   const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / d;
@@ -971,9 +985,9 @@ __device__ __forceinline__ void prolong_parent(const Work& wc, const Work& wf, c
       Uf[3 * wf.N + pf] = mz;
       Uf[4 * wf.N + pf] = conservative ? e + T(0.5) * (b2[q] - mean_b2) : pr / (gam - T(1)) + ek + T(0.5) * b2[q];
     }
-    if (face_ok[q][0]) Bf[pf] = fx[a][b + 2 * c];
-    if (face_ok[q][1]) Bf[wf.N + pf] = fy[b][c + 2 * a];
-    if (face_ok[q][2]) Bf[2 * wf.N + pf] = fz[c][a + 2 * b];
+    if (face_ok[q][0]) Bf[pf] = F[0][a][b + 2 * c];
+    if (face_ok[q][1]) Bf[wf.N + pf] = F[1][b][c + 2 * a];
+    if (face_ok[q][2]) Bf[2 * wf.N + pf] = F[2][c][a + 2 * b];
   }
 }
 
@@ -997,36 +1011,45 @@ __global__ void __launch_bounds__(kBlock) k_prolong_all(Work wc, Work wf, Coarse
 
 // ghost halos of the listed fine groups: items are the coarse cells over the
 // halo boxes; a child is written when it lies outside every listed group, a
-// child's lower face when both cells of that face do
+// child's lower face when both cells of that face do.  The eight children
+// of a parent share one fine group (groups have an even edge), so one
+// occupancy lookup decides all of them, and three more their lower
+// neighbours across the parent's lower faces.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_ghosts(Work wc, Work wf, Coarse<T> Uc,
                                                            Coarse<T> Bc, T* __restrict__ Uf,
                                                            T* __restrict__ Bf, T gam) {
   const long long per = (long long)wc.box * wc.box * wc.box;
   FOR_ITEMS(wc, t) {
-    int i, j, k;
-    cell_of(wc, t, i, j, k);
+    int i, j, k, a0, b0, c0;
+    cell_of(wc, t, i, j, k, a0, b0, c0);
+    // parents under the item's own (listed) group have listed children only
+    const int lo = wc.halo, hi = wc.halo + wc.edge;
+    if (a0 >= lo && a0 < hi && b0 >= lo && b0 < hi && c0 >= lo && c0 < hi) continue;
     auto listed = [&](int x, int y, int z) {
       x = wrapc(x, wf.nx); y = wrapc(y, wf.ny); z = wrapc(z, wf.nz);
       return wf.occ[((long long)(z / wf.edge) * wf.gny + y / wf.edge) * wf.gnx + x / wf.edge] != 0;
     };
+    const int I0 = 2 * i, J0 = 2 * j, K0 = 2 * k;
+    if (listed(I0, J0, K0)) continue;
+    const bool lx = listed(I0 - 1, J0, K0), ly = listed(I0, J0 - 1, K0), lz = listed(I0, J0, K0 - 1);
     // children inside the requested fine halo box [o - halo, o + edge + halo + 1) of this item's group
     const int* o = wf.groups + 3 * (t / per);
     auto in_box = [&](int x, int y, int z) {
       const int dx = wrap_delta(x - o[0], wf.nx), dy = wrap_delta(y - o[1], wf.ny), dz = wrap_delta(z - o[2], wf.nz);
-      const int lo = -wf.halo, hi = wf.edge + wf.halo + 1;
-      return dx >= lo && dx < hi && dy >= lo && dy < hi && dz >= lo && dz < hi;
+      const int blo = -wf.halo, bhi = wf.edge + wf.halo + 1;
+      return dx >= blo && dx < bhi && dy >= blo && dy < bhi && dz >= blo && dz < bhi;
     };
     bool cell_ok[8], face_ok[8][3];
     bool any = false;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int I = 2 * i + (q & 1), J = 2 * j + ((q >> 1) & 1), K = 2 * k + (q >> 2);
-      const bool ghost = !listed(I, J, K) && in_box(I, J, K);
+      const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+      const bool ghost = in_box(I0 + a, J0 + b, K0 + c);
       cell_ok[q] = ghost;
-      face_ok[q][0] = ghost && !listed(I - 1, J, K);
-      face_ok[q][1] = ghost && !listed(I, J - 1, K);
-      face_ok[q][2] = ghost && !listed(I, J, K - 1);
+      face_ok[q][0] = ghost && (a || !lx);
+      face_ok[q][1] = ghost && (b || !ly);
+      face_ok[q][2] = ghost && (c || !lz);
       any = any || ghost;
     }
     if (any) prolong_parent(wc, wf, Uc, Bc, Uf, Bf, i, j, k, cell_ok, face_ok, gam);
