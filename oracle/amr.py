@@ -152,3 +152,206 @@ def restrict(Uf):
             for dx in (0, 1):
                 Uc += Uf[:, dz::2, dy::2, dx::2]
     return Uc / 8.0
+
+
+# ---------------------------------------------------------------- regridding
+# Refinement / derefinement operation of Sec. 3.3: fine groups are created
+# where a refinement criterion holds on the coarse level and removed where
+# it no longer does; a created group takes its data from the coarse level by
+# the prolongation above, except that where it touches a fine group that
+# already exists, the existing fine faces on the shared coarse face are kept.
+# Those four faces need not follow a linear profile: beyond the linear part
+# (mean m and slopes S_b, S_c, which the interior reconstruction uses) they
+# carry a twist d s_b s_c (s = -1 / +1 for the first / second child along an
+# axis).  The twist changes the divergence of the four children behind the
+# face by -+d; it is given back to them through the mid-plane faces of the
+# next axis b = (a+1)%3 in that layer of children: the b-mid-plane face of
+# the children at position g along c = (a+2)%3 gets -d s_g (lower a-face) or
+# +d s_g (upper a-face).  Then every created fine cell has its parent's
+# divergence, as in the plain prolongation.
+
+def refine_indicator_exceeds(Bc, thr):
+    """Cells where |curl B| dx / |B| > thr, decided as
+    (jx^2 + jy^2 + jz^2) > thr^2 (bx^2 + by^2 + bz^2) with j = dx curl B from
+    central differences of the cell-centred field b (periodic)."""
+    bx = 0.5 * (Bc[0] + np.roll(Bc[0], -1, axis=2))
+    by = 0.5 * (Bc[1] + np.roll(Bc[1], -1, axis=1))
+    bz = 0.5 * (Bc[2] + np.roll(Bc[2], -1, axis=0))
+
+    def d(f, axis):          # (f(+1) - f(-1)) / 2 along array axis
+        return 0.5 * (np.roll(f, -1, axis=axis) - np.roll(f, 1, axis=axis))
+
+    jx = d(bz, 1) - d(by, 0)
+    jy = d(bx, 0) - d(bz, 2)
+    jz = d(by, 2) - d(bx, 1)
+    return (jx * jx + jy * jy + jz * jz) > thr * thr * (bx * bx + by * by + bz * bz)
+
+
+def refine_groups(Bc, thr, fine_edge=16, buffer=1, coarse_groups=None, coarse_edge=16):
+    """Origins (fine cells) of the fine groups to hold after regridding, in
+    increasing (z, y, x) group order: a candidate group (a block of
+    fine_edge/2 coarse cells per axis) is kept when the criterion holds in a
+    coarse cell of the block widened by `buffer` cells (periodic), and, when
+    the coarse level has a group list, when its block lies in a listed coarse
+    group (proper nesting)."""
+    hit = refine_indicator_exceeds(Bc, thr)
+    nz, ny, nx = hit.shape
+    e = fine_edge // 2
+    listed = None
+    if coarse_groups is not None:
+        listed = {tuple(int(v) // coarse_edge for v in g) for g in coarse_groups}
+    out = []
+    for gk in range(nz // e):
+        for gj in range(ny // e):
+            for gi in range(nx // e):
+                if listed is not None and ((gi * e) // coarse_edge, (gj * e) // coarse_edge,
+                                           (gk * e) // coarse_edge) not in listed:
+                    continue
+                ks = [(gk * e + t) % nz for t in range(-buffer, e + buffer)]
+                js = [(gj * e + t) % ny for t in range(-buffer, e + buffer)]
+                is_ = [(gi * e + t) % nx for t in range(-buffer, e + buffer)]
+                if hit[np.ix_(ks, js, is_)].any():
+                    out.append((gi * fine_edge, gj * fine_edge, gk * fine_edge))
+    return np.array(out, dtype=np.int32).reshape(-1, 3)
+
+
+def _in_groups(groups, edge, shape):
+    """Boolean map of the fine cells inside the listed groups."""
+    m = np.zeros(shape, bool)
+    for (i, j, k) in groups:
+        m[k:k + edge, j:j + edge, i:i + edge] = True
+    return m
+
+
+def prolong_new_groups(Uc, Bc, Uf, Bf, new_groups, old_groups, edge=16, gamma=5.0 / 3.0):
+    """Fine level after regridding: groups of new_groups not in old_groups
+    are filled from the coarse level (cells, their lower faces, and their
+    upper boundary faces), faces shared with an old group are kept; every
+    other fine value is left as it is.  Returns new arrays."""
+    Uf, Bf = Uf.copy(), Bf.copy()
+    nzc, nyc, nxc = Uc.shape[1:]
+    nc = (nxc, nyc, nzc)
+    nf = (2 * nxc, 2 * nyc, 2 * nzc)
+    S = face_slopes(Bc)
+    old_map = _in_groups(old_groups, edge, Bf.shape[1:])
+    old_set = {tuple(int(v) for v in g) for g in old_groups}
+
+    def old_at(I, J, K):
+        return old_map[K % nf[2], J % nf[1], I % nf[0]]
+
+    def sgn(x):
+        return 1.0 if x else -1.0
+
+    for g in new_groups:
+        if tuple(int(v) for v in g) in old_set:
+            continue
+        o = [int(v) // 2 for v in g]
+        for ck in range(o[2], o[2] + edge // 2):
+            for cj in range(o[1], o[1] + edge // 2):
+                for ci in range(o[0], o[0] + edge // 2):
+                    c = (ci, cj, ck)
+                    # per face (a, s): mean, slopes along (a+1)%3 and (a+2)%3, twist, and fixed values
+                    m = np.zeros((3, 2))
+                    sl = np.zeros((3, 2, 2))
+                    tw = np.zeros((3, 2))
+                    fixed = [[None, None] for _ in range(3)]
+                    for a in range(3):
+                        b, cc = (a + 1) % 3, (a + 2) % 3
+                        for s in range(2):
+                            cell = list(c)
+                            cell[a] += s
+                            beyond = [2 * c[0], 2 * c[1], 2 * c[2]]   # fine cell across the face
+                            beyond[a] = 2 * c[a] - 1 if s == 0 else 2 * c[a] + 2
+                            if old_at(*beyond):
+                                f = []
+                                for q in range(4):
+                                    F = [2 * c[0], 2 * c[1], 2 * c[2]]
+                                    F[a] = 2 * c[a] + 2 * s
+                                    F[b] += q & 1
+                                    F[cc] += q >> 1
+                                    f.append(Bf[a, F[2] % nf[2], F[1] % nf[1], F[0] % nf[0]])
+                                fixed[a][s] = f
+                                m[a, s] = 0.25 * ((f[0] + f[1]) + (f[2] + f[3]))
+                                sl[a, s, 0] = (f[1] - f[0]) + (f[3] - f[2])
+                                sl[a, s, 1] = (f[2] - f[0]) + (f[3] - f[1])
+                                tw[a, s] = 0.25 * ((f[0] - f[1]) + (f[3] - f[2]))
+                            else:
+                                i, j, k = cell[0] % nc[0], cell[1] % nc[1], cell[2] % nc[2]
+                                m[a, s] = Bc[a, k, j, i]
+                                sl[a, s, 0] = S[a, 0, k, j, i]
+                                sl[a, s, 1] = S[a, 1, k, j, i]
+                    # fine faces fine[a][p][q]: plane p (0 lower, 1 mid, 2 upper) of component a
+                    fine = np.zeros((3, 3, 4))
+                    for a in range(3):
+                        b, cc = (a + 1) % 3, (a + 2) % 3
+                        for q in range(4):
+                            u, v = q & 1, q >> 1
+                            tb, tc = 0.25 * sgn(u), 0.25 * sgn(v)
+                            for s in range(2):
+                                if fixed[a][s] is not None:
+                                    fine[a, 2 * s, q] = fixed[a][s][q]
+                                else:
+                                    fine[a, 2 * s, q] = m[a, s] + sl[a, s, 0] * tb + sl[a, s, 1] * tc
+                            # interior: the quadratic of the coarse cell (mid-plane of a)
+                            b_xy = sl[b, 1, 1] - sl[b, 0, 1]       # slope of B_b along a (a = (b+2)%3)
+                            c_xz = sl[cc, 1, 0] - sl[cc, 0, 0]     # slope of B_c along a (a = (c+1)%3)
+                            a_xx = -0.5 * (b_xy + c_xz)
+                            a0 = 0.5 * (m[a, 0] + m[a, 1]) - 0.25 * a_xx
+                            a_b = 0.5 * (sl[a, 0, 0] + sl[a, 1, 0])
+                            a_c = 0.5 * (sl[a, 0, 1] + sl[a, 1, 1])
+                            fine[a, 1, q] = a0 + a_b * tb + a_c * tc
+                    # give each twist back through the b-mid-plane faces of its layer
+                    for a in range(3):
+                        b = (a + 1) % 3
+                        for s in range(2):
+                            if tw[a, s] == 0.0:
+                                continue
+                            for gpos in range(2):     # position along (a+2)%3 = the first in-face axis of b
+                                q = gpos + 2 * s       # b's second in-face axis is a: layer s
+                                fine[b, 1, q] += (1.0 if s else -1.0) * tw[a, s] * sgn(gpos)
+                    # children
+                    kids = []
+                    for q in range(8):
+                        x, y, z = q & 1, (q >> 1) & 1, q >> 2
+                        pos = (x, y, z)
+                        bcell = []
+                        for a in range(3):
+                            b, cc = (a + 1) % 3, (a + 2) % 3
+                            t = pos[b] + 2 * pos[cc]
+                            bcell.append(0.5 * (fine[a, pos[a], t] + fine[a, pos[a] + 1, t]))
+                        kids.append((pos, sum(w * w for w in bcell)))
+                    mean_b2 = sum(k2 for _, k2 in kids) / 8.0
+                    i, j, k = ci % nc[0], cj % nc[1], ck % nc[2]
+                    bpar = [0.5 * (Bc[0, k, j, i] + Bc[0, k, j, (i + 1) % nc[0]]),
+                            0.5 * (Bc[1, k, j, i] + Bc[1, k, (j + 1) % nc[1], i]),
+                            0.5 * (Bc[2, k, j, i] + Bc[2, (k + 1) % nc[2], j, i])]
+                    d = Uc[0, k, j, i]
+                    mom = Uc[1:4, k, j, i]
+                    ek = 0.5 * float(mom @ mom) / d
+                    b2c = sum(w * w for w in bpar)
+                    p = (gamma - 1) * (Uc[4, k, j, i] - ek - 0.5 * b2c)
+                    conservative = p - (gamma - 1) * 0.5 * (mean_b2 - b2c) > 0.0
+                    for pos, k2 in kids:
+                        I, J, K = 2 * ci + pos[0], 2 * cj + pos[1], 2 * ck + pos[2]
+                        Uf[0, K, J, I] = d
+                        Uf[1:4, K, J, I] = mom
+                        Uf[4, K, J, I] = (Uc[4, k, j, i] + 0.5 * (k2 - mean_b2) if conservative
+                                          else p / (gamma - 1) + ek + 0.5 * k2)
+                        for a in range(3):
+                            b, cc = (a + 1) % 3, (a + 2) % 3
+                            t = pos[b] + 2 * pos[cc]
+                            if pos[a] == 0 and fixed[a][0] is not None:
+                                continue
+                            Bf[a, K, J, I] = fine[a, pos[a], t]
+                    # upper boundary faces of the parent unless they belong to an old group
+                    for a in range(3):
+                        b, cc = (a + 1) % 3, (a + 2) % 3
+                        if fixed[a][1] is not None:
+                            continue
+                        for q in range(4):
+                            F = [2 * ci, 2 * cj, 2 * ck]
+                            F[a] += 2
+                            F[b] += q & 1
+                            F[cc] += q >> 1
+                            Bf[a, F[2] % nf[2], F[1] % nf[1], F[0] % nf[0]] = fine[a, 2, q]
+    return Uf, Bf

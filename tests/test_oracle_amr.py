@@ -98,3 +98,127 @@ def test_prolongation_is_second_order():
         _, Bf = amr.prolong(Uc, Bc)
         errs.append(np.abs(Bf - exact).max())
     assert errs[0] / errs[1] > 3.5, errs
+
+
+# ---- regridding (refinement / derefinement operation of Sec. 3.3)
+
+def test_indicator_closed_form_on_the_abc_field():
+    # the central-difference curl of the cell-centred ABC field is
+    # sin(k dx) times the field (the discrete field stays Beltrami), so the
+    # indicator |curl B| dx / |B| equals sin(2 pi / n) in every cell
+    n = 32
+    Bc = np.stack(inputs.abc_face_field(n))
+    s = np.sin(2 * np.pi / n)
+    assert amr.refine_indicator_exceeds(Bc, s * (1 - 1e-9)).all()
+    assert not amr.refine_indicator_exceeds(Bc, s * (1 + 1e-9)).any()
+    assert len(amr.refine_groups(Bc, s * (1 - 1e-9))) == (2 * n // 16) ** 3
+    assert len(amr.refine_groups(Bc, s * (1 + 1e-9))) == 0
+    assert not amr.refine_indicator_exceeds(np.ones((3, 8, 8, 8)), 1e-12).any()   # uniform field
+
+
+def test_refine_groups_buffer_order_and_nesting():
+    n = 32
+    Bc = np.ones((3, n, n, n))
+    Bc[1, 5, 9, 20] += 1.0            # a local current around coarse cell (20, 9, 5)
+    hot = amr.refine_indicator_exceeds(Bc, 0.1)
+    cells = {(i, j, k) for (k, j, i) in zip(*np.nonzero(hot))}
+    assert cells and all(abs(i - 20) <= 1 and abs(j - 9) <= 1 and abs(k - 5) <= 1 for (i, j, k) in cells)
+    g0 = amr.refine_groups(Bc, 0.1, buffer=0)
+    want0 = sorted({(i // 8, j // 8, k // 8) for (i, j, k) in cells}, key=lambda t: (t[2], t[1], t[0]))
+    assert [tuple(x // 16) for x in g0] == want0
+    g2 = amr.refine_groups(Bc, 0.1, buffer=4)
+    want2 = set()
+    for (i, j, k) in cells:
+        for di in (-4, 0, 4):
+            for dj in (-4, 0, 4):
+                for dk in (-4, 0, 4):
+                    want2.add((((i + di) % n) // 8, ((j + dj) % n) // 8, ((k + dk) % n) // 8))
+    got2 = [tuple(x // 16) for x in g2]
+    assert set(got2) == want2 and got2 == sorted(got2, key=lambda t: (t[2], t[1], t[0]))
+    # nesting: only candidates inside listed coarse groups survive
+    g_n = amr.refine_groups(Bc, 0.1, buffer=4, coarse_groups=[(16, 0, 0)], coarse_edge=16)
+    assert len(g_n) and all(16 <= x[0] // 2 < 32 and x[1] // 2 < 16 and x[2] // 2 < 16 for x in g_n)
+
+
+def _curl_perturbation(shape, box, seed, amp=0.05):
+    """Face field of the discrete curl of a random edge potential that is
+    nonzero on the edges of the fine box [lo, hi) (inclusive of its
+    boundary planes): divergence-free to round-off, and non-linear across
+    the box's boundary faces."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    A = np.zeros((3,) + shape)            # A[a] on the a-edges at the lower corner of each cell
+    (i0, j0, k0), (i1, j1, k1) = box
+    A[:, k0:k1 + 1, j0:j1 + 1, i0:i1 + 1] = amp * rng.standard_normal((3, k1 - k0 + 1, j1 - j0 + 1, i1 - i0 + 1))
+    dB = np.zeros((3,) + shape)
+    # Bx = dAz/dy - dAy/dz on x-faces, cyclic (unit spacing; divergence-free discretely)
+    dB[0] = (np.roll(A[2], -1, axis=1) - A[2]) - (np.roll(A[1], -1, axis=0) - A[1])
+    dB[1] = (np.roll(A[0], -1, axis=0) - A[0]) - (np.roll(A[2], -1, axis=2) - A[2])
+    dB[2] = (np.roll(A[1], -1, axis=2) - A[1]) - (np.roll(A[0], -1, axis=1) - A[0])
+    return dB
+
+
+def regrid_case(seed=0):
+    """Coarse 16^3 state, fine level prolonged from it with one old group
+    at (0, 0, 0) whose field is perturbed by a discrete curl reaching its
+    boundary faces, the coarse faces of the old group's region reset to the
+    fine means (as the restriction does)."""
+    p = inputs.smooth_problem(16, 16, 16, seed=seed)
+    import oracle
+    Uc, Bc = oracle.initial_state(p)
+    Uf, Bf = amr.prolong(Uc, Bc)
+    old = np.array([[0, 0, 0]], dtype=np.int32)
+    Bf = Bf + _curl_perturbation(Bf.shape[1:], ((0, 0, 0), (16, 16, 16)), seed)
+    # restriction of the old group's faces (its cells and its upper boundary faces)
+    Bc = Bc.copy()
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        for k in range(9 if a == 2 else 8):
+            for j in range(9 if a == 1 else 8):
+                for i in range(9 if a == 0 else 8):
+                    I = [2 * i, 2 * j, 2 * k]
+                    s = 0.0
+                    for q in range(4):
+                        F = list(I)
+                        F[b] += q & 1
+                        F[c] += q >> 1
+                        s += Bf[a, F[2] % 32, F[1] % 32, F[0] % 32]
+                    Bc[a, k % 16, j % 16, i % 16] = 0.25 * s
+    return p, Uc, Bc, Uf, Bf, old
+
+
+def test_prolong_new_groups_without_old_groups_is_the_prolongation():
+    p = inputs.smooth_problem(16, 16, 16, seed=3)
+    import oracle
+    Uc, Bc = oracle.initial_state(p)
+    Uf, Bf = amr.prolong(Uc, Bc)
+    allg = np.array([(i, j, k) for k in (0, 16) for j in (0, 16) for i in (0, 16)], dtype=np.int32)
+    U2, B2 = amr.prolong_new_groups(Uc, Bc, np.zeros_like(Uf), np.zeros_like(Bf), allg, np.zeros((0, 3), np.int32))
+    assert np.allclose(U2, Uf, rtol=1e-15, atol=1e-15) and np.allclose(B2, Bf, rtol=1e-15, atol=1e-15)
+
+
+def test_prolong_new_groups_next_to_an_old_group():
+    import oracle
+    p, Uc, Bc, Uf, Bf, old = regrid_case(seed=1)
+    new = np.array([[0, 0, 0], [16, 0, 0], [0, 16, 0], [16, 16, 16]], dtype=np.int32)
+    U2, B2 = amr.prolong_new_groups(Uc, Bc, Uf, Bf, new, old)
+    dxc = p["dx"]
+    old_map = amr._in_groups(old, 16, Uf.shape[1:])
+    made = amr._in_groups(new, 16, Uf.shape[1:]) & ~old_map
+    # the old group's cells and faces are kept
+    assert np.array_equal(U2[:, old_map], Uf[:, old_map]) and np.array_equal(B2[:, old_map], Bf[:, old_map])
+    # every created fine cell has its parent's divergence (Eq. 16), twists included
+    dc = oracle.divb(Bc, dxc)
+    df = oracle.divb(B2, dxc / 2)
+    parent = np.repeat(np.repeat(np.repeat(dc, 2, 0), 2, 1), 2, 2)
+    scale = np.abs(Bc).max() / dxc
+    assert np.abs(df[made] - parent[made]).max() <= 1e-12 * scale
+    # the twist is real here: without giving it back the divergence would differ
+    assert np.abs(dc).max() > 0 and np.abs(df[old_map]).max() <= 1e-12 * scale
+    # conservative: the children of each created parent average to it
+    Ur = amr.restrict(np.where(made[None], U2, 0.0))
+    pm = made[::2, ::2, ::2]
+    assert np.allclose(Ur[:, pm] * 1.0, Uc[:, pm] / 1.0, rtol=1e-14, atol=1e-14)
+    # nothing outside the created groups moved
+    rest = ~made & ~old_map
+    assert np.array_equal(U2[:, rest], Uf[:, rest])
