@@ -151,6 +151,41 @@ int mhd_set_launch(mhd_ctx ctx, int blocks_per_cu);
  * positive and finite. */
 int mhd_cfl_dt_min(mhd_ctx ctx, const mhd_level* lv, double scale, double* dt_dev);
 
+/* Refinement / derefinement operation of paper Sec. 3.3, step 1: the group
+ * list of the level above `coarse`.  A candidate fine group (fine_edge^3
+ * fine cells, a block of fine_edge/2 coarse cells per axis) is listed when
+ * the criterion |curl B| dx / |B| > threshold holds in a coarse cell of its
+ * block widened by `buffer` coarse cells (periodic); it is decided as
+ * (jx^2 + jy^2 + jz^2) > threshold^2 (bx^2 + by^2 + bz^2), b the cell-centred
+ * field and j = dx curl b by central differences, without contraction.
+ * When `coarse` has a group list, only candidates inside listed coarse
+ * groups qualify (proper nesting; coarse->group_edge must be a multiple of
+ * fine_edge/2).  groups_out (device int32[capacity][3], fine-cell origins)
+ * receives the listed candidates in increasing (z, y, x) order, at most
+ * `capacity` of them; *count_dev = min(*wanted_dev, capacity) and
+ * *wanted_dev = the number that qualified (device int32 each): the caller
+ * checks *wanted_dev <= capacity.  0 <= buffer <= fine_edge/2; the coarse
+ * dimensions must be multiples of fine_edge/2.  Not for MHD_F32_MIXED. */
+int mhd_regrid_flag(mhd_ctx ctx, const mhd_level* coarse, double threshold, int buffer, int fine_edge,
+                    int* groups_out, int capacity, int* count_dev, int* wanted_dev);
+
+/* Refinement / derefinement operation of paper Sec. 3.3, step 2: data of
+ * the fine groups created by a new list.  fine_new and fine_old describe
+ * the same fine arrays (U, B) with the new and the previous group list
+ * (fine_old NULL or without a list: nothing existed).  Groups of the new
+ * list that the old list does not hold take cells, lower faces and upper
+ * boundary faces from `coarse` by the prolongation of mhd_prolong (Balsara's
+ * reconstruction, conservative energy); a face whose far side is a fine
+ * cell of an old group keeps its value, and the twist of those kept faces
+ * (the part of the four values beyond a mean and two slopes) is returned
+ * through the created parent's mid-plane faces so that each created cell
+ * keeps its parent's divergence.  Everything else is left untouched: old
+ * groups keep their data, removed groups need nothing (their parent cells
+ * hold the restricted data).  Call it after mhd_restrict so that the coarse
+ * faces next to old groups are their fine means.  Not for MHD_F32_MIXED. */
+int mhd_prolong_new_groups(mhd_ctx ctx, const mhd_level* coarse, const mhd_level* fine_new,
+                           const mhd_level* fine_old);
+
 /* *dt_fine = *dt_coarse / parts on the device (the step of a level that
  * sub-cycles parts times inside its parent's step); parts >= 1. */
 int mhd_dt_subdivide(mhd_ctx ctx, const double* dt_coarse, int parts, double* dt_fine);

@@ -33,7 +33,14 @@ dt_{l-1} / 2, and
       restrict l + 1 onto l
 
 Group lists are chosen with a seeded generator and are octree-consistent:
-every group of level l + 1 lies inside a group of level l.
+every group of level l + 1 lies inside a group of level l.  With a list
+capacity, regrid() replaces them by the refinement criterion (Sec. 3.3,
+refinement / derefinement): for each refined level, coarse to fine, the
+candidate groups where |curl B| dx / |B| exceeds a threshold on the parent
+level (inside the parent's groups) become the new list (mhd_regrid_flag),
+and the created groups take the parent's data (mhd_prolong_new_groups); the
+lists live in fixed (capacity, 3) buffers with a device count, so a
+captured step stays valid across regrids.
 """
 from __future__ import annotations
 
@@ -73,7 +80,7 @@ class Hierarchy:
 
     def __init__(self, n_root: int, counts, scheme="ctu", recon="ppm", riemann="hlld", prec="f32",
                  noise: float = 0.1, seed: int = 0, edge: int = 16, stream: torch.cuda.Stream | None = None,
-                 correct: bool = True, subcycle: bool = False):
+                 correct: bool = True, subcycle: bool = False, capacity: int | None = None):
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.correct = correct
         self.subcycle = subcycle
@@ -93,10 +100,24 @@ class Hierarchy:
                 Bf = torch.empty((3, n, n, n), dtype=s0.dtype, device="cuda")
                 fine = Level(U, Bf, p["dx"] / (1 << lvl))
                 self.solvers[lvl].prolong(self.levels[-1], fine)     # whole level, initial data
-                fine.set_groups(torch.from_numpy(g).cuda())
+                if capacity is None:
+                    fine.set_groups(torch.from_numpy(g).cuda())
+                else:
+                    if len(g) > capacity:
+                        raise ValueError("initial group list longer than the capacity")
+                    buf = torch.zeros((capacity, 3), dtype=torch.int32, device="cuda")
+                    buf[:len(g)] = torch.from_numpy(g).cuda()
+                    fine.set_groups(buf)
+                    fine.n_groups_dev = torch.tensor([len(g)], dtype=torch.int32, device="cuda")
                 fine.group_edge = edge
                 self.levels.append(fine)
             # per-level steps (all equal without sub-cycling); dt is the root's
+            self.capacity = capacity
+            self.edge = edge
+            if capacity is not None:
+                self._new = torch.zeros((capacity, 3), dtype=torch.int32, device="cuda")
+                self._count = torch.zeros(1, dtype=torch.int32, device="cuda")
+                self._wanted = torch.zeros(len(self.levels), dtype=torch.int32, device="cuda")
             self.dts = torch.zeros(len(self.levels), dtype=torch.float64, device="cuda")
             self.dt = self.dts[:1]
             # a level's state at the start of its step, for its children's ghosts
@@ -110,11 +131,42 @@ class Hierarchy:
     def s(self):
         return self.solvers[0]
 
+    def group_counts(self):
+        """Listed groups of each refined level (a host sync with a capacity)."""
+        if self.capacity is None:
+            return [len(g) for g in self.groups]
+        return [int(lv.n_groups_dev.item()) for lv in self.levels[1:]]
+
     def cells_per_level(self):
         out = [int(np.prod(self.levels[0].shape))]
-        for g, lv in zip(self.groups, self.levels[1:]):
-            out.append(len(g) * lv.group_edge ** 3)
+        for n, lv in zip(self.group_counts(), self.levels[1:]):
+            out.append(n * lv.group_edge ** 3)
         return out
+
+    def regrid(self, threshold: float, buffer: int = 1):
+        """Refinement / derefinement of every refined level from the criterion
+        |curl B| dx / |B| > threshold on its parent (asynchronous); then
+        check_regrid() reports whether every list fitted its capacity."""
+        if self.capacity is None:
+            raise RuntimeError("regrid needs a Hierarchy built with a list capacity")
+        with torch.cuda.stream(self.stream):
+            for lvl in range(1, len(self.levels)):
+                s, coarse, fine = self.solvers[lvl], self.levels[lvl - 1], self.levels[lvl]
+                s.regrid_flag(coarse, threshold, buffer, self.edge, self._new, self._count,
+                              self._wanted[lvl - 1:lvl])
+                new = Level(fine.U, fine.B, fine.dx, groups=self._new, group_edge=self.edge)
+                new.n_groups_dev = self._count
+                s.prolong_new_groups(coarse, new, fine)
+                fine.groups.copy_(self._new)
+                fine.n_groups_dev.copy_(self._count)
+
+    def check_regrid(self):
+        """Groups each level wanted at the last regrid; raises if one did not fit."""
+        self.stream.synchronize()
+        wanted = self._wanted[:len(self.levels) - 1].cpu().tolist()
+        if max(wanted, default=0) > self.capacity:
+            raise RuntimeError(f"regrid wanted {wanted} groups per level, capacity {self.capacity}")
+        return wanted
 
     def updates_per_step(self):
         """Cell updates of each level in one root step (2^l sub-steps on level l

@@ -43,6 +43,10 @@ struct mhd_ctx_s {
   void* RF;               // time-averaged final fluxes of a sub-cycled level: 21 * cap_reg
   void* RE;               // time-averaged final EMFs: 3 * cap_reg
   long long cap_reg;
+  int* rflags;            // regridding: one flag per candidate fine group
+  long long cap_rflags;
+  int* occ_old;           // regridding: occupancy of the fine level's previous list
+  long long cap_occ_old;
   double* parts;          // reduction partials
   double* dres;           // 8 device doubles of reduction results
   unsigned long long* smax;
@@ -201,23 +205,26 @@ Work stage_work(const mhd_level* lv, int lo, int hi, int ghost) {
   return w;
 }
 
-// occupancy map of the level's group list (list mode only)
-int build_occupancy(mhd_ctx_s* c, const mhd_level* lv) {
+// occupancy map of a level's group list (list mode only) into *occ
+int build_occupancy_into(mhd_ctx_s* c, const mhd_level* lv, int** occ, long long* cap) {
   if (!lv->groups || lv->n_groups <= 0) return MHD_OK;
   const long long ng = (long long)(lv->nx / lv->group_edge) * (lv->ny / lv->group_edge) * (lv->nz / lv->group_edge);
-  if (ng > c->cap_occ) {
-    hipFree(c->occ);
-    c->occ = nullptr;
-    c->cap_occ = 0;
-    if (hipMalloc(&c->occ, ng * sizeof(int)) != hipSuccess) return MHD_ERR_OUT_OF_MEMORY;
-    c->cap_occ = ng;
+  if (ng > *cap) {
+    hipFree(*occ);
+    *occ = nullptr;
+    *cap = 0;
+    if (hipMalloc(occ, ng * sizeof(int)) != hipSuccess) return MHD_ERR_OUT_OF_MEMORY;
+    *cap = ng;
   }
-  k_occ_clear<<<(unsigned)((ng + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(c->occ, ng);
+  k_occ_clear<<<(unsigned)((ng + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(*occ, ng);
   k_occ_set<<<(unsigned)((lv->n_groups + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-      c->occ, lv->groups, lv->n_groups, lv->n_groups_dev, lv->group_edge, lv->nx / lv->group_edge,
+      *occ, lv->groups, lv->n_groups, lv->n_groups_dev, lv->group_edge, lv->nx / lv->group_edge,
       lv->ny / lv->group_edge);
   return MHD_OK;
 }
+
+// occupancy map of the level's group list in the context's map
+int build_occupancy(mhd_ctx_s* c, const mhd_level* lv) { return build_occupancy_into(c, lv, &c->occ, &c->cap_occ); }
 
 // grid of a reduction kernel: one thread per item (fixed, so results are
 // bitwise stable)
@@ -489,6 +496,8 @@ int mhd_finalize(mhd_ctx c) {
   hipFree(c->mlp_ws);
   hipFree(c->RF);
   hipFree(c->RE);
+  hipFree(c->rflags);
+  hipFree(c->occ_old);
   hipFree(c->parts); hipFree(c->dres); hipFree(c->smax); hipFree(c->flag); hipFree(c->nfb); hipFree(c->occ);
   if (c->host) hipHostFree(c->host);
   delete c;
@@ -883,6 +892,94 @@ int mhd_accumulate_registers(mhd_ctx c, const mhd_level* lv, double weight, int 
     k_accumulate_registers<float><<<(unsigned)nb, kBlock, 0, c->stream>>>(
         (const float*)v.F, (const float*)v.E, (float*)c->RF, (float*)c->RE, ns, v.sb, ghost, lv->group_edge,
         items, (float)weight, reset);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_regrid_flag(mhd_ctx c, const mhd_level* coarse, double threshold, int buffer, int fine_edge,
+                    int* groups_out, int capacity, int* count_dev, int* wanted_dev) {
+  if (!c || !groups_out || !count_dev || !wanted_dev || capacity < 0) return MHD_ERR_INVALID_ARG;
+  int rc = check_level(c, coarse);
+  if (rc) return rc;
+  if (!(threshold >= 0.0 && std::isfinite(threshold))) return MHD_ERR_INVALID_ARG;
+  if (fine_edge < 4 || fine_edge % 2) return MHD_ERR_INVALID_ARG;
+  const int e = fine_edge / 2;
+  if (buffer < 0 || buffer > e) return MHD_ERR_INVALID_ARG;
+  if (coarse->nx % e || coarse->ny % e || coarse->nz % e) return MHD_ERR_INVALID_ARG;
+  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
+  const int gnx = coarse->nx / e, gny = coarse->ny / e, gnz = coarse->nz / e;
+  const long long ng = (long long)gnx * gny * gnz;
+  if (ng > c->cap_rflags) {
+    hipFree(c->rflags);
+    c->rflags = nullptr;
+    c->cap_rflags = 0;
+    if (hipMalloc(&c->rflags, ng * sizeof(int)) != hipSuccess) return MHD_ERR_OUT_OF_MEMORY;
+    c->cap_rflags = ng;
+  }
+  // nesting: candidates must lie in listed coarse groups
+  const int* cocc = nullptr;
+  if (list_mode(coarse)) {
+    if (coarse->group_edge % e) return MHD_ERR_INVALID_ARG;
+    rc = build_occupancy(c, coarse);
+    if (rc) return rc;
+    cocc = c->occ;
+  }
+  k_fill_int<<<(unsigned)((ng + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(c->rflags, ng, 0);
+  const mhd_level cw = whole_grid(coarse);
+  const Work w = make_work(&cw, 0, 0);
+  g_max_blocks = c->max_blocks;
+  if (c->cfg.prec == MHD_F64)
+    k_refine_mark<double><<<sblocks(w), kBlock, 0, c->stream>>>(w, (const double*)coarse->B, threshold, e, buffer,
+                                                                 gnx, gny, gnz, c->rflags);
+  else
+    k_refine_mark<float><<<sblocks(w), kBlock, 0, c->stream>>>(w, (const float*)coarse->B, (float)threshold, e,
+                                                                buffer, gnx, gny, gnz, c->rflags);
+  k_compact_groups<<<1, 1024, 0, c->stream>>>(c->rflags, gnx, gny, gnz, e, fine_edge, cocc,
+                                              cocc ? coarse->nx / coarse->group_edge : 0,
+                                              cocc ? coarse->ny / coarse->group_edge : 0,
+                                              cocc ? coarse->group_edge : 1, groups_out, capacity, count_dev,
+                                              wanted_dev);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+}
+
+int mhd_prolong_new_groups(mhd_ctx c, const mhd_level* coarse, const mhd_level* fine_new,
+                           const mhd_level* fine_old) {
+  if (!c || !coarse || !fine_new) return MHD_ERR_INVALID_ARG;
+  int rc = check_pair(c, coarse, fine_new);
+  if (rc) return rc;
+  if (!list_mode(fine_new)) return MHD_ERR_INVALID_ARG;
+  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
+  const int* occ_old = nullptr;
+  if (fine_old && list_mode(fine_old)) {
+    rc = check_pair(c, coarse, fine_old);
+    if (rc) return rc;
+    if (fine_old->U != fine_new->U || fine_old->B != fine_new->B || fine_old->group_edge != fine_new->group_edge)
+      return MHD_ERR_INVALID_ARG;
+    rc = build_occupancy_into(c, fine_old, &c->occ_old, &c->cap_occ_old);
+    if (rc) return rc;
+    occ_old = c->occ_old;
+  }
+  g_max_blocks = c->max_blocks;
+  const mhd_level cw = whole_grid(coarse);
+  Work wc = make_work(&cw, 0, 0);
+  wc.groups = fine_new->groups;
+  wc.edge = fine_new->group_edge / 2;
+  wc.halo = 0;
+  wc.box = fine_new->group_edge / 2;
+  wc.items = (long long)fine_new->n_groups * wc.box * wc.box * wc.box;
+  wc.n_dev = fine_new->n_groups_dev;
+  wc.gnx = wc.gny = wc.gnz = 0;
+  wc.oshift = 1;
+  Work wf = make_work(fine_new, 0, 0);
+  if (c->cfg.prec == MHD_F64) {
+    const Coarse<double> Uc{(const double*)coarse->U, nullptr, 0.0}, Bc{(const double*)coarse->B, nullptr, 0.0};
+    k_prolong_created<double><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, Uc, Bc, (double*)fine_new->U,
+                                                                     (double*)fine_new->B, occ_old, c->cfg.gamma);
+  } else {
+    const Coarse<float> Uc{(const float*)coarse->U, nullptr, 0.0f}, Bc{(const float*)coarse->B, nullptr, 0.0f};
+    k_prolong_created<float><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, Uc, Bc, (float*)fine_new->U,
+                                                                    (float*)fine_new->B, occ_old,
+                                                                    (float)c->cfg.gamma);
+  }
   return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 

@@ -1382,6 +1382,257 @@ __global__ void __launch_bounds__(kBlock) k_correct_b(Work wc, Work wf, LevelScr
   }
 }
 
+// ---- regridding (refinement / derefinement operation, Sec. 3.3)
+// Criterion: |curl B| dx / |B| > thr on the coarse level, decided as
+// (jx^2 + jy^2 + jz^2) > thr^2 (bx^2 + by^2 + bz^2) with b the cell-centred
+// field and j = dx curl b by central differences.  Contraction is off so
+// that the decision rounds like the plain definition.
+template <typename T>
+__device__ __forceinline__ T cell_b(const Work& w, const T* __restrict__ B, int A, int i, int j, int k) {
+  const T* Ba = B + (long long)A * w.N;
+  const long long p = lin(w, wrapc(i, w.nx), wrapc(j, w.ny), wrapc(k, w.nz));
+  const long long q = lin(w, wrapc(i + (A == 0), w.nx), wrapc(j + (A == 1), w.ny), wrapc(k + (A == 2), w.nz));
+  return T(0.5) * (Ba[p] + Ba[q]);
+}
+
+template <typename T>
+__device__ bool refine_hit(const Work& w, const T* __restrict__ B, int i, int j, int k, T thr) {
+#pragma clang fp contract(off)
+  const T bx = cell_b(w, B, 0, i, j, k), by = cell_b(w, B, 1, i, j, k), bz = cell_b(w, B, 2, i, j, k);
+  const T jx = T(0.5) * (cell_b(w, B, 2, i, j + 1, k) - cell_b(w, B, 2, i, j - 1, k)) -
+               T(0.5) * (cell_b(w, B, 1, i, j, k + 1) - cell_b(w, B, 1, i, j, k - 1));
+  const T jy = T(0.5) * (cell_b(w, B, 0, i, j, k + 1) - cell_b(w, B, 0, i, j, k - 1)) -
+               T(0.5) * (cell_b(w, B, 2, i + 1, j, k) - cell_b(w, B, 2, i - 1, j, k));
+  const T jz = T(0.5) * (cell_b(w, B, 1, i + 1, j, k) - cell_b(w, B, 1, i - 1, j, k)) -
+               T(0.5) * (cell_b(w, B, 0, i, j + 1, k) - cell_b(w, B, 0, i, j - 1, k));
+  return (jx * jx + jy * jy + jz * jz) > thr * thr * (bx * bx + by * by + bz * bz);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_int(int* p, long long n, int v) {
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Marks every candidate fine group (a block of e coarse cells per axis,
+// g = gnx x gny x gnz of them) whose block widened by `buffer` cells holds a
+// coarse cell where the criterion holds.  Items: the coarse cells.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_refine_mark(Work w, const T* __restrict__ B, T thr, int e, int buffer,
+                                                        int gnx, int gny, int gnz, int* __restrict__ flags) {
+  FOR_ITEMS(w, t) {
+    int i, j, k;
+    cell_of(w, t, i, j, k);
+    if (!refine_hit(w, B, i, j, k, thr)) continue;
+    const int xs = floor_div(i - buffer, e), xe = floor_div(i + buffer, e);
+    const int ys = floor_div(j - buffer, e), ye = floor_div(j + buffer, e);
+    const int zs = floor_div(k - buffer, e), ze = floor_div(k + buffer, e);
+    for (int z = zs; z <= ze; ++z)
+      for (int y = ys; y <= ye; ++y)
+        for (int x = xs; x <= xe; ++x) {
+          const long long g = ((long long)wrapc(z, gnz) * gny + wrapc(y, gny)) * gnx + wrapc(x, gnx);
+          atomicOr(flags + g, 1);
+        }
+  }
+}
+
+// One block: the marked candidates (inside a listed coarse group when a
+// coarse occupancy map is given) become the group list in increasing
+// (z, y, x) order; at most `capacity` origins (fine cells) are written,
+// *count = min(wanted, capacity), *wanted = the number marked.
+__global__ void __launch_bounds__(1024) k_compact_groups(const int* __restrict__ flags, int gnx, int gny, int gnz,
+                                                         int e, int fine_edge, const int* __restrict__ cocc,
+                                                         int cgnx, int cgny, int coarse_edge,
+                                                         int* __restrict__ out, int capacity, int* count,
+                                                         int* wanted) {
+  __shared__ int wave_sum[16];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  const long long total = (long long)gnx * gny * gnz;
+  for (long long c0 = 0; c0 < total; c0 += 1024) {
+    const long long g = c0 + tid;
+    bool ok = false;
+    int gi = 0, gj = 0, gk = 0;
+    if (g < total && flags[g]) {
+      gi = (int)(g % gnx);
+      gj = (int)((g / gnx) % gny);
+      gk = (int)(g / ((long long)gnx * gny));
+      ok = true;
+      if (cocc) {
+        const int ci = gi * e / coarse_edge, cj = gj * e / coarse_edge, ck = gk * e / coarse_edge;
+        ok = cocc[((long long)ck * cgny + cj) * cgnx + ci] != 0;
+      }
+    }
+    const unsigned long long ballot = __ballot(ok);
+    const int before = __popcll(ballot & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_sum[wave] = __popcll(ballot);
+    __syncthreads();
+    int offset = base;
+    for (int v = 0; v < wave; ++v) offset += wave_sum[v];
+    const int pos = offset + before;
+    if (ok && pos < capacity) {
+      out[3 * pos + 0] = gi * fine_edge;
+      out[3 * pos + 1] = gj * fine_edge;
+      out[3 * pos + 2] = gk * fine_edge;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int add = 0;
+      for (int v = 0; v < 16; ++v) add += wave_sum[v];
+      base += add;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *wanted = base;
+    *count = base < capacity ? base : capacity;
+  }
+}
+
+// Children of a parent under a created fine group.  Faces of the parent
+// whose far side is a fine cell of an existing group (occ_old) keep their
+// four fine values: their mean and slopes replace the coarse ones in the
+// reconstruction and their twist d (the bilinear part) is given back through
+// the b-mid-plane faces (b = (A+1)%3) of that layer of children, -d s_g or
+// +d s_g for the lower or upper A-face, g the child's position along
+// (A+2)%3.  Writes the cells, their lower faces, and the parent's upper
+// boundary faces, except faces kept from existing groups.
+template <typename T>
+__device__ __forceinline__ void prolong_parent_kept(const Work& wc, const Work& wf, const Coarse<T>& Uc,
+                                                    const Coarse<T>& Bc, T* __restrict__ Uf, T* __restrict__ Bf,
+                                                    const int* __restrict__ occ_old, int i, int j, int k, T gam) {
+  auto old_at = [&](int x, int y, int z) {
+    if (!occ_old) return false;
+    x = wrapc(x, wf.nx); y = wrapc(y, wf.ny); z = wrapc(z, wf.nz);
+    return occ_old[((long long)(z / wf.edge) * wf.gny + y / wf.edge) * wf.gnx + x / wf.edge] != 0;
+  };
+  ParentFaces<T> P;
+  load_face_pair<T, 0>(wc, Bc, i, j, k, P);
+  load_face_pair<T, 1>(wc, Bc, i, j, k, P);
+  load_face_pair<T, 2>(wc, Bc, i, j, k, P);
+  const int C[3] = {i, j, k};
+  bool kept[3][2];
+  T fv[3][2][4];
+  T tw[3][2];
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    const int b = (A + 1) % 3, c = (A + 2) % 3;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      int X[3] = {2 * C[0], 2 * C[1], 2 * C[2]};
+      X[A] = s ? 2 * C[A] + 2 : 2 * C[A] - 1;
+      kept[A][s] = old_at(X[0], X[1], X[2]);
+      tw[A][s] = T(0);
+      if (kept[A][s]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int F[3] = {2 * C[0], 2 * C[1], 2 * C[2]};
+          F[A] = 2 * C[A] + 2 * s;
+          F[b] += q & 1;
+          F[c] += q >> 1;
+          fv[A][s][q] = Bf[(long long)A * wf.N + lin(wf, wrapc(F[0], wf.nx), wrapc(F[1], wf.ny), wrapc(F[2], wf.nz))];
+        }
+        const T* f = fv[A][s];
+        P.v[A][s] = T(0.25) * ((f[0] + f[1]) + (f[2] + f[3]));
+        P.s[A][s][0] = (f[1] - f[0]) + (f[3] - f[2]);
+        P.s[A][s][1] = (f[2] - f[0]) + (f[3] - f[1]);
+        tw[A][s] = T(0.25) * ((f[0] - f[1]) + (f[3] - f[2]));
+      }
+    }
+  }
+  T F[3][3][4];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      F[0][p][q] = fine_face<T, 0>(P, p, q);
+      F[1][p][q] = fine_face<T, 1>(P, p, q);
+      F[2][p][q] = fine_face<T, 2>(P, p, q);
+    }
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    const int b = (A + 1) % 3;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (!kept[A][s]) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) F[A][2 * s][q] = fv[A][s][q];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) F[b][1][g + 2 * s] += (s ? T(1) : T(-1)) * tw[A][s] * (g ? T(1) : T(-1));
+    }
+  }
+  T b2[8];
+  T mean_b2 = T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+    const T bx = T(0.5) * (F[0][a][b + 2 * c] + F[0][a + 1][b + 2 * c]);
+    const T by = T(0.5) * (F[1][b][c + 2 * a] + F[1][b + 1][c + 2 * a]);
+    const T bz = T(0.5) * (F[2][c][a + 2 * b] + F[2][c + 1][a + 2 * b]);
+    b2[q] = bx * bx + by * by + bz * bz;
+    mean_b2 += b2[q];
+  }
+  mean_b2 *= T(0.125);
+  const long long pc = lin(wc, i, j, k);
+  // the parent's cell-centred field from its coarse faces
+  const Coarse<T> B0 = Bc, B1 = Bc.shift(wc.N), B2 = Bc.shift(2 * wc.N);
+  const T cbx = T(0.5) * (B0[pc] + B0[nbr(wc, i, j, k, 1, 0, 0)]);
+  const T cby = T(0.5) * (B1[pc] + B1[nbr(wc, i, j, k, 0, 1, 0)]);
+  const T cbz = T(0.5) * (B2[pc] + B2[nbr(wc, i, j, k, 0, 0, 1)]);
+  const T b2c = cbx * cbx + cby * cby + cbz * cbz;
+  const T d = Uc[pc], mx = Uc[wc.N + pc], my = Uc[2 * wc.N + pc], mz = Uc[3 * wc.N + pc], e = Uc[4 * wc.N + pc];
+  const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / d;
+  const T pr = (gam - T(1)) * (e - ek - T(0.5) * b2c);
+  const bool conservative = pr - (gam - T(1)) * T(0.5) * (mean_b2 - b2c) > T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+    const long long pf = lin(wf, 2 * i + a, 2 * j + b, 2 * k + c);
+    Uf[pf] = d;
+    Uf[wf.N + pf] = mx;
+    Uf[2 * wf.N + pf] = my;
+    Uf[3 * wf.N + pf] = mz;
+    Uf[4 * wf.N + pf] = conservative ? e + T(0.5) * (b2[q] - mean_b2) : pr / (gam - T(1)) + ek + T(0.5) * b2[q];
+    if (a || !kept[0][0]) Bf[pf] = F[0][a][b + 2 * c];
+    if (b || !kept[1][0]) Bf[wf.N + pf] = F[1][b][c + 2 * a];
+    if (c || !kept[2][0]) Bf[2 * wf.N + pf] = F[2][c][a + 2 * b];
+  }
+  // the parent's upper boundary faces
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    if (kept[A][1]) continue;
+    const int b = (A + 1) % 3, c = (A + 2) % 3;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int G[3] = {2 * C[0], 2 * C[1], 2 * C[2]};
+      G[A] += 2;
+      G[b] += q & 1;
+      G[c] += q >> 1;
+      Bf[(long long)A * wf.N + lin(wf, wrapc(G[0], wf.nx), wrapc(G[1], wf.ny), wrapc(G[2], wf.nz))] = F[A][2][q];
+    }
+  }
+}
+
+// Created fine groups: items are the coarse cells under the groups of the
+// new list; groups present in the old list (occ_old) keep their data.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_created(Work wc, Work wf, Coarse<T> Uc, Coarse<T> Bc,
+                                                            T* __restrict__ Uf, T* __restrict__ Bf,
+                                                            const int* __restrict__ occ_old, T gam) {
+  FOR_ITEMS(wc, t) {
+    int i, j, k;
+    cell_of(wc, t, i, j, k);
+    if (occ_old) {
+      const int I = wrapc(2 * i, wf.nx), J = wrapc(2 * j, wf.ny), K = wrapc(2 * k, wf.nz);
+      if (occ_old[((long long)(K / wf.edge) * wf.gny + J / wf.edge) * wf.gnx + I / wf.edge] != 0) continue;
+    }
+    prolong_parent_kept(wc, wf, Uc, Bc, Uf, Bf, occ_old, i, j, k, gam);
+  }
+}
+
 // Time-averaged registers of a sub-cycled level: R = (reset ? 0 : R) + w S
 // over the final fluxes and EMFs S of the level's last update.  Whole grid
 // (sb = 0): every slot; group list: the slots of each group's cells and of

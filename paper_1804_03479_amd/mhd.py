@@ -57,7 +57,8 @@ EXPORTS = ["mhd_abi_version", "mhd_strerror", "mhd_required_ghost", "mhd_init", 
            "mhd_mlp_num_params", "mhd_mlp_set_weights", "mhd_mlp_forward", "mhd_mlp_backward",
            "mhd_mlp_train_step", "mhd_mlp_prepare", "mhd_mlp_face_flux", "mhd_set_capture", "mhd_correct",
            "mhd_advance_graph", "mhd_set_launch", "mhd_cfl_dt_min", "mhd_prolong", "mhd_restrict",
-           "mhd_prolong_time", "mhd_accumulate_registers", "mhd_dt_subdivide"]
+           "mhd_prolong_time", "mhd_accumulate_registers", "mhd_dt_subdivide", "mhd_regrid_flag",
+           "mhd_prolong_new_groups"]
 
 
 def load(path: str = LIB_PATH):
@@ -103,6 +104,9 @@ def load(path: str = LIB_PATH):
     lib.mhd_prolong_time.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc), D,
                                      ctypes.POINTER(LevelDesc), I]
     lib.mhd_accumulate_registers.argtypes = [P, ctypes.POINTER(LevelDesc), D, I]
+    lib.mhd_regrid_flag.argtypes = [P, ctypes.POINTER(LevelDesc), D, I, I, P, I, P, P]
+    lib.mhd_prolong_new_groups.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc),
+                                           ctypes.POINTER(LevelDesc)]
     lib.mhd_prolong.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc), I]
     lib.mhd_restrict.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc)]
     lib.mhd_correct.argtypes = [P, ctypes.POINTER(LevelDesc), P, ctypes.POINTER(LevelDesc), P, I]
@@ -274,6 +278,27 @@ class Solver:
         do = None if coarse_old is None else ctypes.byref(coarse_old.desc())
         _check(self.lib.mhd_prolong_time(self.h, do, ctypes.byref(dc), float(alpha), ctypes.byref(df), int(halo)),
                "mhd_prolong_time")
+
+    def regrid_flag(self, coarse: Level, threshold: float, buffer: int, fine_edge: int, groups_out: torch.Tensor,
+                    count: torch.Tensor, wanted: torch.Tensor):
+        """Group list of the level above coarse from the refinement criterion
+        into groups_out (int32 (capacity, 3)), count and wanted (int32 (1,))."""
+        for t in (groups_out, count, wanted):
+            if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("regrid outputs must be contiguous int32 device tensors")
+        if groups_out.dim() != 2 or groups_out.shape[1] != 3:
+            raise ValueError("groups_out must be (capacity, 3)")
+        d = coarse.desc()
+        _check(self.lib.mhd_regrid_flag(self.h, ctypes.byref(d), float(threshold), int(buffer), int(fine_edge),
+                                        ctypes.c_void_p(groups_out.data_ptr()), int(groups_out.shape[0]),
+                                        ctypes.c_void_p(count.data_ptr()), ctypes.c_void_p(wanted.data_ptr())),
+               "mhd_regrid_flag")
+
+    def prolong_new_groups(self, coarse: Level, fine_new: Level, fine_old: Level | None):
+        dc, dn = coarse.desc(), fine_new.desc()
+        do = None if fine_old is None else ctypes.byref(fine_old.desc())
+        _check(self.lib.mhd_prolong_new_groups(self.h, ctypes.byref(dc), ctypes.byref(dn), do),
+               "mhd_prolong_new_groups")
 
     def accumulate_registers(self, lv: Level, weight: float, reset: bool):
         d = lv.desc()

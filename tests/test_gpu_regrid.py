@@ -1,0 +1,204 @@
+"""Regridding (paper Sec. 3.3, refinement / derefinement) through the C ABI
+against the oracle: the group list from the criterion (bit-exact, FP64
+decisions), the data of created groups next to an existing one (1e-14), and
+a hierarchy that regrids between steps (conservation, div B, graph replay
+across a regrid)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from oracle import amr as oamr  # noqa: E402
+from paper_1804_03479_amd import inputs  # noqa: E402
+from paper_1804_03479_amd.amr import Hierarchy  # noqa: E402
+from paper_1804_03479_amd.mhd import Level, MHDError, Solver  # noqa: E402
+
+from amr_cases import regrid_case  # noqa: E402
+
+
+def level(U, B, dx, groups=None, dtype=torch.float64):
+    g = None if groups is None else torch.from_numpy(np.asarray(groups, np.int32).reshape(-1, 3)).cuda()
+    return Level(torch.from_numpy(U).to("cuda", dtype).contiguous(), torch.from_numpy(B).to("cuda", dtype).contiguous(),
+                 dx, groups=g)
+
+
+def gpu_list(s, coarse, thr, buffer, capacity=64, fine_edge=16):
+    out = torch.full((capacity, 3), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    wanted = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s.regrid_flag(coarse, thr, buffer, fine_edge, out, cnt, wanted)
+    torch.cuda.synchronize()
+    n = int(cnt.item())
+    return out[:n].cpu().numpy(), int(wanted.item())
+
+
+def test_regrid_list_on_the_abc_closed_form():
+    n = 32
+    Bc = np.stack(inputs.abc_face_field(n))
+    U = np.ones((5, n, n, n))
+    s = Solver("ctu", "ppm", "hlld")
+    lv = level(U, Bc, 1.0 / n)
+    t = np.sin(2 * np.pi / n)
+    g, w = gpu_list(s, lv, t * (1 - 1e-9), 1)
+    assert w == 64 and np.array_equal(g, oamr.refine_groups(Bc, t * (1 - 1e-9)))
+    g, w = gpu_list(s, lv, t * (1 + 1e-9), 1)
+    assert w == 0 and len(g) == 0
+
+
+@pytest.mark.parametrize("buffer", [0, 1, 4, 8])
+def test_regrid_list_matches_oracle(buffer):
+    n = 32
+    rng = np.random.default_rng(buffer)
+    Bc = np.ones((3, n, n, n)) + 0.02 * rng.standard_normal((3, n, n, n))
+    for (i, j, k) in [(20, 9, 5), (3, 30, 17), (31, 0, 0)]:
+        Bc[1, k, j, i] += 1.0
+    U = np.ones((5, n, n, n))
+    s = Solver("ctu", "ppm", "hlld")
+    lv = level(U, Bc, 1.0 / n)
+    for thr in (0.05, 0.2):
+        want = oamr.refine_groups(Bc, thr, buffer=buffer)
+        g, w = gpu_list(s, lv, thr, buffer)
+        assert w == len(want) and np.array_equal(g, want), (thr, buffer)
+    # capacity: the first groups in order, the count capped, the wanted number reported
+    want = oamr.refine_groups(Bc, 0.05, buffer=buffer)
+    if len(want) > 3:
+        g, w = gpu_list(s, lv, 0.05, buffer, capacity=3)
+        assert w == len(want) and np.array_equal(g, want[:3])
+
+
+def test_regrid_list_nests_in_the_coarse_groups():
+    n = 64
+    rng = np.random.default_rng(7)
+    Bc = np.ones((3, n, n, n)) + 0.05 * rng.standard_normal((3, n, n, n))
+    cg = [(0, 0, 0), (16, 32, 48), (48, 16, 0)]
+    s = Solver("ctu", "ppm", "hlld")
+    lv = level(np.ones((5, n, n, n)), Bc, 1.0 / n, groups=cg)
+    want = oamr.refine_groups(Bc, 0.05, buffer=1, coarse_groups=cg, coarse_edge=16)
+    g, w = gpu_list(s, lv, 0.05, 1, capacity=128)
+    assert len(want) and w == len(want) and np.array_equal(g, want)
+
+
+def test_regrid_rejects_bad_arguments():
+    n = 32
+    s = Solver("ctu", "ppm", "hlld")
+    lv = level(np.ones((5, n, n, n)), np.ones((3, n, n, n)), 1.0 / n)
+    out = torch.zeros((4, 3), dtype=torch.int32, device="cuda")
+    c = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for thr, buf, edge in ((-1.0, 1, 16), (0.1, 9, 16), (0.1, 1, 5), (float("nan"), 1, 16)):
+        with pytest.raises(MHDError):
+            s.regrid_flag(lv, thr, buf, edge, out, c, c.clone())
+
+
+def test_created_groups_match_oracle():
+    p, Uc, Bc, Uf, Bf, old = regrid_case(seed=2)
+    new = np.array([[0, 0, 0], [16, 0, 0], [0, 16, 0], [16, 16, 16]], dtype=np.int32)
+    U2, B2 = oamr.prolong_new_groups(Uc, Bc, Uf, Bf, new, old)
+    s = Solver("ctu", "ppm", "hlld")
+    c = level(Uc, Bc, p["dx"])
+    f_old = level(Uf, Bf, p["dx"] / 2, groups=old)
+    f_new = Level(f_old.U, f_old.B, f_old.dx, groups=torch.from_numpy(new).cuda())
+    s.prolong_new_groups(c, f_new, f_old)
+    torch.cuda.synchronize()
+    assert np.allclose(f_new.U.cpu().numpy(), U2, rtol=1e-14, atol=1e-14)
+    assert np.allclose(f_new.B.cpu().numpy(), B2, rtol=1e-14, atol=1e-14)
+    # without an old list every new group is created
+    f0 = level(np.zeros_like(Uf), np.zeros_like(Bf), p["dx"] / 2, groups=new)
+    s.prolong_new_groups(c, f0, None)
+    torch.cuda.synchronize()
+    U3, B3 = oamr.prolong_new_groups(Uc, Bc, np.zeros_like(Uf), np.zeros_like(Bf), new, np.zeros((0, 3), np.int32))
+    assert np.allclose(f0.U.cpu().numpy(), U3, rtol=1e-14, atol=1e-14)
+    assert np.allclose(f0.B.cpu().numpy(), B3, rtol=1e-14, atol=1e-14)
+
+
+def _indicator(Bc):
+    bx = 0.5 * (Bc[0] + np.roll(Bc[0], -1, 2))
+    by = 0.5 * (Bc[1] + np.roll(Bc[1], -1, 1))
+    bz = 0.5 * (Bc[2] + np.roll(Bc[2], -1, 0))
+    d = lambda f, a: 0.5 * (np.roll(f, -1, a) - np.roll(f, 1, a))   # noqa: E731
+    j2 = (d(bz, 1) - d(by, 0)) ** 2 + (d(bx, 0) - d(bz, 2)) ** 2 + (d(by, 2) - d(bx, 1)) ** 2
+    return np.sqrt(j2 / (bx * bx + by * by + bz * bz))
+
+
+def _threshold(Bc, current, lo=8, hi=48):
+    """A threshold whose oracle list holds lo..hi groups and both adds to and
+    drops from the current list."""
+    ind = _indicator(Bc)
+    cur = {tuple(x) for x in current}
+    for q in (0.99995, 0.9999, 0.9995, 0.999, 0.998, 0.995, 0.99, 0.98):
+        thr = float(np.quantile(ind, q))
+        want = {tuple(x) for x in oamr.refine_groups(Bc, thr, buffer=1)}
+        if lo <= len(want) <= hi and want - cur and cur - want:
+            return thr
+    raise AssertionError("no threshold gives a changing list")
+
+
+def _root_totals(h):
+    s, lv = h.solvers[0], h.levels[0]
+    t = np.array(s.sums(lv)[:5])
+    U = lv.U.double().cpu().numpy()
+    return t, np.array([np.abs(U[m]).sum() for m in range(5)]) * lv.dx ** 3
+
+
+@pytest.mark.parametrize("subcycle", [False, True])
+def test_hierarchy_regrid_conserves_and_stays_solenoidal(subcycle):
+    h = Hierarchy(32, [5, 9], prec="f64", noise=0.1, seed=1, capacity=128, subcycle=subcycle)
+    t0, scale = _root_totals(h)
+    for _ in range(2):
+        h.step()
+    h.stream.synchronize()
+    before = h.levels[1].groups[:h.group_counts()[0]].cpu().numpy().copy()
+    thr = _threshold(h.levels[0].B.cpu().numpy(), before)
+    h.regrid(thr, buffer=1)
+    wanted = h.check_regrid()
+    n1 = h.group_counts()[0]
+    after = h.levels[1].groups[:n1].cpu().numpy()
+    assert np.array_equal(after, oamr.refine_groups(h.levels[0].B.cpu().numpy(), thr, buffer=1))
+    created = {tuple(x) for x in after} - {tuple(x) for x in before}
+    removed = {tuple(x) for x in before} - {tuple(x) for x in after}
+    assert created and removed and wanted[0] == n1
+    # level 2 nests in the new level 1
+    lv1 = {tuple(x // 16) for x in after}
+    for x in h.levels[2].groups[:h.group_counts()[1]].cpu().numpy():
+        assert tuple((x // 2) // 16) in lv1
+    for lvl_i, lv in enumerate(h.levels):
+        mx, _ = h.solvers[lvl_i].divb(lv)
+        assert mx * lv.dx <= 1e-12, (lvl_i, mx)
+    for _ in range(2):
+        h.step()
+    h.stream.synchronize()
+    t1, _ = _root_totals(h)
+    assert (np.abs(t1 - t0) / scale).max() <= 1e-13
+    for lvl_i, lv in enumerate(h.levels):
+        mx, _ = h.solvers[lvl_i].divb(lv)
+        assert mx * lv.dx <= 1e-12, (lvl_i, mx)
+    h.close()
+
+
+def test_captured_step_stays_valid_across_a_regrid():
+    a = Hierarchy(32, [5, 9], prec="f32", seed=2, capacity=128)
+    b = Hierarchy(32, [5, 9], prec="f32", seed=2, capacity=128)
+    g = a.capture()
+    b.step()
+    a.replay(g)
+    b.step()
+    a.stream.synchronize()
+    b.stream.synchronize()
+    cur = a.levels[1].groups[:a.group_counts()[0]].cpu().numpy()
+    thr = _threshold(a.levels[0].B.double().cpu().numpy(), cur)
+    for h in (a, b):
+        h.regrid(thr)
+        h.check_regrid()
+    for rep in range(2):
+        a.replay(g)
+        b.step()
+        a.stream.synchronize()
+        b.stream.synchronize()
+        for x, y in zip(a.levels, b.levels):
+            assert torch.equal(x.U, y.U) and torch.equal(x.B, y.B), rep
+    a.close()
+    b.close()
