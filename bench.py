@@ -243,6 +243,80 @@ def run_amr(n_root: int, counts, steps: int, warmup: int, seed: int, tune: bool)
                           "value": sum(upd) / (ms_sub * 1e-3)}}
 
 
+def run_amr_criterion(n_root: int, steps: int, warmup: int, fraction: float = 0.187, t_cross: float = 1.3,
+                      capacity: int = 2048):
+    """The n = 2 ABC relaxation problem evolved on the root to t = 1.3 L/C_s
+    (current sheets formed), then regridded by |curl B| dx / |B| > thr with
+    thr chosen so that level 1 covers about `fraction` of the root (the
+    paper's 18.7 % at that time); the same threshold lists level 2 from
+    level 1.  Times the hierarchy from one HIP graph, shared dt and
+    sub-cycled."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1804_03479_amd import inputs
+    from paper_1804_03479_amd.amr import Hierarchy
+    from paper_1804_03479_amd.mhd import Solver
+    p = inputs.abc_relaxation_problem(n_root)
+    s = Solver("ctu", "ppm", "hlld", "f32")
+    W5 = torch.from_numpy(np.stack([p["rho"], p["vx"], p["vy"], p["vz"], p["p"]]))
+    B = torch.from_numpy(np.stack([p["bx"], p["by"], p["bz"]]))
+    lv = s.level_from_primitives(W5, B, p["dx"])
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t_stop = t_cross / math.sqrt(5.0 / 3.0)
+    evolve = 0
+    while float(t.item()) < t_stop:
+        for _ in range(100):
+            s.advance(lv, t_dev=t)
+        evolve += 100
+    torch.cuda.synchronize()
+    # threshold for the wanted level-1 coverage (bisection on the device count)
+    cand = (2 * n_root // 16) ** 3
+    out = torch.zeros((cand, 3), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    wanted = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lo, hi = 0.0, 4.0
+    for _ in range(30):
+        mid = 0.5 * (lo + hi)
+        s.regrid_flag(lv, mid, 1, 16, out, cnt, wanted)
+        if int(wanted.item()) > fraction * cand:
+            lo = mid
+        else:
+            hi = mid
+    thr = hi
+    res = {"evolved_root_steps": evolve, "t_over_tcross": float(t.item()) * math.sqrt(5.0 / 3.0), "threshold": thr}
+    for sub in (False, True):
+        h = Hierarchy(n_root, [0, 0], prec="f32", subcycle=sub, capacity=capacity, problem=p)
+        h.reset_root(lv.U, lv.B)
+        h.regrid(thr)
+        res["wanted"] = h.check_regrid()
+        counts = h.group_counts()
+        st = h.stream
+        for _ in range(warmup):
+            h.step()
+        g = h.capture()
+        for _ in range(warmup):
+            h.replay(g)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            h.replay(g)
+        e1.record(st)
+        st.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        upd = h.updates_per_step()
+        key = "subcycled" if sub else "shared"
+        res[key] = {"ms_per_root_step_graph": ms, "updates_per_root_step": upd, "value": sum(upd) / (ms * 1e-3)}
+        res["groups_per_level"] = counts
+        res["volume_fraction_per_level"] = [c * 16 ** 3 / int(np.prod(x.shape))
+                                            for c, x in zip(counts, h.levels[1:])]
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+    s.close()
+    return res
+
+
 def l1_vs_oracle(wl: dict, n: int, seed: int, nsteps: int, precs):
     """Relative L1 error (rho, e, B) of each GPU form after nsteps from the
     same initial state against the FP64 oracle; returns the oracle time too."""
@@ -436,6 +510,9 @@ def main():
             r = run_amr(n, cs, args.steps, args.warmup, args.seed, tune=not args.no_tune)
             r["workload"] = f"abc{n}_root_plus_{len(cs)}_levels_ctu_ppm_hlld_ct_f32"
             forms["amr_f32_" + "_".join(map(str, cs))] = r
+        r = run_amr_criterion(n, args.steps, args.warmup)
+        r["workload"] = f"abc_n2_{n}_root_plus_2_levels_criterion_lists_ctu_ppm_hlld_ct_f32"
+        forms["amr_f32_criterion"] = r
 
     if head_key is None:
         print(json.dumps({"forms": forms}))

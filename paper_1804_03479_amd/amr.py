@@ -80,7 +80,8 @@ class Hierarchy:
 
     def __init__(self, n_root: int, counts, scheme="ctu", recon="ppm", riemann="hlld", prec="f32",
                  noise: float = 0.1, seed: int = 0, edge: int = 16, stream: torch.cuda.Stream | None = None,
-                 correct: bool = True, subcycle: bool = False, capacity: int | None = None):
+                 correct: bool = True, subcycle: bool = False, capacity: int | None = None,
+                 problem: inputs.Problem | None = None):
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.correct = correct
         self.subcycle = subcycle
@@ -89,23 +90,25 @@ class Hierarchy:
             self.solvers = [Solver(scheme, recon, riemann, prec, stream=self.stream)
                             for _ in range(len(self.groups) + 1)]
             s0 = self.solvers[0]
-            p = inputs.abc_problem(n_root, noise, seed=seed)
+            p = problem if problem is not None else inputs.abc_problem(n_root, noise, seed=seed)
             W5 = torch.from_numpy(np.stack([p["rho"], p["vx"], p["vy"], p["vz"], p["p"]]))
             B = torch.from_numpy(np.stack([p["bx"], p["by"], p["bz"]]))
             root = s0.level_from_primitives(W5, B, p["dx"])
             self.levels = [root]
             for lvl, g in enumerate(self.groups, start=1):
-                n = n_root << lvl
-                U = torch.empty((5, n, n, n), dtype=s0.dtype, device="cuda")
-                Bf = torch.empty((3, n, n, n), dtype=s0.dtype, device="cuda")
+                shape = tuple(x << lvl for x in root.shape)
+                U = torch.empty((5,) + shape, dtype=s0.dtype, device="cuda")
+                Bf = torch.empty((3,) + shape, dtype=s0.dtype, device="cuda")
                 fine = Level(U, Bf, p["dx"] / (1 << lvl))
                 self.solvers[lvl].prolong(self.levels[-1], fine)     # whole level, initial data
                 if capacity is None:
                     fine.set_groups(torch.from_numpy(g).cuda())
                 else:
-                    if len(g) > capacity:
+                    # at most every candidate group of the level
+                    cap = min(capacity, int(np.prod(shape)) // edge ** 3)
+                    if len(g) > cap:
                         raise ValueError("initial group list longer than the capacity")
-                    buf = torch.zeros((capacity, 3), dtype=torch.int32, device="cuda")
+                    buf = torch.zeros((cap, 3), dtype=torch.int32, device="cuda")
                     buf[:len(g)] = torch.from_numpy(g).cuda()
                     fine.set_groups(buf)
                     fine.n_groups_dev = torch.tensor([len(g)], dtype=torch.int32, device="cuda")
@@ -152,20 +155,52 @@ class Hierarchy:
         with torch.cuda.stream(self.stream):
             for lvl in range(1, len(self.levels)):
                 s, coarse, fine = self.solvers[lvl], self.levels[lvl - 1], self.levels[lvl]
-                s.regrid_flag(coarse, threshold, buffer, self.edge, self._new, self._count,
-                              self._wanted[lvl - 1:lvl])
-                new = Level(fine.U, fine.B, fine.dx, groups=self._new, group_edge=self.edge)
+                cap = fine.groups.shape[0]
+                buf = self._new[:cap]
+                s.regrid_flag(coarse, threshold, buffer, self.edge, buf, self._count, self._wanted[lvl - 1:lvl])
+                new = Level(fine.U, fine.B, fine.dx, groups=buf, group_edge=self.edge)
                 new.n_groups_dev = self._count
                 s.prolong_new_groups(coarse, new, fine)
-                fine.groups.copy_(self._new)
+                fine.groups.copy_(buf)
                 fine.n_groups_dev.copy_(self._count)
+
+    def run(self, t_end: float, threshold: float | None = None, regrid_every: int = 0, buffer: int = 1):
+        """Root steps to t_end (the last one shortened), regridding every
+        regrid_every root steps; returns (steps, per-regrid group counts)."""
+        t, steps, counts = 0.0, 0, []
+        while t < t_end * (1.0 - 1e-12):
+            if threshold is not None and regrid_every and steps and steps % regrid_every == 0:
+                self.regrid(threshold, buffer)
+                self.check_regrid()
+                counts.append(self.group_counts())
+            self.step(dt_max=t_end - t)
+            self.stream.synchronize()
+            t += float(self.dts[0].item())
+            steps += 1
+        return steps, counts
+
+    def reset_root(self, U: torch.Tensor, B: torch.Tensor):
+        """Replace the root state (conserved U, face B of the root's shape and
+        dtype), refill every finer level from it by whole-level prolongation
+        and empty the group lists (capacity mode; regrid() lists them again)."""
+        if self.capacity is None:
+            raise RuntimeError("reset_root needs a Hierarchy built with a list capacity")
+        with torch.cuda.stream(self.stream):
+            self.levels[0].U.copy_(U)
+            self.levels[0].B.copy_(B)
+            for lvl in range(1, len(self.levels)):
+                fine = self.levels[lvl]
+                whole = Level(fine.U, fine.B, fine.dx)
+                self.solvers[lvl].prolong(self.levels[lvl - 1], whole)
+                fine.n_groups_dev.zero_()
 
     def check_regrid(self):
         """Groups each level wanted at the last regrid; raises if one did not fit."""
         self.stream.synchronize()
         wanted = self._wanted[:len(self.levels) - 1].cpu().tolist()
-        if max(wanted, default=0) > self.capacity:
-            raise RuntimeError(f"regrid wanted {wanted} groups per level, capacity {self.capacity}")
+        caps = [lv.groups.shape[0] for lv in self.levels[1:]]
+        if any(w > c for w, c in zip(wanted, caps)):
+            raise RuntimeError(f"regrid wanted {wanted} groups per level, capacities {caps}")
         return wanted
 
     def updates_per_step(self):
@@ -178,12 +213,13 @@ class Hierarchy:
         for s, b in zip(self.solvers, shapes):
             s.set_launch(int(b))
 
-    def shared_dt(self):
+    def shared_dt(self, dt_max: float = float("inf")):
         """Device steps of all levels: the shared CFL minimum, or with
-        sub-cycling dt_0 = min_l 2^l dt_cfl(l) and dt_l = dt_0 / 2^l."""
+        sub-cycling dt_0 = min_l 2^l dt_cfl(l) and dt_l = dt_0 / 2^l; dt_0 is
+        at most dt_max."""
         with torch.cuda.stream(self.stream):
             d0 = self.dts[:1]
-            d0.fill_(float("inf"))
+            d0.fill_(float(dt_max))
             for lvl, (s, lv) in enumerate(zip(self.solvers, self.levels)):
                 s.cfl_dt_min(lv, d0, scale=float(1 << lvl) if self.subcycle else 1.0)
             for lvl in range(1, len(self.levels)):
@@ -221,10 +257,10 @@ class Hierarchy:
                 cs.accumulate_registers(child, 0.5, reset=sub == 0)
         self._close_level(lvl + 1, registers=True)
 
-    def step(self):
+    def step(self, dt_max: float = float("inf")):
         """One root step of all levels (asynchronous on self.stream)."""
         with torch.cuda.stream(self.stream):
-            self.shared_dt()
+            self.shared_dt(dt_max)
             if self.subcycle:
                 self._advance(0)
                 return

@@ -23,6 +23,8 @@ Problems:
   ABC field with A = B = C = sqrt(P0), the printed unstable eigenmode of
   Eqs. 21-23 added (exact face averages), and a uniform drift along the box
   diagonal of magnitude C_s / (8 sqrt(gamma)).
+* ``orszag_tang``: the vortex of Sec. 4.1(iii), Eq. 25 (2D, uniform along z
+  on a periodic slab).
 * ``shock_tube``: the 1D Riemann problems of Table 1 (RJ2a, Torrilhon) on a
   periodic pencil: the left state fills the middle half of the pencil, the
   right state the rest, so the tabulated left|right discontinuity sits at
@@ -40,7 +42,7 @@ import math
 import numpy as np
 
 __all__ = ["abc_problem", "smooth_problem", "abc_face_field", "velocity_noise", "Problem", "shock_tube",
-           "SHOCK_TUBES", "abc_relaxation_problem", "eigenmode_face_field"]
+           "SHOCK_TUBES", "abc_relaxation_problem", "eigenmode_face_field", "orszag_tang"]
 
 
 class Problem(dict):
@@ -275,3 +277,26 @@ def abc_relaxation_problem(n: int, rho0: float = 1.0, p0: float = 1.0, gamma: fl
     v = velocity_noise(shape, noise * cs, seed) if noise > 0.0 else np.zeros((3,) + shape)
     return Problem(rho=np.full(shape, rho0), vx=v[0] + v0, vy=v[1] + v0, vz=v[2] + v0,
                    p=np.full(shape, p0), bx=bx, by=by, bz=bz, dx=1.0 / n)
+
+
+def orszag_tang(n: int, nz: int = 16, gamma: float = 5.0 / 3.0, rho0: float = 25.0 / (36.0 * math.pi),
+                p0: float = 5.0 / (12.0 * math.pi)) -> Problem:
+    """Sec. 4.1(iii), Eq. 25 on an n x n x nz periodic slab of side 1 in x, y
+    (cells 1/n), uniform along z: V = C_s (-sin 2 pi y, sin 2 pi x, 0),
+    B = sqrt(P0/gamma) (-sin 2 pi y, sin 4 pi x, 0), rho0, P0 constant
+    (defaults give C_s = 1).  Bx on x-faces and By on y-faces are exact
+    face averages (each depends on one transverse coordinate only), so the
+    discrete divergence is zero."""
+    dx = 1.0 / n
+    shape = (nz, n, n)
+    cs = math.sqrt(gamma * p0 / rho0)
+    b0 = math.sqrt(p0 / gamma)
+    x = _centres(n, dx)[None, None, :]
+    y = _centres(n, dx)[None, :, None]
+    k1, k2 = 2.0 * math.pi, 4.0 * math.pi
+    vx = np.broadcast_to(-cs * np.sin(k1 * y), shape).copy()
+    vy = np.broadcast_to(cs * np.sin(k1 * x), shape).copy()
+    bx = np.broadcast_to(-b0 * _cell_avg_factor(k1, dx) * np.sin(k1 * y), shape).copy()
+    by = np.broadcast_to(b0 * _cell_avg_factor(k2, dx) * np.sin(k2 * x), shape).copy()
+    return Problem(rho=np.full(shape, rho0), vx=vx, vy=vy, vz=np.zeros(shape), p=np.full(shape, p0),
+                   bx=bx, by=by, bz=np.zeros(shape), dx=dx)
