@@ -317,6 +317,68 @@ def run_amr_criterion(n_root: int, steps: int, warmup: int, fraction: float = 0.
     return res
 
 
+def run_c4(n_root: int, count: int, steps: int, warmup: int, seed: int, params, drift_root: int = 64,
+           drift_count: int = 7, drift_steps: int = 100):
+    """Full stack: FP32 CTU+PPM with the learned flux (HLLD fallback) on an
+    AMR hierarchy (n_root^3 ABC root, noise 0.3, one refined level of
+    `count` groups), `steps` root steps replayed from one HIP graph; energy
+    budget and fallback fraction over the run.  Then the L1 drift of the same
+    stack against the FP64 HLLD hierarchy at drift_root^3 + one level after
+    drift_steps steps (root data, which holds the restricted fine data)."""
+    import numpy as np
+    import torch
+    from paper_1804_03479_amd.amr import Hierarchy
+    from paper_1804_03479_amd.mhd import MlpOps
+    h = Hierarchy(n_root, [count], "ctu", "ppm", "mlp", "f32", noise=0.3, seed=seed)
+    for sv in h.solvers:
+        MlpOps(sv).set_weights(params)
+    st = h.stream
+    e_start = h.s.sums(h.levels[0])
+    fb0 = sum(sv.fallback_count() for sv in h.solvers)
+    for _ in range(warmup):
+        h.step()
+    g = h.capture()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        h.replay(g)
+    e1.record(st)
+    st.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    total_steps = warmup + 1 + steps
+    e_end = h.s.sums(h.levels[0])
+    fb = sum(sv.fallback_count() for sv in h.solvers) - fb0
+    cells = h.cells_per_level()
+    mx = max(sv.divb(lv)[0] * lv.dx for sv, lv in zip(h.solvers, h.levels))
+    h.close()
+    del h
+    torch.cuda.empty_cache()
+    out = {"n_root": n_root, "groups": count, "cells_per_level": cells, "noise": 0.3, "steps": total_steps,
+           "timed_steps": steps, "ms_per_step_graph": ms, "value": sum(cells) / (ms * 1e-3),
+           "algorithmic_GBps": sum(cells) / (ms * 1e-3) * 64 / 1e9,
+           "fallback_fraction": fb / (6.0 * sum(cells) * total_steps),
+           "energy": {"E_T": [e_start[4], e_end[4]], "U_B": [e_start[5], e_end[5]], "U_V": [e_start[6], e_end[6]]},
+           "E_T_drift": abs(e_end[4] - e_start[4]) / abs(e_start[4]), "max_divb_dx": mx}
+    # drift of the stack against the FP64 HLLD hierarchy (same steps, same time)
+    ref = Hierarchy(drift_root, [drift_count], "ctu", "ppm", "hlld", "f64", noise=0.3, seed=seed)
+    run = Hierarchy(drift_root, [drift_count], "ctu", "ppm", "mlp", "f32", noise=0.3, seed=seed)
+    for sv in run.solvers:
+        MlpOps(sv).set_weights(params)
+    for _ in range(drift_steps):
+        ref.step()
+        ref.stream.synchronize()
+        run.step(dt_max=float(ref.dts[0].item()))
+    run.stream.synchronize()
+    Ur, Br = ref.levels[0].U.cpu().numpy(), ref.levels[0].B.cpu().numpy()
+    Ug, Bg = run.levels[0].U.double().cpu().numpy(), run.levels[0].B.double().cpu().numpy()
+    rel = lambda a, b: float(np.abs(a - b).mean() / np.abs(b).mean())   # noqa: E731
+    out["l1_drift_vs_f64_hlld"] = {"root": drift_root, "groups": drift_count, "steps": drift_steps,
+                                   "rho": rel(Ug[0], Ur[0]), "e": rel(Ug[4], Ur[4]), "B": rel(Bg, Br)}
+    ref.close()
+    run.close()
+    return out
+
+
 def l1_vs_oracle(wl: dict, n: int, seed: int, nsteps: int, precs):
     """Relative L1 error (rho, e, B) of each GPU form after nsteps from the
     same initial state against the FP64 oracle; returns the oracle time too."""
@@ -405,6 +467,8 @@ def main():
     ap.add_argument("--amr-counts", default="511,1024",
                     help="patch groups (16^3 cells) of each refined level; also runs 7,64")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--c4-steps", type=int, default=1000,
+                    help="root steps of the full-stack form (AMR + learned flux, FP32); 0 skips it")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print one line with cell-updates/s of the CTU form "
                          "over grid sizes 32^3 .. 512^3 (FP32) and .. 384^3 (FP64)")
@@ -503,6 +567,10 @@ def main():
                      "unit": "TFLOP/s", "frac": round(flops / t_flux / 1e12 / MFMA_BF16_PEAK, 5),
                      "flop_per_face": MLP_FLOP_PER_FACE}
         forms["ctu_f32_mlp"] = e
+        if args.c4_steps > 0:
+            r = run_c4(2 * n, 511, args.c4_steps, args.warmup, args.seed, params)
+            r["workload"] = f"abc{2 * n}_root_plus_1_level_ctu_ppm_mlp_hlld_fallback_ct_f32"
+            forms["c4_full_stack"] = r
 
     if "amr" in todo:
         counts = [int(x) for x in args.amr_counts.split(",")]
