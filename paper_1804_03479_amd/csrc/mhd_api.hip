@@ -22,6 +22,7 @@
 
 #include "../../include/mhd.h"
 #include "mhd_kernels.hpp"
+#include "mhd_amr.hpp"
 
 using namespace mhd;
 
@@ -700,334 +701,9 @@ int mhd_cfl_dt_min(mhd_ctx c, const mhd_level* lv, double scale, double* dt_dev)
 
 }  // extern "C"
 
-namespace {
-int check_pair(mhd_ctx_s* c, const mhd_level* coarse, const mhd_level* fine) {
-  int rc = check_level(c, coarse);
-  if (rc) return rc;
-  rc = check_level(c, fine);
-  if (rc) return rc;
-  if (fine->nx != 2 * coarse->nx || fine->ny != 2 * coarse->ny || fine->nz != 2 * coarse->nz)
-    return MHD_ERR_INVALID_ARG;
-  return MHD_OK;
-}
-
-// the coarse side of a transfer is addressed as a whole grid, whatever its list
-mhd_level whole_grid(const mhd_level* lv) {
-  mhd_level w = *lv;
-  w.n_groups = 0;
-  w.groups = nullptr;
-  w.n_groups_dev = nullptr;
-  return w;
-}
-
-template <typename T>
-void launch_prolong(mhd_ctx_s* c, const mhd_level* coarse_old, const mhd_level* coarse, double alpha,
-                    const mhd_level* fine, int halo) {
-  // alpha = 0: the old state alone; alpha = 1: the new state alone
-  const bool interp = coarse_old && alpha > 0.0 && alpha < 1.0;
-  const mhd_level* first = (coarse_old && alpha == 0.0) ? coarse_old : coarse;
-  const Coarse<T> Uc{(const T*)(interp ? coarse_old->U : first->U), interp ? (const T*)coarse->U : nullptr, (T)alpha};
-  const Coarse<T> Bc{(const T*)(interp ? coarse_old->B : first->B), interp ? (const T*)coarse->B : nullptr, (T)alpha};
-  const mhd_level cw = whole_grid(coarse);
-  Work wc = make_work(&cw, 0, 0);
-  Work wf = make_work(fine, 0, 0);
-  if (fine->groups && fine->n_groups > 0) {
-    // items: the coarse cells over each fine group's halo box (fine cells
-    // [o - halo, o + edge + halo + 1) need coarse [o/2 - lo, o/2 + edge/2 + hi))
-    wf.occ = c->occ;
-    wf.halo = halo;
-    const int lo = (halo + 1) / 2, hi = (halo + 2) / 2;
-    wc.groups = fine->groups;
-    wc.oshift = 1;
-    wc.edge = fine->group_edge / 2;
-    wc.halo = lo;
-    wc.box = fine->group_edge / 2 + lo + hi;
-    wc.items = (long long)fine->n_groups * wc.box * wc.box * wc.box;
-    wc.n_dev = fine->n_groups_dev;
-    wc.gnx = wc.gny = wc.gnz = 0;
-    k_prolong_ghosts<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, Uc, Bc, (T*)fine->U, (T*)fine->B,
-                                                               (T)c->cfg.gamma);
-  } else {
-    k_prolong_all<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, Uc, Bc, (T*)fine->U, (T*)fine->B,
-                                                            (T)c->cfg.gamma);
-  }
-}
-
-template <typename T>
-void launch_restrict(mhd_ctx_s* c, const mhd_level* fine, const mhd_level* coarse) {
-  Work wf = make_work(fine, 0, 0);
-  wf.occ = c->occ;
-  const mhd_level cw = whole_grid(coarse);
-  Work wc = make_work(&cw, 0, 0);
-  if (fine->groups && fine->n_groups > 0) {
-    // coarse footprint of each fine group: the fine origins halved, edge/2
-    wc.groups = fine->groups;
-    wc.edge = fine->group_edge / 2;
-    wc.halo = 0;
-    wc.box = fine->group_edge / 2;
-    wc.items = (long long)fine->n_groups * wc.box * wc.box * wc.box;
-    wc.n_dev = fine->n_groups_dev;
-    wc.gnx = wc.gny = wc.gnz = 0;
-    wc.oshift = 1;
-  }
-  k_restrict<T><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, (const T*)fine->U, (T*)coarse->U, (const T*)fine->B,
-                                                         (T*)coarse->B);
-}
-
-// the stage scratch of context c as left by its last update of level lv
-LevelScratch level_scratch(mhd_ctx_s* c, const mhd_level* lv) {
-  const int ghost = c->cfg.scheme == MHD_CTU ? 4 : 3;
-  LevelScratch v;
-  v.F = c->cfg.scheme == MHD_CTU ? c->F2 : c->F;
-  v.E = c->E;
-  v.NS = scratch_cells(lv, ghost);
-  v.sb = list_mode(lv) ? (int)scratch_box(lv, ghost) : 0;
-  v.ghost = ghost;
-  v.occ = c->occ;
-  v.groups = lv->groups;
-  v.edge = lv->group_edge;
-  v.gnx = lv->nx / lv->group_edge;
-  v.gny = lv->ny / lv->group_edge;
-  v.gnz = lv->nz / lv->group_edge;
-  v.nx = lv->nx; v.ny = lv->ny; v.nz = lv->nz;
-  return v;
-}
-
-template <typename T>
-void launch_correct(mhd_ctx_s* cc, const mhd_level* coarse, mhd_ctx_s* cf, const mhd_level* fine, const double* dt,
-                    int fine_registers) {
-  Work wc = make_work(coarse, 0, 0);
-  wc.occ = cc->occ;
-  Work wf = make_work(fine, 0, 0);
-  wf.occ = cf->occ;
-  const LevelScratch sc = level_scratch(cc, coarse);
-  LevelScratch sf = level_scratch(cf, fine);
-  if (fine_registers) {
-    sf.F = cf->RF;
-    sf.E = cf->RE;
-  }
-  const T inv_dx = (T)(1.0 / coarse->dx);
-  k_correct_u<T><<<sblocks(wc), kBlock, 0, cc->stream>>>(wc, wf, sc, sf, (T*)coarse->U, dt, inv_dx);
-  k_correct_b<T><<<sblocks(wc), kBlock, 0, cc->stream>>>(wc, wf, sc, sf, (T*)coarse->B, dt, inv_dx);
-  // the coarse fluxes and EMFs on the refined region become the fine means
-  const mhd_level cw = whole_grid(coarse);
-  Work wcf = make_work(&cw, 0, 0);
-  if (list_mode(fine)) {
-    wcf.groups = fine->groups;
-    wcf.edge = fine->group_edge / 2;
-    wcf.halo = 0;
-    wcf.box = fine->group_edge / 2;
-    wcf.items = (long long)fine->n_groups * wcf.box * wcf.box * wcf.box;
-    wcf.n_dev = fine->n_groups_dev;
-    wcf.gnx = wcf.gny = wcf.gnz = 0;
-    wcf.oshift = 1;
-  }
-  k_correct_registers<T><<<sblocks(wcf), kBlock, 0, cc->stream>>>(wcf, wf, sc, sf);
-}
-}  // namespace
+#include "mhd_amr_api.inc"
 
 extern "C" {
-
-int mhd_prolong_time(mhd_ctx c, const mhd_level* coarse_old, const mhd_level* coarse, double alpha,
-                     const mhd_level* fine, int halo) {
-  if (!c || !coarse || !fine || halo < 0 || halo > 8) return MHD_ERR_INVALID_ARG;
-  if (!(alpha >= 0.0 && alpha <= 1.0)) return MHD_ERR_INVALID_ARG;
-  int rc = check_pair(c, coarse, fine);
-  if (rc) return rc;
-  if (coarse_old) {
-    rc = check_level(c, coarse_old);
-    if (rc) return rc;
-    if (coarse_old->nx != coarse->nx || coarse_old->ny != coarse->ny || coarse_old->nz != coarse->nz ||
-        coarse_old->dx != coarse->dx)
-      return MHD_ERR_INVALID_ARG;
-  }
-  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
-  rc = build_occupancy(c, fine);
-  if (rc) return rc;
-  g_max_blocks = c->max_blocks;
-  if (c->cfg.prec == MHD_F64) launch_prolong<double>(c, coarse_old, coarse, alpha, fine, halo);
-  else launch_prolong<float>(c, coarse_old, coarse, alpha, fine, halo);
-  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
-}
-
-int mhd_prolong(mhd_ctx c, const mhd_level* coarse, const mhd_level* fine, int halo) {
-  return mhd_prolong_time(c, nullptr, coarse, 1.0, fine, halo);
-}
-
-int mhd_accumulate_registers(mhd_ctx c, const mhd_level* lv, double weight, int reset) {
-  if (!c) return MHD_ERR_INVALID_ARG;
-  int rc = check_level(c, lv);
-  if (rc) return rc;
-  if (!std::isfinite(weight)) return MHD_ERR_INVALID_ARG;
-  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
-  const int ghost = c->cfg.scheme == MHD_CTU ? 4 : 3;
-  const long long ns = scratch_cells(lv, ghost);
-  if (c->cap_cells < ns) return MHD_ERR_INVALID_ARG;     // no update of this level has run
-  if (c->cap_reg < ns) {
-    if (!reset) return MHD_ERR_INVALID_ARG;             // nothing accumulated to add to
-    hipFree(c->RF);
-    hipFree(c->RE);
-    c->RF = c->RE = nullptr;
-    c->cap_reg = 0;
-    if (hipMalloc(&c->RF, 21 * ns * c->elem) != hipSuccess || hipMalloc(&c->RE, 3 * ns * c->elem) != hipSuccess) {
-      hipFree(c->RF);
-      hipFree(c->RE);
-      c->RF = c->RE = nullptr;
-      return MHD_ERR_OUT_OF_MEMORY;
-    }
-    c->cap_reg = ns;
-  }
-  const LevelScratch v = level_scratch(c, lv);
-  const long long m = lv->group_edge + 1;
-  const long long items = v.sb ? (long long)lv->n_groups * m * m * m : ns;
-  if (items == 0) return MHD_OK;
-  long long nb = (items + kBlock - 1) / kBlock;
-  const long long cap = 16LL * c->num_cu;
-  if (nb > cap) nb = cap;
-  if (c->cfg.prec == MHD_F64)
-    k_accumulate_registers<double><<<(unsigned)nb, kBlock, 0, c->stream>>>(
-        (const double*)v.F, (const double*)v.E, (double*)c->RF, (double*)c->RE, ns, v.sb, ghost, lv->group_edge,
-        items, weight, reset);
-  else
-    k_accumulate_registers<float><<<(unsigned)nb, kBlock, 0, c->stream>>>(
-        (const float*)v.F, (const float*)v.E, (float*)c->RF, (float*)c->RE, ns, v.sb, ghost, lv->group_edge,
-        items, (float)weight, reset);
-  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
-}
-
-int mhd_regrid_flag(mhd_ctx c, const mhd_level* coarse, double threshold, int buffer, int fine_edge,
-                    int* groups_out, int capacity, int* count_dev, int* wanted_dev) {
-  if (!c || !groups_out || !count_dev || !wanted_dev || capacity < 0) return MHD_ERR_INVALID_ARG;
-  int rc = check_level(c, coarse);
-  if (rc) return rc;
-  if (!(threshold >= 0.0 && std::isfinite(threshold))) return MHD_ERR_INVALID_ARG;
-  if (fine_edge < 4 || fine_edge % 2) return MHD_ERR_INVALID_ARG;
-  const int e = fine_edge / 2;
-  if (buffer < 0 || buffer > e) return MHD_ERR_INVALID_ARG;
-  if (coarse->nx % e || coarse->ny % e || coarse->nz % e) return MHD_ERR_INVALID_ARG;
-  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
-  const int gnx = coarse->nx / e, gny = coarse->ny / e, gnz = coarse->nz / e;
-  const long long ng = (long long)gnx * gny * gnz;
-  if (ng > c->cap_rflags) {
-    hipFree(c->rflags);
-    c->rflags = nullptr;
-    c->cap_rflags = 0;
-    if (hipMalloc(&c->rflags, ng * sizeof(int)) != hipSuccess) return MHD_ERR_OUT_OF_MEMORY;
-    c->cap_rflags = ng;
-  }
-  // nesting: candidates must lie in listed coarse groups
-  const int* cocc = nullptr;
-  if (list_mode(coarse)) {
-    if (coarse->group_edge % e) return MHD_ERR_INVALID_ARG;
-    rc = build_occupancy(c, coarse);
-    if (rc) return rc;
-    cocc = c->occ;
-  }
-  k_fill_int<<<(unsigned)((ng + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(c->rflags, ng, 0);
-  const mhd_level cw = whole_grid(coarse);
-  const Work w = make_work(&cw, 0, 0);
-  g_max_blocks = c->max_blocks;
-  if (c->cfg.prec == MHD_F64)
-    k_refine_mark<double><<<sblocks(w), kBlock, 0, c->stream>>>(w, (const double*)coarse->B, threshold, e, buffer,
-                                                                 gnx, gny, gnz, c->rflags);
-  else
-    k_refine_mark<float><<<sblocks(w), kBlock, 0, c->stream>>>(w, (const float*)coarse->B, (float)threshold, e,
-                                                                buffer, gnx, gny, gnz, c->rflags);
-  k_compact_groups<<<1, 1024, 0, c->stream>>>(c->rflags, gnx, gny, gnz, e, fine_edge, cocc,
-                                              cocc ? coarse->nx / coarse->group_edge : 0,
-                                              cocc ? coarse->ny / coarse->group_edge : 0,
-                                              cocc ? coarse->group_edge : 1, groups_out, capacity, count_dev,
-                                              wanted_dev);
-  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
-}
-
-int mhd_prolong_new_groups(mhd_ctx c, const mhd_level* coarse, const mhd_level* fine_new,
-                           const mhd_level* fine_old) {
-  if (!c || !coarse || !fine_new) return MHD_ERR_INVALID_ARG;
-  int rc = check_pair(c, coarse, fine_new);
-  if (rc) return rc;
-  if (!list_mode(fine_new)) return MHD_ERR_INVALID_ARG;
-  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
-  const int* occ_old = nullptr;
-  if (fine_old && list_mode(fine_old)) {
-    rc = check_pair(c, coarse, fine_old);
-    if (rc) return rc;
-    if (fine_old->U != fine_new->U || fine_old->B != fine_new->B || fine_old->group_edge != fine_new->group_edge)
-      return MHD_ERR_INVALID_ARG;
-    rc = build_occupancy_into(c, fine_old, &c->occ_old, &c->cap_occ_old);
-    if (rc) return rc;
-    occ_old = c->occ_old;
-  }
-  g_max_blocks = c->max_blocks;
-  const mhd_level cw = whole_grid(coarse);
-  Work wc = make_work(&cw, 0, 0);
-  wc.groups = fine_new->groups;
-  wc.edge = fine_new->group_edge / 2;
-  wc.halo = 0;
-  wc.box = fine_new->group_edge / 2;
-  wc.items = (long long)fine_new->n_groups * wc.box * wc.box * wc.box;
-  wc.n_dev = fine_new->n_groups_dev;
-  wc.gnx = wc.gny = wc.gnz = 0;
-  wc.oshift = 1;
-  Work wf = make_work(fine_new, 0, 0);
-  if (c->cfg.prec == MHD_F64) {
-    const Coarse<double> Uc{(const double*)coarse->U, nullptr, 0.0}, Bc{(const double*)coarse->B, nullptr, 0.0};
-    k_prolong_created<double><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, Uc, Bc, (double*)fine_new->U,
-                                                                     (double*)fine_new->B, occ_old, c->cfg.gamma);
-  } else {
-    const Coarse<float> Uc{(const float*)coarse->U, nullptr, 0.0f}, Bc{(const float*)coarse->B, nullptr, 0.0f};
-    k_prolong_created<float><<<sblocks(wc), kBlock, 0, c->stream>>>(wc, wf, Uc, Bc, (float*)fine_new->U,
-                                                                    (float*)fine_new->B, occ_old,
-                                                                    (float)c->cfg.gamma);
-  }
-  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
-}
-
-int mhd_dt_subdivide(mhd_ctx c, const double* dt_coarse, int parts, double* dt_fine) {
-  if (!c || !dt_coarse || !dt_fine || parts < 1) return MHD_ERR_INVALID_ARG;
-  k_subdivide_dt<<<1, 1, 0, c->stream>>>(dt_coarse, parts, dt_fine);
-  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
-}
-
-int mhd_restrict(mhd_ctx c, const mhd_level* fine, const mhd_level* coarse) {
-  if (!c || !coarse || !fine) return MHD_ERR_INVALID_ARG;
-  int rc = check_pair(c, coarse, fine);
-  if (rc) return rc;
-  if (c->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
-  rc = build_occupancy(c, fine);
-  if (rc) return rc;
-  g_max_blocks = c->max_blocks;
-  if (c->cfg.prec == MHD_F64) launch_restrict<double>(c, fine, coarse);
-  else launch_restrict<float>(c, fine, coarse);
-  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
-}
-
-int mhd_correct(mhd_ctx cc, const mhd_level* coarse, mhd_ctx cf, const mhd_level* fine, const double* dt_dev,
-                int fine_registers) {
-  if (!cc || !cf || !coarse || !fine || !dt_dev) return MHD_ERR_INVALID_ARG;
-  int rc = check_pair(cc, coarse, fine);
-  if (rc) return rc;
-  rc = check_level(cf, fine);
-  if (rc) return rc;
-  if (cc->cfg.prec != cf->cfg.prec || cc->cfg.scheme != cf->cfg.scheme || cc->stream != cf->stream)
-    return MHD_ERR_INVALID_ARG;
-  if (cc->cfg.prec == MHD_F32_MIXED) return MHD_ERR_UNSUPPORTED;
-  const int ghost = cc->cfg.scheme == MHD_CTU ? 4 : 3;
-  // both contexts must hold the scratch of an update of these levels
-  if (cc->cap_cells < scratch_cells(coarse, ghost) || cf->cap_cells < scratch_cells(fine, ghost))
-    return MHD_ERR_INVALID_ARG;
-  if (fine_registers && (!cf->RF || cf->cap_reg < scratch_cells(fine, ghost))) return MHD_ERR_INVALID_ARG;
-  rc = build_occupancy(cc, coarse);
-  if (rc) return rc;
-  rc = build_occupancy(cf, fine);
-  if (rc) return rc;
-  if (list_mode(coarse) && !cc->occ) return MHD_ERR_INVALID_ARG;
-  if (list_mode(fine) && !cf->occ) return MHD_ERR_INVALID_ARG;
-  g_max_blocks = cc->max_blocks;
-  if (cc->cfg.prec == MHD_F64) launch_correct<double>(cc, coarse, cf, fine, dt_dev, fine_registers);
-  else launch_correct<float>(cc, coarse, cf, fine, dt_dev, fine_registers);
-  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
-}
 
 int mhd_divB(mhd_ctx c, const mhd_level* lv, double* max_abs, double* l1) {
   if (!c) return MHD_ERR_INVALID_ARG;
