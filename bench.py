@@ -474,7 +474,7 @@ def main():
                          "over grid sizes 32^3 .. 512^3 (FP32) and .. 384^3 (FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
