@@ -98,6 +98,16 @@ typedef struct {
  * integrator and reconstruction (stencil count: 3 for PLM, 4 for PPM). */
 int mhd_required_ghost(int scheme, int recon);
 
+/* Device bytes the context's stage scratch takes to update lv (in
+ * *bytes): W, Bh, F, E (35 words per scratch cell; CTU adds QL, QR, F2: 98;
+ * the learned flux adds Qc: 112) times the scratch cells (the level's cells,
+ * or (groups + 2) boxes of (edge + 2 ghost)^3 cells for a group list), plus
+ * the group occupancy map.  The context allocates this on the first update
+ * of a level that needs more than it holds; the time-mean registers of
+ * mhd_accumulate_registers (24 words per scratch cell) come on top.  No
+ * HIP call. */
+int mhd_workspace_bytes(mhd_ctx ctx, const mhd_level* lv, size_t* bytes);
+
 /* Validate cfg and create a context bound to hip_stream (a hipStream_t, or
  * NULL for the default stream) on the current device. */
 int mhd_init(const mhd_config* cfg, void* hip_stream, mhd_ctx* out);

@@ -451,6 +451,22 @@ int mhd_required_ghost(int scheme, int recon) {
   return MHD_ERR_INVALID_ARG;
 }
 
+int mhd_workspace_bytes(mhd_ctx c, const mhd_level* lv, size_t* bytes) {
+  if (!c || !bytes) return MHD_ERR_INVALID_ARG;
+  const int rc = check_level(c, lv);
+  if (rc) return rc;
+  const int ghost = c->cfg.scheme == MHD_CTU ? 4 : 3;
+  long long words = 35;
+  if (c->cfg.scheme == MHD_CTU) words += 63;
+  if (c->cfg.riemann == MHD_MLP) words += 14;
+  long long total = words * scratch_cells(lv, ghost) * (long long)c->elem;
+  if (list_mode(lv))
+    total += (long long)(lv->nx / lv->group_edge) * (lv->ny / lv->group_edge) * (lv->nz / lv->group_edge) *
+             (long long)sizeof(int);
+  *bytes = (size_t)total;
+  return MHD_OK;
+}
+
 int mhd_init(const mhd_config* cfg, void* hip_stream, mhd_ctx* out) {
   if (!out) return MHD_ERR_INVALID_ARG;
   *out = nullptr;

@@ -58,7 +58,7 @@ EXPORTS = ["mhd_abi_version", "mhd_strerror", "mhd_required_ghost", "mhd_init", 
            "mhd_mlp_train_step", "mhd_mlp_prepare", "mhd_mlp_face_flux", "mhd_set_capture", "mhd_correct",
            "mhd_advance_graph", "mhd_set_launch", "mhd_cfl_dt_min", "mhd_prolong", "mhd_restrict",
            "mhd_prolong_time", "mhd_accumulate_registers", "mhd_dt_subdivide", "mhd_regrid_flag",
-           "mhd_prolong_new_groups"]
+           "mhd_prolong_new_groups", "mhd_workspace_bytes"]
 
 
 def load(path: str = LIB_PATH):
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.mhd_prolong_time.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc), D,
                                      ctypes.POINTER(LevelDesc), I]
     lib.mhd_accumulate_registers.argtypes = [P, ctypes.POINTER(LevelDesc), D, I]
+    lib.mhd_workspace_bytes.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(ctypes.c_size_t)]
     lib.mhd_regrid_flag.argtypes = [P, ctypes.POINTER(LevelDesc), D, I, I, P, I, P, P]
     lib.mhd_prolong_new_groups.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc),
                                            ctypes.POINTER(LevelDesc)]
@@ -278,6 +279,13 @@ class Solver:
         do = None if coarse_old is None else ctypes.byref(coarse_old.desc())
         _check(self.lib.mhd_prolong_time(self.h, do, ctypes.byref(dc), float(alpha), ctypes.byref(df), int(halo)),
                "mhd_prolong_time")
+
+    def workspace_bytes(self, lv: Level) -> int:
+        """Device bytes of stage scratch this context needs to update lv."""
+        d = lv.desc()
+        v = ctypes.c_size_t()
+        _check(self.lib.mhd_workspace_bytes(self.h, ctypes.byref(d), ctypes.byref(v)), "mhd_workspace_bytes")
+        return v.value
 
     def regrid_flag(self, coarse: Level, threshold: float, buffer: int, fine_edge: int, groups_out: torch.Tensor,
                     count: torch.Tensor, wanted: torch.Tensor):

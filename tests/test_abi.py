@@ -122,6 +122,17 @@ def test_null_context_calls(mhd):
     assert lib.mhd_divB(None, ctypes.byref(lv), ctypes.byref(d), ctypes.byref(d)) == -1
     assert lib.mhd_sync(None) == -1
     assert lib.mhd_finalize(None) == -1
+    sz = ctypes.c_size_t()
+    i = ctypes.c_int()
+    assert lib.mhd_workspace_bytes(None, ctypes.byref(lv), ctypes.byref(sz)) == -1
+    assert lib.mhd_prolong(None, ctypes.byref(lv), ctypes.byref(lv), 4) == -1
+    assert lib.mhd_prolong_time(None, None, ctypes.byref(lv), 0.5, ctypes.byref(lv), 4) == -1
+    assert lib.mhd_restrict(None, ctypes.byref(lv), ctypes.byref(lv)) == -1
+    assert lib.mhd_correct(None, ctypes.byref(lv), None, ctypes.byref(lv), None, 0) == -1
+    assert lib.mhd_accumulate_registers(None, ctypes.byref(lv), 0.5, 1) == -1
+    assert lib.mhd_dt_subdivide(None, None, 2, None) == -1
+    assert lib.mhd_regrid_flag(None, ctypes.byref(lv), 1.0, 1, 16, None, 4, ctypes.byref(i), ctypes.byref(i)) == -1
+    assert lib.mhd_prolong_new_groups(None, ctypes.byref(lv), ctypes.byref(lv), None) == -1
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

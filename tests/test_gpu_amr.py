@@ -310,3 +310,19 @@ def test_accumulate_registers_needs_a_reset_first():
     s.accumulate_registers(a, 0.5, reset=True)
     s.accumulate_registers(a, 0.5, reset=False)
     torch.cuda.synchronize()
+
+
+def test_workspace_bytes_matches_the_scratch_layout():
+    p = inputs.abc_problem(32, 0.1, seed=1)
+    U, B = oracle.initial_state(p)
+    for (sch, rec, rie, prec, words, el) in (("ctu", "ppm", "hlld", "f32", 98, 4), ("vl", "plm", "roe", "f64", 35, 8)):
+        s = Solver(sch, rec, rie, prec)
+        dtype = torch.float32 if prec == "f32" else torch.float64
+        lv = lvl(U, B, p["dx"], dtype)
+        assert s.workspace_bytes(lv) == words * 32 ** 3 * el
+        g = torch.tensor([[0, 0, 0], [16, 16, 16]], dtype=torch.int32, device="cuda")
+        lg = lvl(U, B, p["dx"], dtype, groups=g)
+        ghost = 4 if sch == "ctu" else 3
+        box = 16 + 2 * ghost
+        assert s.workspace_bytes(lg) == words * (2 + 2) * box ** 3 * el + 8 * 4
+        s.close()
