@@ -234,8 +234,10 @@ int mhd_prolong_time(mhd_ctx ctx, const mhd_level* coarse_old, const mhd_level* 
 
 /* Time-averaged coarse-fine registers of a sub-cycled level: R = weight S
  * (reset != 0) or R + weight S, with S the final fluxes and EMFs of ctx's
- * last update of lv, over the faces and edges of each listed group (every
- * face and edge without a list).  After the sub-steps of one parent step
+ * last update of lv, on the boundary faces and edges of each listed group
+ * (every face and edge without a list): the only ones a correction reads,
+ * given that the groups of the finer level lie inside listed groups of
+ * this one.  After the sub-steps of one parent step
  * (weight 1/parts each, the first with reset), mhd_correct with
  * fine_registers = 1 corrects the parent with the time mean.  The registers
  * live in ctx (21 + 3 arrays of its scratch size, allocated on the first

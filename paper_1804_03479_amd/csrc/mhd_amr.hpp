@@ -801,8 +801,11 @@ __global__ void __launch_bounds__(kBlock) k_prolong_created(Work wc, Work wf, Co
 
 // Time-averaged registers of a sub-cycled level: R = (reset ? 0 : R) + w S
 // over the final fluxes and EMFs S of the level's last update.  Whole grid
-// (sb = 0): every slot; group list: the slots of each group's cells and of
-// its upper boundary faces and edges (box positions ghost .. ghost + edge).
+// (sb = 0): every slot; group list: the slots on each group's boundary shell
+// (box positions ghost .. ghost + edge with one coordinate at either end).
+// A correction reads registers only on the boundary of the refined region,
+// and a group of a finer level never straddles a group boundary of this one
+// (groups nest in their parent's groups), so interior slots are never read.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_accumulate_registers(const T* __restrict__ F, const T* __restrict__ E,
                                                                  T* __restrict__ RF, T* __restrict__ RE, long long NS,
@@ -815,6 +818,7 @@ __global__ void __launch_bounds__(kBlock) k_accumulate_registers(const T* __rest
       const long long m = edge + 1, per = m * m * m;
       const long long g = t / per, r = t - g * per;
       const long long a = r % m, b = (r / m) % m, c = r / (m * m);
+      if (a != 0 && a != edge && b != 0 && b != edge && c != 0 && c != edge) continue;
       q = (g + 1) * sb * sb * sb + ((c + ghost) * sb + (b + ghost)) * sb + (a + ghost);
     }
 #pragma unroll
