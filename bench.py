@@ -528,6 +528,24 @@ def main():
         cpu = {"value": cells * args.cpu_steps / t_cpu, "unit": "cell-updates/s", "cores": oracle.get_threads(),
                "kind": "oracle",
                "sample": f"{n}^3 ABC box, {wl['label']} FP64, {args.cpu_steps} steps incl. CFL"}
+        # the same oracle on one core (one step incl. CFL) and the host CPU
+        from paper_1804_03479_amd import inputs
+        p = inputs.abc_problem(n, wl["noise"], seed=args.seed)
+        U, B = oracle.initial_state(p)
+        threads = oracle.get_threads()
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        dt = oracle.cfl_dt(U, B, p["dx"])
+        oracle.step(U, B, dt, p["dx"], scheme=oracle.CTU if wl["scheme"] == "ctu" else oracle.VL,
+                    recon=oracle.PPM if wl["recon"] == "ppm" else oracle.PLM,
+                    riemann={"roe": oracle.ROE, "hlle": oracle.HLLE, "hlld": oracle.HLLD}[wl["riemann"]])
+        cpu["value_1_core"] = cells / (time.perf_counter() - t0)
+        oracle.set_threads(threads)
+        try:
+            cpu["cpu_model"] = next(line.split(":", 1)[1].strip() for line in open("/proc/cpuinfo")
+                                    if line.startswith("model name"))
+        except (OSError, StopIteration):
+            cpu["cpu_model"] = None
 
     for key, r in results.items():
         wl = WORKLOADS[key]
