@@ -114,13 +114,14 @@ class Hierarchy:
                     fine.n_groups_dev = torch.tensor([len(g)], dtype=torch.int32, device="cuda")
                 fine.group_edge = edge
                 self.levels.append(fine)
-            # per-level steps (all equal without sub-cycling); dt is the root's
             self.capacity = capacity
             self.edge = edge
             if capacity is not None:
+                # regridding: the new list, its count, and the number each level wanted
                 self._new = torch.zeros((capacity, 3), dtype=torch.int32, device="cuda")
                 self._count = torch.zeros(1, dtype=torch.int32, device="cuda")
                 self._wanted = torch.zeros(len(self.levels), dtype=torch.int32, device="cuda")
+            # per-level steps (all equal without sub-cycling); dt is the root's
             self.dts = torch.zeros(len(self.levels), dtype=torch.float64, device="cuda")
             self.dt = self.dts[:1]
             # a level's state at the start of its step, for its children's ghosts
