@@ -158,9 +158,13 @@ def train_surrogate(n_capture: int, seed: int, n_samples: int, epochs: int):
     from paper_1804_03479_amd import surrogate
     from paper_1804_03479_amd.mhd import MlpOps, Solver
     t0 = _t.perf_counter()
-    stride = max(1, (6 * n_capture ** 3 * 4) // (2 * n_samples))
-    samples = surrogate.capture(n=n_capture, steps=4, noise=0.1, seed=seed + 1, stride=stride,
-                                cap=2 * n_samples)
+    # interfaces of 8 steps spread over a 500-step run (early, noisy flow and
+    # the smoother flow of later times), another noise realisation than the
+    # measured runs
+    at = [0, 1, 100, 101, 250, 251, 450, 451]
+    stride = max(1, (6 * n_capture ** 3 * len(at)) // (2 * n_samples))
+    samples = surrogate.capture(n=n_capture, steps=452, noise=0.1, seed=seed + 1, stride=stride,
+                                cap=2 * n_samples, capture_at=at)
     s = Solver("ctu", "ppm", "mlp", "f32")
     ops = MlpOps(s)
     X, T, info = surrogate.training_set(ops, samples, n_samples, seed=seed)

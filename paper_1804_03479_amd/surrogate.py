@@ -5,7 +5,8 @@ Adam) runs in libmhd's kernels; this module only chooses samples (seeded
 index selection) and the learning-rate schedule.
 
 Recipe: capture (wl, wr, bn, HLLD flux) from CTU+PPM+HLLD runs of the ABC
-box, drop samples whose normalised jump is below 1e-4 (their targets are
+box (at several times of a run, so that the decaying flow of late times is
+represented as well as the noisy start), drop samples whose normalised jump is below 1e-4 (their targets are
 float round-off), classify the rest with the fallback test (strong jump =
 "shock"), draw a seeded 3:1 smooth:shock mix (with replacement when a class
 is short), split 90/10 by a seeded permutation, and train with MSE + Adam
@@ -38,8 +39,10 @@ def init_params(nparam: int, seed: int = 0) -> torch.Tensor:
 
 
 def capture(n: int = 64, steps: int = 10, noise: float = 0.1, seed: int = 0, stride: int = 1,
-            cap: int = 1_000_000, prec: str = "f32") -> torch.Tensor:
-    """Run CTU+PPM+HLLD on an n^3 ABC box with capture on; returns samples (m, 22)."""
+            cap: int = 1_000_000, prec: str = "f32", capture_at=None) -> torch.Tensor:
+    """Run CTU+PPM+HLLD on an n^3 ABC box for `steps` steps, capturing the
+    interfaces of the steps listed in capture_at (default: all of them);
+    returns samples (m, 22)."""
     s = Solver("ctu", "ppm", "hlld", prec)
     ops = MlpOps(s)
     p = inputs.abc_problem(n, noise, seed=seed)
@@ -48,8 +51,15 @@ def capture(n: int = 64, steps: int = 10, noise: float = 0.1, seed: int = 0, str
     lv = s.level_from_primitives(W5, B, p["dx"])
     buf = torch.empty((cap, 22), dtype=torch.float32, device="cuda")
     count = torch.zeros(1, dtype=torch.int64, device="cuda")
-    ops.set_capture(buf, count, stride)
-    for _ in range(steps):
+    when = set(range(steps)) if capture_at is None else set(capture_at)
+    on = False
+    for k in range(steps):
+        if (k in when) != on:
+            on = k in when
+            if on:
+                ops.set_capture(buf, count, stride)
+            else:
+                ops.set_capture(None)
         s.advance(lv)
     ops.set_capture(None)
     torch.cuda.synchronize()
