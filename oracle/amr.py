@@ -19,13 +19,19 @@ fine faces (the cell's mid-planes) take its values at their centres:
 Bx(0, y, z) = a0 + ay y + az z with a0 = (Bx- + Bx+)/2 - axx/4 and ay, az the
 mean transverse slopes of the two x-faces.  Every fine cell then has the
 divergence of its parent.
-Cell data (conservative): density and momentum are injected; the fine
-energy is e_parent + (|b_child|^2 - <|b|^2>)/2 with b the fine cell-centred
-field and <.> the mean over the eight children, so the children's energies
-average to the parent's and their pressure is the parent's minus
-(gamma - 1)(<|b|^2> - |b_parent|^2)/2.  Where that pressure would not be
-positive, the parent's pressure is kept instead (e = p_parent / (gamma - 1)
-+ parent's kinetic energy + |b_child|^2 / 2, not conservative).
+Cell data (conservative interpolation): each conserved component takes a
+minmod-limited linear profile in the coarse cell, u_child = u + (s_x sx +
+s_y sy + s_z sz)/4 with s the minmod of the two one-sided differences along
+an axis and sx, sy, sz = -1 / +1 for the lower / upper child, so the eight
+children average to the parent; the energy also moves the magnetic energy
+to where the fine field has it, + (|b_child|^2 - <|b|^2>)/2 (b the fine
+cell-centred field, <.> the mean over the children), which keeps the mean.
+Where a child would get a non-positive density or pressure, the parent's
+children take the parent's density and momentum instead, with energies
+e_parent + (|b_child|^2 - <|b|^2>)/2 (a common pressure) or, where that
+pressure would not be positive either, the parent's pressure (e = p_parent
+/ (gamma - 1) + parent's kinetic energy + |b_child|^2 / 2, not
+conservative).
 Restriction: a coarse cell takes the mean of its eight children.
 """
 from __future__ import annotations
@@ -39,6 +45,55 @@ def mc(a, b):
         return 0.0
     m = min(2.0 * abs(a), 2.0 * abs(b), 0.5 * abs(a + b))
     return m if a > 0 else -m
+
+
+def minmod(a, b):
+    """Minmod of two one-sided differences."""
+    if a * b <= 0.0:
+        return 0.0
+    return a if abs(a) < abs(b) else b
+
+
+def children_cells(Uc, Bc, i, j, k, b2, gamma):
+    """Conserved data of the eight children (q = x + 2 y + 4 z) of coarse
+    cell (i, j, k) given the children's |b|^2 (list of 8), as described in the
+    module docstring."""
+    nz, ny, nx = Uc.shape[1:]
+    u0 = Uc[:, k, j, i]
+    sl = np.zeros((5, 3))
+    for m in range(5):
+        for d, (di, dj, dk) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+            up = Uc[m, (k + dk) % nz, (j + dj) % ny, (i + di) % nx]
+            dn = Uc[m, (k - dk) % nz, (j - dj) % ny, (i - di) % nx]
+            sl[m, d] = minmod(u0[m] - dn, up - u0[m])
+    mean_b2 = sum(b2) / 8.0
+    kids, ok = [], True
+    for q in range(8):
+        sx, sy, sz = [1.0 if (q >> d) & 1 else -1.0 for d in range(3)]
+        u = np.array([u0[m] + 0.25 * (sl[m, 0] * sx + sl[m, 1] * sy + sl[m, 2] * sz) for m in range(5)])
+        u[4] = u[4] + 0.5 * (b2[q] - mean_b2)
+        if not u[0] > 0.0:
+            ok = False
+        else:
+            p = (gamma - 1) * (u[4] - 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0] - 0.5 * b2[q])
+            ok = ok and p > 0.0
+        kids.append(u)
+    if ok:
+        return kids
+    bc = [0.5 * (Bc[0, k, j, i] + Bc[0, k, j, (i + 1) % nx]),
+          0.5 * (Bc[1, k, j, i] + Bc[1, k, (j + 1) % ny, i]),
+          0.5 * (Bc[2, k, j, i] + Bc[2, (k + 1) % nz, j, i])]
+    d = u0[0]
+    m = u0[1:4]
+    ek = 0.5 * float(m @ m) / d
+    b2c = sum(x * x for x in bc)
+    p = (gamma - 1) * (u0[4] - ek - 0.5 * b2c)
+    conservative = p - (gamma - 1) * 0.5 * (mean_b2 - b2c) > 0.0
+    kids = []
+    for q in range(8):
+        e = u0[4] + 0.5 * (b2[q] - mean_b2) if conservative else p / (gamma - 1) + ek + 0.5 * b2[q]
+        kids.append(np.array([d, m[0], m[1], m[2], e]))
+    return kids
 
 
 def face_slopes(Bc):
@@ -117,14 +172,6 @@ def prolong(Uc, Bc, gamma=5.0 / 3.0):
     for k in range(nzc):
         for j in range(nyc):
             for i in range(nxc):
-                bc = [0.5 * (Bc[0, k, j, i] + Bc[0, k, j, (i + 1) % nxc]),
-                      0.5 * (Bc[1, k, j, i] + Bc[1, k, (j + 1) % nyc, i]),
-                      0.5 * (Bc[2, k, j, i] + Bc[2, (k + 1) % nzc, j, i])]
-                d = Uc[0, k, j, i]
-                m = Uc[1:4, k, j, i]
-                ek = 0.5 * float(m @ m) / d
-                b2c = sum(x * x for x in bc)
-                p = (gamma - 1) * (Uc[4, k, j, i] - ek - 0.5 * b2c)
                 kids = [(2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2)) for q in range(8)]
                 b2 = []
                 for (I, J, K) in kids:
@@ -132,15 +179,8 @@ def prolong(Uc, Bc, gamma=5.0 / 3.0):
                           0.5 * (Bf[1, K, J, I] + Bf[1, K, (J + 1) % ny, I]),
                           0.5 * (Bf[2, K, J, I] + Bf[2, (K + 1) % nz, J, I])]
                     b2.append(sum(x * x for x in bf))
-                mean_b2 = sum(b2) / 8.0
-                conservative = p - (gamma - 1) * 0.5 * (mean_b2 - b2c) > 0.0
-                for (I, J, K), bb in zip(kids, b2):
-                    Uf[0, K, J, I] = d
-                    Uf[1:4, K, J, I] = m
-                    if conservative:
-                        Uf[4, K, J, I] = Uc[4, k, j, i] + 0.5 * (bb - mean_b2)
-                    else:
-                        Uf[4, K, J, I] = p / (gamma - 1) + ek + 0.5 * bb
+                for (I, J, K), u in zip(kids, children_cells(Uc, Bc, i, j, k, b2, gamma)):
+                    Uf[:, K, J, I] = u
     return Uf, Bf
 
 
@@ -320,23 +360,10 @@ def prolong_new_groups(Uc, Bc, Uf, Bf, new_groups, old_groups, edge=16, gamma=5.
                             t = pos[b] + 2 * pos[cc]
                             bcell.append(0.5 * (fine[a, pos[a], t] + fine[a, pos[a] + 1, t]))
                         kids.append((pos, sum(w * w for w in bcell)))
-                    mean_b2 = sum(k2 for _, k2 in kids) / 8.0
-                    i, j, k = ci % nc[0], cj % nc[1], ck % nc[2]
-                    bpar = [0.5 * (Bc[0, k, j, i] + Bc[0, k, j, (i + 1) % nc[0]]),
-                            0.5 * (Bc[1, k, j, i] + Bc[1, k, (j + 1) % nc[1], i]),
-                            0.5 * (Bc[2, k, j, i] + Bc[2, (k + 1) % nc[2], j, i])]
-                    d = Uc[0, k, j, i]
-                    mom = Uc[1:4, k, j, i]
-                    ek = 0.5 * float(mom @ mom) / d
-                    b2c = sum(w * w for w in bpar)
-                    p = (gamma - 1) * (Uc[4, k, j, i] - ek - 0.5 * b2c)
-                    conservative = p - (gamma - 1) * 0.5 * (mean_b2 - b2c) > 0.0
-                    for pos, k2 in kids:
+                    cells = children_cells(Uc, Bc, ci % nc[0], cj % nc[1], ck % nc[2], [k2 for _, k2 in kids], gamma)
+                    for (pos, _), u in zip(kids, cells):
                         I, J, K = 2 * ci + pos[0], 2 * cj + pos[1], 2 * ck + pos[2]
-                        Uf[0, K, J, I] = d
-                        Uf[1:4, K, J, I] = mom
-                        Uf[4, K, J, I] = (Uc[4, k, j, i] + 0.5 * (k2 - mean_b2) if conservative
-                                          else p / (gamma - 1) + ek + 0.5 * k2)
+                        Uf[:, K, J, I] = u
                         for a in range(3):
                             b, cc = (a + 1) % 3, (a + 2) % 3
                             t = pos[b] + 2 * pos[cc]
