@@ -13,9 +13,8 @@ namespace mhd {
 __device__ __forceinline__ int wrap_delta(int d, int n) { return d > n / 2 ? d - n : (d < -(n / 2) ? d + n : d); }
 
 // Prolongation from a coarse level (nc) to a fine level (2 nc), paper
-// Sec. 3.3 (refinement operation).  Cell data: density and momentum are
-// injected; the energy is shared out so that the children keep a common
-// pressure and average to the parent (conservative, see prolong_parent).
+// Sec. 3.3 (refinement operation).  Cell data: conservative limited-linear
+// interpolation of the conserved variables (child_cells).
 // Face field (Balsara's divergence-free reconstruction, in 3D): a coarse
 // face carries a linear profile B + S_t1 t1 + S_t2 t2 in its transverse
 // coordinates (coarse-cell units, t in [-1/2, 1/2]) with MC-limited slopes
@@ -92,13 +91,67 @@ __device__ __forceinline__ T fine_face(const ParentFaces<T>& P, int p, int q) {
   return a0 + ab * tb + ac * tc;
 }
 
-// The eight children of coarse cell (i, j, k): conservative cell data and
-// their lower faces, where allowed.  cell_ok[q] / face_ok[q][A] say which
-// child q = a + 2 b + 4 c (position (a, b, c) in the parent) and which of its
-// lower faces may be written.  The children's energies are
-// e_parent + (|b_child|^2 - <|b|^2>)/2 (they average to the parent's); where
-// the resulting common pressure would not be positive the parent's pressure
-// is kept instead.
+// Conserved data of the eight children q = x + 2 y + 4 z of coarse cell
+// (i, j, k), given the children's |b|^2 (conservative interpolation): each
+// component takes the minmod-limited linear profile of the cell, u + (s_x sx
+// + s_y sy + s_z sz)/4 with sx, sy, sz = -1 / +1 for the lower / upper child,
+// so the children average to the parent; the energy also moves magnetic
+// energy to where the fine field has it, + (|b_q|^2 - <|b|^2>)/2.  If a child
+// would get a non-positive density or pressure, the children take the
+// parent's density and momentum and energies e + (|b_q|^2 - <|b|^2>)/2 (one
+// common pressure) or, where that pressure would not be positive, the
+// parent's pressure.  (cbx, cby, cbz): the parent's cell-centred field.
+template <typename T>
+__device__ __forceinline__ void child_cells(const Work& wc, const Coarse<T>& Uc, int i, int j, int k, T cbx, T cby,
+                                            T cbz, const T b2[8], T mean_b2, T gam, T u[8][5]) {
+  const long long pc = lin(wc, i, j, k);
+  const long long pu[3] = {lin(wc, wrapc(i + 1, wc.nx), j, k), lin(wc, i, wrapc(j + 1, wc.ny), k),
+                           lin(wc, i, j, wrapc(k + 1, wc.nz))};
+  const long long pd[3] = {lin(wc, wrapc(i - 1, wc.nx), j, k), lin(wc, i, wrapc(j - 1, wc.ny), k),
+                           lin(wc, i, j, wrapc(k - 1, wc.nz))};
+  T u0[5], sl[5][3];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    u0[m] = Uc[m * wc.N + pc];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      sl[m][d] = minmod(u0[m] - Uc[m * wc.N + pd[d]], Uc[m * wc.N + pu[d]] - u0[m]);
+  }
+  bool ok = true;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const T sx = (q & 1) ? T(1) : T(-1), sy = ((q >> 1) & 1) ? T(1) : T(-1), sz = (q >> 2) ? T(1) : T(-1);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) u[q][m] = u0[m] + T(0.25) * (sl[m][0] * sx + sl[m][1] * sy + sl[m][2] * sz);
+    u[q][4] = u[q][4] + T(0.5) * (b2[q] - mean_b2);
+    if (!(u[q][0] > T(0))) {
+      ok = false;
+    } else {
+      const T p = (gam - T(1)) * (u[q][4] - T(0.5) * (u[q][1] * u[q][1] + u[q][2] * u[q][2] + u[q][3] * u[q][3]) /
+                                                u[q][0] - T(0.5) * b2[q]);
+      ok = ok && p > T(0);
+    }
+  }
+  if (ok) return;
+  const T b2c = cbx * cbx + cby * cby + cbz * cbz;
+  const T d = u0[0], mx = u0[1], my = u0[2], mz = u0[3], e = u0[4];
+  const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / d;
+  const T pr = (gam - T(1)) * (e - ek - T(0.5) * b2c);
+  const bool conservative = pr - (gam - T(1)) * T(0.5) * (mean_b2 - b2c) > T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    u[q][0] = d;
+    u[q][1] = mx;
+    u[q][2] = my;
+    u[q][3] = mz;
+    u[q][4] = conservative ? e + T(0.5) * (b2[q] - mean_b2) : pr / (gam - T(1)) + ek + T(0.5) * b2[q];
+  }
+}
+
+// The eight children of coarse cell (i, j, k): conservative cell data
+// (child_cells) and their lower faces, where allowed.  cell_ok[q] /
+// face_ok[q][A] say which child q = a + 2 b + 4 c (position (a, b, c) in the
+// parent) and which of its lower faces may be written.
 template <typename T>
 __device__ __forceinline__ void prolong_parent(const Work& wc, const Work& wf, const Coarse<T>& Uc,
                                                const Coarse<T>& Bc, T* __restrict__ Uf, T* __restrict__ Bf,
@@ -131,25 +184,16 @@ __device__ __forceinline__ void prolong_parent(const Work& wc, const Work& wf, c
     mean_b2 += b2[q];
   }
   mean_b2 *= T(0.125);
-  const long long pc = lin(wc, i, j, k);
-  const T cbx = T(0.5) * (P.v[0][0] + P.v[0][1]);
-  const T cby = T(0.5) * (P.v[1][0] + P.v[1][1]);
-  const T cbz = T(0.5) * (P.v[2][0] + P.v[2][1]);
-  const T b2c = cbx * cbx + cby * cby + cbz * cbz;
-  const T d = Uc[pc], mx = Uc[wc.N + pc], my = Uc[2 * wc.N + pc], mz = Uc[3 * wc.N + pc], e = Uc[4 * wc.N + pc];
-  const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / d;
-  const T pr = (gam - T(1)) * (e - ek - T(0.5) * b2c);
-  const bool conservative = pr - (gam - T(1)) * T(0.5) * (mean_b2 - b2c) > T(0);
+  T u[8][5];
+  child_cells(wc, Uc, i, j, k, T(0.5) * (P.v[0][0] + P.v[0][1]), T(0.5) * (P.v[1][0] + P.v[1][1]),
+              T(0.5) * (P.v[2][0] + P.v[2][1]), b2, mean_b2, gam, u);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
     const long long pf = lin(wf, 2 * i + a, 2 * j + b, 2 * k + c);
     if (cell_ok[q]) {
-      Uf[pf] = d;
-      Uf[wf.N + pf] = mx;
-      Uf[2 * wf.N + pf] = my;
-      Uf[3 * wf.N + pf] = mz;
-      Uf[4 * wf.N + pf] = conservative ? e + T(0.5) * (b2[q] - mean_b2) : pr / (gam - T(1)) + ek + T(0.5) * b2[q];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) Uf[m * wf.N + pf] = u[q][m];
     }
     if (face_ok[q][0]) Bf[pf] = F[0][a][b + 2 * c];
     if (face_ok[q][1]) Bf[wf.N + pf] = F[1][b][c + 2 * a];
@@ -745,23 +789,16 @@ __device__ __forceinline__ void prolong_parent_kept(const Work& wc, const Work& 
   const long long pc = lin(wc, i, j, k);
   // the parent's cell-centred field from its coarse faces
   const Coarse<T> B0 = Bc, B1 = Bc.shift(wc.N), B2 = Bc.shift(2 * wc.N);
-  const T cbx = T(0.5) * (B0[pc] + B0[nbr(wc, i, j, k, 1, 0, 0)]);
-  const T cby = T(0.5) * (B1[pc] + B1[nbr(wc, i, j, k, 0, 1, 0)]);
-  const T cbz = T(0.5) * (B2[pc] + B2[nbr(wc, i, j, k, 0, 0, 1)]);
-  const T b2c = cbx * cbx + cby * cby + cbz * cbz;
-  const T d = Uc[pc], mx = Uc[wc.N + pc], my = Uc[2 * wc.N + pc], mz = Uc[3 * wc.N + pc], e = Uc[4 * wc.N + pc];
-  const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / d;
-  const T pr = (gam - T(1)) * (e - ek - T(0.5) * b2c);
-  const bool conservative = pr - (gam - T(1)) * T(0.5) * (mean_b2 - b2c) > T(0);
+  T u[8][5];
+  child_cells(wc, Uc, i, j, k, T(0.5) * (B0[pc] + B0[nbr(wc, i, j, k, 1, 0, 0)]),
+              T(0.5) * (B1[pc] + B1[nbr(wc, i, j, k, 0, 1, 0)]), T(0.5) * (B2[pc] + B2[nbr(wc, i, j, k, 0, 0, 1)]),
+              b2, mean_b2, gam, u);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
     const long long pf = lin(wf, 2 * i + a, 2 * j + b, 2 * k + c);
-    Uf[pf] = d;
-    Uf[wf.N + pf] = mx;
-    Uf[2 * wf.N + pf] = my;
-    Uf[3 * wf.N + pf] = mz;
-    Uf[4 * wf.N + pf] = conservative ? e + T(0.5) * (b2[q] - mean_b2) : pr / (gam - T(1)) + ek + T(0.5) * b2[q];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Uf[m * wf.N + pf] = u[q][m];
     if (a || !kept[0][0]) Bf[pf] = F[0][a][b + 2 * c];
     if (b || !kept[1][0]) Bf[wf.N + pf] = F[1][b][c + 2 * a];
     if (c || !kept[2][0]) Bf[2 * wf.N + pf] = F[2][c][a + 2 * b];
