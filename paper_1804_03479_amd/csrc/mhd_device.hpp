@@ -15,6 +15,10 @@ namespace mhd {
 template <typename T> __device__ __forceinline__ T dsqrt(T x);
 template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
 template <> __device__ __forceinline__ float dsqrt<float>(float x) { return sqrtf(x); }
+// 1/sqrt(x): one v_rsq in float (1 ulp), the divided square root in double
+template <typename T> __device__ __forceinline__ T drsqrt(T x);
+template <> __device__ __forceinline__ double drsqrt<double>(double x) { return 1.0 / sqrt(x); }
+template <> __device__ __forceinline__ float drsqrt<float>(float x) { return rsqrtf(x); }
 template <typename T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
 template <typename T> __device__ __forceinline__ T dmin(T a, T b) { return a < b ? a : b; }
 template <typename T> __device__ __forceinline__ T dmax(T a, T b) { return a > b ? a : b; }
@@ -254,7 +258,8 @@ template <typename T>
 __device__ __forceinline__ void hlld_star(const T w[7], const T u[7], T bn, T S, T SM, T pts, T us[7]) {
   const T d = w[0], vn = w[1];
   const T sv = S - vn, sm = S - SM;
-  const T ds = d * sv / sm;
+  const T ism = T(1) / sm;
+  const T ds = d * sv * ism;
   const T q = d * sv * sm;
   const T den = q - bn * bn;
   T v1, v2, b1, b2;
@@ -276,7 +281,7 @@ __device__ __forceinline__ void hlld_star(const T w[7], const T u[7], T bn, T S,
   const T pt = w[4] + T(0.5) * (bn * bn + w[5] * w[5] + w[6] * w[6]);
   const T vb = vn * bn + w[2] * w[5] + w[3] * w[6];
   const T vbs = SM * bn + v1 * b1 + v2 * b2;
-  const T es = (sv * u[4] - pt * vn + pts * SM + bn * (vb - vbs)) / sm;
+  const T es = (sv * u[4] - pt * vn + pts * SM + bn * (vb - vbs)) * ism;
   us[0] = ds; us[1] = ds * SM; us[2] = ds * v1; us[3] = ds * v2; us[4] = es; us[5] = b1; us[6] = b2;
 }
 
@@ -309,9 +314,10 @@ __device__ __forceinline__ void riemann_hlld(const T wl[7], const T wr[7], T bn,
   T usl[7], usr[7];
   hlld_star(wl, ul, bn, SL, SM, pts, usl);
   hlld_star(wr, ur, bn, SR, SM, pts, usr);
-  const T sdl = dsqrt(usl[0]), sdr = dsqrt(usr[0]);
-  const T SLs = SM - dabs(bn) / sdl;
-  const T SRs = SM + dabs(bn) / sdr;
+  const T isdl = drsqrt(usl[0]), isdr = drsqrt(usr[0]);
+  const T sdl = usl[0] * isdl, sdr = usr[0] * isdr;
+  const T SLs = SM - dabs(bn) * isdl;
+  const T SRs = SM + dabs(bn) * isdr;
   if (SLs >= T(0)) {
 #pragma unroll
     for (int m = 0; m < 7; ++m) f[m] = fl[m] + SL * (usl[m] - ul[m]);
@@ -324,7 +330,7 @@ __device__ __forceinline__ void riemann_hlld(const T wl[7], const T wr[7], T bn,
   }
   const T sgn = bn >= T(0) ? T(1) : T(-1);
   const T iden = T(1) / (sdl + sdr);
-  const T idl = T(1) / usl[0], idr = T(1) / usr[0];
+  const T idl = isdl * isdl, idr = isdr * isdr;
   const T v1l = usl[2] * idl, v2l = usl[3] * idl;
   const T v1r = usr[2] * idr, v2r = usr[3] * idr;
   const T v1ss = (sdl * v1l + sdr * v1r + (usr[5] - usl[5]) * sgn) * iden;
@@ -428,17 +434,17 @@ __device__ __forceinline__ void trace_cell(const T q[5][7], T bn_lo, T bn_hi, T 
   // primitive eigen-system of the cell (Roe & Balsara normalisation)
   const T d = q[2][0], u = q[2][1], p = q[2][4], by = q[2][5], bz = q[2][6];
   const T bn = T(0.5) * (bn_lo + bn_hi);
-  const T id = T(1) / d;
+  const T isd = drsqrt(d), sd = d * isd, id = isd * isd;
   const T asq = gam * p * id, a = dsqrt(asq);
-  const T casq = bn * bn * id, ctsq = (by * by + bz * bz) * id;
+  const T btsq = by * by + bz * bz;
+  const T casq = bn * bn * id, ctsq = btsq * id;
   const T sum = asq + casq + ctsq, dif = casq + ctsq - asq;
   const T cfsq = T(0.5) * (sum + dsqrt(dif * dif + T(4) * asq * ctsq));
   const T cssq = asq * casq / cfsq;
-  const T cf = dsqrt(cfsq), cs = dsqrt(cssq), ca = dsqrt(casq);
-  const T bt = dsqrt(by * by + bz * bz);
+  const T cf = dsqrt(cfsq), cs = dsqrt(cssq), ca = dabs(bn) * isd;
   T b2, b3;
-  if (bt > T(0)) {
-    const T ib = T(1) / bt;
+  if (btsq > T(0)) {
+    const T ib = drsqrt(btsq);
     b2 = by * ib;
     b3 = bz * ib;
   } else {
@@ -454,64 +460,54 @@ __device__ __forceinline__ void trace_cell(const T q[5][7], T bn_lo, T bn_hi, T 
     af = dsqrt((asq - cssq) * inv);
     as = dsqrt((cfsq - asq) * inv);
   }
-  const T sg = bn >= T(0) ? T(1) : T(-1), sd = dsqrt(d), isd = T(1) / sd;
+  const T sg = bn >= T(0) ? T(1) : T(-1);
   const T Cff = cf * af, Css = cs * as, Qf = cf * af * sg, Qs = cs * as * sg, Af = a * af * sd, As = a * as * sd;
-  const T nrm = T(0.5) / asq;
-  auto apply = [&](T lam, const T l[7], const T r[7]) {
+  const T iasq = T(1) / asq, nrm = T(0.5) * iasq;
+  // The left and right eigenvectors of the waves u -+ c (c = cf, ca, cs)
+  // differ only in the sign of an antisymmetric part: l = S -+ A, r = Rs -+ Ra.
+  // So each pair needs the projections S.x and A.x of x = dq, q6, and the
+  // two waves' amplitudes enter each edge as (sum) Rs + (difference) Ra.
+  // Transverse projections of the velocity (2, 3) and field (5, 6) parts:
+  const T pv_d = b2 * dq[2] + b3 * dq[3], pb_d = b2 * dq[5] + b3 * dq[6];
+  const T xv_d = b2 * dq[3] - b3 * dq[2], xb_d = b2 * dq[6] - b3 * dq[5];
+  const T pv_6 = b2 * q6[2] + b3 * q6[3], pb_6 = b2 * q6[5] + b3 * q6[6];
+  const T xv_6 = b2 * q6[3] - b3 * q6[2], xb_6 = b2 * q6[6] - b3 * q6[5];
+  // amplitudes toward the upper (R) and lower (L) edge of a wave with
+  // xi = lam dt/dx and projections (ad, a6); zero for waves moving away
+  auto amps = [&](T lam, T ad, T a6, T& aR, T& aL) {
     const T xi = lam * dtdx;
-    if (xi == T(0)) return;
-    T ad = T(0), a6 = T(0);
-#pragma unroll
-    for (int m = 0; m < 7; ++m) {
-      ad += l[m] * dq[m];
-      a6 += l[m] * q6[m];
-    }
-    if (xi > T(0)) {
-      const T amp = T(0.5) * xi * (ad - (T(1) - T(2.0 / 3.0) * xi) * a6);
-#pragma unroll
-      for (int m = 0; m < 7; ++m) sr[m] -= amp * r[m];
-    } else {
-      const T ax = -xi;
-      const T amp = T(0.5) * ax * (ad + (T(1) - T(2.0 / 3.0) * ax) * a6);
-#pragma unroll
-      for (int m = 0; m < 7; ++m) sl[m] += amp * r[m];
-    }
+    aR = T(0.5) * dmax(xi, T(0)) * (ad - (T(1) - T(2.0 / 3.0) * xi) * a6);
+    aL = T(0.5) * dmax(-xi, T(0)) * (ad + (T(1) + T(2.0 / 3.0) * xi) * a6);
   };
-  {
-    const T l[7] = {T(0), -nrm * Cff, nrm * Qs * b2, nrm * Qs * b3, nrm * af * id, nrm * As * b2 * id, nrm * As * b3 * id};
-    const T r[7] = {d * af, -Cff, Qs * b2, Qs * b3, d * asq * af, As * b2, As * b3};
-    apply(u - cf, l, r);
-  }
-  {
-    const T l[7] = {T(0), T(0), T(-0.5) * b3, T(0.5) * b2, T(0), T(-0.5) * sg * b3 * isd, T(0.5) * sg * b2 * isd};
-    const T r[7] = {T(0), T(0), -b3, b2, T(0), -sg * sd * b3, sg * sd * b2};
-    apply(u - ca, l, r);
-  }
-  {
-    const T l[7] = {T(0), -nrm * Css, -nrm * Qf * b2, -nrm * Qf * b3, nrm * as * id, -nrm * Af * b2 * id, -nrm * Af * b3 * id};
-    const T r[7] = {d * as, -Css, -Qf * b2, -Qf * b3, d * asq * as, -Af * b2, -Af * b3};
-    apply(u - cs, l, r);
-  }
-  {
-    const T l[7] = {T(1), T(0), T(0), T(0), -T(1) / asq, T(0), T(0)};
-    const T r[7] = {T(1), T(0), T(0), T(0), T(0), T(0), T(0)};
-    apply(u, l, r);
-  }
-  {
-    const T l[7] = {T(0), nrm * Css, nrm * Qf * b2, nrm * Qf * b3, nrm * as * id, -nrm * Af * b2 * id, -nrm * Af * b3 * id};
-    const T r[7] = {d * as, Css, Qf * b2, Qf * b3, d * asq * as, -Af * b2, -Af * b3};
-    apply(u + cs, l, r);
-  }
-  {
-    const T l[7] = {T(0), T(0), T(0.5) * b3, T(-0.5) * b2, T(0), T(-0.5) * sg * b3 * isd, T(0.5) * sg * b2 * isd};
-    const T r[7] = {T(0), T(0), b3, -b2, T(0), -sg * sd * b3, sg * sd * b2};
-    apply(u + ca, l, r);
-  }
-  {
-    const T l[7] = {T(0), nrm * Cff, -nrm * Qs * b2, -nrm * Qs * b3, nrm * af * id, nrm * As * b2 * id, nrm * As * b3 * id};
-    const T r[7] = {d * af, Cff, -Qs * b2, -Qs * b3, d * asq * af, As * b2, As * b3};
-    apply(u + cf, l, r);
-  }
+  // a wave pair (lam -+ c): returns the sums and differences of the amplitudes
+  auto pair = [&](T c, T s_d, T a_d, T s_6, T a_6, T& sR, T& dR, T& sL, T& dL) {
+    T rm, lm, rp, lp;
+    amps(u - c, s_d - a_d, s_6 - a_6, rm, lm);
+    amps(u + c, s_d + a_d, s_6 + a_6, rp, lp);
+    sR = rm + rp; dR = rp - rm;
+    sL = lm + lp; dL = lp - lm;
+  };
+  T fsR, fdR, fsL, fdL, ssR, sdR, ssL, sdL, asR, adR, asL, adL, eR, eL;
+  pair(cf, nrm * (af * id * dq[4] + As * id * pb_d), nrm * (Cff * dq[1] - Qs * pv_d),
+       nrm * (af * id * q6[4] + As * id * pb_6), nrm * (Cff * q6[1] - Qs * pv_6), fsR, fdR, fsL, fdL);
+  pair(cs, nrm * (as * id * dq[4] - Af * id * pb_d), nrm * (Css * dq[1] + Qf * pv_d),
+       nrm * (as * id * q6[4] - Af * id * pb_6), nrm * (Css * q6[1] + Qf * pv_6), ssR, sdR, ssL, sdL);
+  pair(ca, T(0.5) * sg * isd * xb_d, T(-0.5) * xv_d, T(0.5) * sg * isd * xb_6, T(-0.5) * xv_6, asR, adR, asL,
+       adL);
+  amps(u, dq[0] - dq[4] * iasq, q6[0] - q6[4] * iasq, eR, eL);
+  // edge += sign * sum over waves of amplitude * right eigenvector
+  auto update = [&](T s[7], T sgn, T fS, T fD, T sS, T sD, T aS, T aD, T e) {
+    const T ms = af * fS + as * sS, mv = Qf * sD - Qs * fD, mb = As * fS - Af * sS;
+    s[0] += sgn * (d * ms + e);
+    s[1] += sgn * (Cff * fD + Css * sD);
+    s[2] += sgn * (b2 * mv + b3 * aD);
+    s[3] += sgn * (b3 * mv - b2 * aD);
+    s[4] += sgn * (d * asq * ms);
+    s[5] += sgn * (b2 * mb - sg * sd * b3 * aS);
+    s[6] += sgn * (b3 * mb + sg * sd * b2 * aS);
+  };
+  update(sr, T(-1), fsR, fdR, ssR, sdR, asR, adR, eR);
+  update(sl, T(1), fsL, fdL, ssL, sdL, asL, adL, eL);
   // multidimensional source term of the transverse field
   const T hb = T(0.5) * dtdx * (bn_hi - bn_lo);   // (dt/2) dBn/dn
   sl[5] += hb * q[2][2];
