@@ -206,10 +206,15 @@ int mhd_dt_subdivide(mhd_ctx ctx, const double* dt_coarse, int parts, double* dt
  * mhd_prolong: with no fine group list, fills the whole fine level from the
  * coarse one; with a list, fills the ghost halo (halo cells around each listed
  * group, plus one above) of the listed groups: cells outside every listed
- * group, and faces whose two cells are both outside.  Density and momentum are
- * injected; the energy is e_parent + (|b_child|^2 - <|b|^2>)/2 over the eight
- * children (conservative; where the common child pressure would not be
- * positive, the parent's pressure is kept).  Face field: Balsara's
+ * group, and faces whose two cells are both outside.  Cell data: each
+ * conserved component of a child is the parent's plus a quarter of the
+ * minmod-limited slope of the parent's neighbours along each axis (the eight
+ * children average to the parent), the energy adding
+ * (|b_child|^2 - <|b|^2>)/2 over the eight children; a parent whose children
+ * would not all keep rho > 0 and p > 0 injects rho and M with the same energy
+ * shift (and keeps its pressure where even that would not be positive, not
+ * conservative).  The slopes read the parent's neighbours, so the coarse
+ * level needs valid data one cell around the prolonged region.  Face field: Balsara's
  * divergence-free reconstruction -- fine faces on a coarse face follow its
  * MC-limited linear profile, fine faces inside a coarse cell the quadratic
  * field matching the cell's six face profiles with no linear divergence
