@@ -2,7 +2,7 @@
 """Throughput of the unsplit MHD update on one MI355X.
 
 Headline workload (the precision-form configuration): the ABC-field box of
-the paper's Sec. 4.1(v)/4.2 (Eq. 20 with n = 1, A = B = C = 1, rho = p = 1)
+the paper's Sec. 5.1(v)/4.2 (Eq. 20 with n = 1, A = B = C = 1, rho = p = 1)
 on a 128^3 periodic grid with seeded uniform velocity noise of amplitude 0.1,
 CTU + PPM + HLLD + CT, Courant 1/2 (summed over directions), gamma = 5/3,
 timed in FP64 and FP32 side by side.  One step = CFL reduction + full update
@@ -14,7 +14,7 @@ Also timed, under "forms":
     FP64 form after --l1-steps steps;
   * the paper's own benchmark scheme (VL + PLM + Roe + CT, noise 0.01), for
     which the paper quotes 1.2e8 (FP32) and 5.5e7 (FP64) cell-updates/s on
-    one Tesla P100 (Sec. 4.2(i));
+    one Tesla P100 (Sec. 5.2(i));
   * the learned-flux form: a surrogate trained here on the GPU from captured
     interfaces, timed on the same box, with its L1 distance from the pure-HLLD
     run after --mlp-l1-steps steps (and the Roe run's, for scale), the HLLD
@@ -36,7 +36,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PAPER_F32 = 1.2e8   # cell-updates/s, Tesla P100, VL+PLM+Roe, FP32 (paper Sec. 4.2(i))
+PAPER_F32 = 1.2e8   # cell-updates/s, Tesla P100, VL+PLM+Roe, FP32 (paper Sec. 5.2(i))
 PAPER_F64 = 5.5e7   # same, FP64
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK = 2500.0                          # TFLOP/s, dense BF16

@@ -65,8 +65,8 @@ typedef struct {
   int recon;         /* MHD_PLM or MHD_PPM */
   int riemann;       /* MHD_ROE, MHD_HLLE, MHD_HLLD, MHD_MLP */
   int prec;          /* MHD_F64, MHD_F32, MHD_F32_MIXED */
-  double gamma;      /* adiabatic index, 5/3 in the paper (Sec. 4) */
-  double courant;    /* Courant factor, 1/2 in the paper (Sec. 4), summed over directions */
+  double gamma;      /* adiabatic index, 5/3 in the paper (Sec. 5) */
+  double courant;    /* Courant factor, 1/2 in the paper (Sec. 5), summed over directions */
   double beta_fp64;  /* MHD_F32_MIXED: cells with 2p/|B|^2 below this recover p in double */
   double mlp_dp;     /* MHD_MLP: relative pressure jump above which HLLD is used (negative: every face) */
   double mlp_drho;   /* MHD_MLP: relative density jump above which HLLD is used (negative: every face) */
@@ -75,7 +75,7 @@ typedef struct {
 /* One level: a dense periodic grid plus an optional list of patch groups.
  * groups == NULL (or n_groups == 0) updates every cell.  Otherwise only the
  * cells of the listed groups are updated; each entry is the origin (i0, j0,
- * k0) of a group of group_edge^3 cells (paper Sec. 3.3: eight patches of N^3
+ * k0) of a group of group_edge^3 cells (paper Sec. 4: eight patches of N^3
  * cells form a group of (2N)^3), and the cells outside the listed groups act
  * as ghost zones that the caller fills (e.g. by prolongation from the coarser
  * level).  All grid dimensions must then be multiples of group_edge. */

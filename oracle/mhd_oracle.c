@@ -654,7 +654,7 @@ void or_cons_to_prim(int nx, int ny, int nz, double gam, const double* U, const 
   primitives(&g, U, B, W8);
 }
 
-/* CFL time step (Sec. 3.2; Courant factor 1/2 in Sec. 4):
+/* CFL time step (Sec. 3.2; Courant factor 1/2 in Sec. 5):
  *   dt = courant * dx / max over cells of sum_d (|v_d| + c_f,d),
  * with the cell-centred field.  The Courant number is the sum over the three
  * directions: the unsplit update is stable for a summed number up to 1.

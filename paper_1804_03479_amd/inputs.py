@@ -13,17 +13,17 @@ lower face of cell i), and likewise ``by`` on y-faces, ``bz`` on z-faces.
 
 Problems:
 
-* ``abc``: the Arnold-Beltrami-Childress force-free field of Sec. 4.1(v),
+* ``abc``: the Arnold-Beltrami-Childress force-free field of Sec. 5.1(v),
   Eq. 20, in a uniform plasma, with i.i.d. uniform velocity noise drawn from
   ``numpy.random.default_rng(seed).uniform(-amp, amp, (3, nz, ny, nx))``
   (component-major, then z, y, x).  Face values are exact area averages of
   Eq. 20 (each component is independent of its own coordinate, so the
   discrete divergence of Eq. 16 is exactly zero).
-* ``abc_relaxation``: the paper's relaxation run of Sec. 4.1(v): the n = 2
+* ``abc_relaxation``: the paper's relaxation run of Sec. 5.1(v): the n = 2
   ABC field with A = B = C = sqrt(P0), the printed unstable eigenmode of
   Eqs. 21-23 added (exact face averages), and a uniform drift along the box
   diagonal of magnitude C_s / (8 sqrt(gamma)).
-* ``orszag_tang``: the vortex of Sec. 4.1(iii), Eq. 25 (2D, uniform along z
+* ``orszag_tang``: the vortex of Sec. 5.1(iii), Eq. 18 (2D, uniform along z
   on a periodic slab).
 * ``shock_tube``: the 1D Riemann problems of Table 1 (RJ2a, Torrilhon) on a
   periodic pencil: the left state fills the middle half of the pencil, the
@@ -255,7 +255,7 @@ def eigenmode_face_field(n: int, scale: float = 1.0, L: float = 1.0):
 def abc_relaxation_problem(n: int, rho0: float = 1.0, p0: float = 1.0, gamma: float = 5.0 / 3.0,
                            perturb: bool = True, drift: bool = True, noise: float = 1e-3,
                            seed: int = 0) -> Problem:
-    """Sec. 4.1(v): n = 2 ABC field, A = B = C = sqrt(P0) (plasma beta 1),
+    """Sec. 5.1(v): n = 2 ABC field, A = B = C = sqrt(P0) (plasma beta 1),
     the eigenmode of Eqs. 21-23 and a diagonal drift V0 (1, 1, 1) / sqrt(3) with
     |V0| = C_s / (8 sqrt(gamma)), C_s = sqrt(gamma P0 / rho0).
 
@@ -281,7 +281,7 @@ def abc_relaxation_problem(n: int, rho0: float = 1.0, p0: float = 1.0, gamma: fl
 
 def orszag_tang(n: int, nz: int = 16, gamma: float = 5.0 / 3.0, rho0: float = 25.0 / (36.0 * math.pi),
                 p0: float = 5.0 / (12.0 * math.pi)) -> Problem:
-    """Sec. 4.1(iii), Eq. 25 on an n x n x nz periodic slab of side 1 in x, y
+    """Sec. 5.1(iii), Eq. 18 on an n x n x nz periodic slab of side 1 in x, y
     (cells 1/n), uniform along z: V = C_s (-sin 2 pi y, sin 2 pi x, 0),
     B = sqrt(P0/gamma) (-sin 2 pi y, sin 4 pi x, 0), rho0, P0 constant
     (defaults give C_s = 1).  Bx on x-faces and By on y-faces are exact

@@ -1,5 +1,5 @@
 """The Orszag-Tang vortex with AMR against uniform grids (paper
-Sec. 4.1(iii)), on one GPU.
+Sec. 5.1(iii)), on one GPU.
 
 The 2D vortex (inputs.orszag_tang) runs on periodic slabs uniform along z:
 an AMR hierarchy (root n^2, `levels` refined levels regridded every few root

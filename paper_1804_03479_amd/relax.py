@@ -1,4 +1,4 @@
-"""The ABC relaxation run of paper Sec. 4.1(v) on one GPU.
+"""The ABC relaxation run of paper Sec. 5.1(v) on one GPU.
 
 The n = 2 ABC field with the eigenmode of Eqs. 21-23 and a diagonal drift
 (inputs.abc_relaxation_problem) is advanced with the CTU + PPM + HLLD + CT

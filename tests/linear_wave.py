@@ -1,4 +1,4 @@
-"""Linear MHD waves along the box diagonal (paper Sec. 4.1(i)).
+"""Linear MHD waves along the box diagonal (paper Sec. 5.1(i)).
 
 The background state and eigenvectors are not printed in the paper; this
 module fixes them: rho = 1, p = 1/gamma (sound speed 1), field 1 along the

@@ -1,4 +1,4 @@
-"""Linear-wave convergence at the paper's set-up (Sec. 4.1(i)): CTU + PLM +
+"""Linear-wave convergence at the paper's set-up (Sec. 5.1(i)): CTU + PLM +
 Roe in double precision, slow, Alfven and fast waves of relative amplitude
 1e-6 along the box diagonal for one period, L1 error of the primitive
 variables against the initial state (the paper's E_L1) at 32^3, 64^3 and

@@ -1,4 +1,4 @@
-"""The ABC relaxation of paper Sec. 4.1(v) at 64^3 in FP32 (the paper's
+"""The ABC relaxation of paper Sec. 5.1(v) at 64^3 in FP32 (the paper's
 precision for this run), to 31 sound-crossing times.  The paper reports:
 total energy constant, magnetic energy falling to about half (the n = 1
 ABC state has half the energy of the n = 2 one at equal helicity,

@@ -1,4 +1,4 @@
-"""The Table 1 Riemann problems (paper Sec. 4.1(ii)) through the C ABI:
+"""The Table 1 Riemann problems (paper Sec. 5.1(ii)) through the C ABI:
 parity with the oracle on a coarse pencil, the same solution along x, y and
 z, and at the paper's resolution (512 cells per unit length, PPM + Roe, FP64)
 positive density and pressure everywhere and fast shocks captured in at most

@@ -1,13 +1,13 @@
 """Grid-level pins of the oracle against what the paper fixes:
 
 * Eq. 10 telescopes: totals of mass, momentum and energy are unchanged to
-  round-off on a periodic box (Sec. 4.1(v): total energy constant to machine
+  round-off on a periodic box (Sec. 5.1(v): total energy constant to machine
   precision).
 * Eq. 13 + Eq. 16: the discrete divergence is unchanged by a step, for any
   initial face field, so a solenoidal field stays solenoidal to round-off.
-* Sec. 4.1(i): linear slow, Alfven and fast waves along the diagonal converge
+* Sec. 5.1(i): linear slow, Alfven and fast waves along the diagonal converge
   at second order.
-* Sec. 4.1(v) closed forms: magnetic energy of the ABC field; a force-free
+* Sec. 5.1(v) closed forms: magnetic energy of the ABC field; a force-free
   ABC field with zero velocity stays static up to truncation error; the
   Galilean-boosted ABC field is an exact moving solution; the A = B = C field
   is invariant under the cyclic permutation of axes.
@@ -78,7 +78,7 @@ def test_cfl_uniform_state_closed_form(orc):
 
 
 def test_abc_magnetic_energy_closed_form(orc):
-    # U_B = (A^2 + B^2 + C^2) L^3 / 2 (Sec. 4.1(v)), times the square of the
+    # U_B = (A^2 + B^2 + C^2) L^3 / 2 (Sec. 5.1(v)), times the square of the
     # face-average factor sinc(k dx / 2) of Eq. 14
     n = 16
     A, Bc, C = 1.0, 0.7, 1.3
@@ -244,7 +244,7 @@ def test_ctu_ppm_hlld_linear_wave_converges(orc, wave):
 
 
 def test_ctu_plm_roe_linear_wave_converges(orc):
-    # the paper's linear-wave combination: CTU + PLM + Roe (Sec. 4.1(i))
+    # the paper's linear-wave combination: CTU + PLM + Roe (Sec. 5.1(i))
     e16 = ctu_wave_l1(orc, 16, "fast", 0, 0)
     e32 = ctu_wave_l1(orc, 32, "fast", 0, 0)
     assert e32 < e16 / 2.5

@@ -1,4 +1,4 @@
-"""Pins of the oracle on the Table 1 Riemann problems (paper Sec. 4.1(ii)):
+"""Pins of the oracle on the Table 1 Riemann problems (paper Sec. 5.1(ii)):
 the same tube along x, y and z gives the same profiles (a transposed index or
 a swapped component in one direction's sweep breaks this), the totals of the
 periodic pencil are conserved, and the initial data hold the tabulated

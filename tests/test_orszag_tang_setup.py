@@ -1,6 +1,6 @@
-"""Pins of the Orszag-Tang set-up (paper Sec. 4.1(iii), Eq. 25): the sound
+"""Pins of the Orszag-Tang set-up (paper Sec. 5.1(iii), Eq. 18): the sound
 speed is one with the default rho0, P0; the field is divergence-free on the
-slab (exact face averages); velocity and field follow Eq. 25 at cell
+slab (exact face averages); velocity and field follow Eq. 18 at cell
 centres / face centres (up to the face-average factor)."""
 import math
 

@@ -1,4 +1,4 @@
-"""Pins of the ABC relaxation set-up (paper Sec. 4.1(v)) and of its
+"""Pins of the ABC relaxation set-up (paper Sec. 5.1(v)) and of its
 diagnostics against the closed forms the paper states: U_B = (A^2 + B^2 +
 C^2) L^3 / 2 and H = U_B L / (pi n) for an ABC field of n periods; the
 eigenmode of Eqs. 21-23 is divergence-free with wave vectors of length
