@@ -336,8 +336,11 @@ int mhd_mlp_prepare(mhd_ctx ctx, const float* samples_dev, int n, float* X_dev, 
 int mhd_mlp_face_flux(mhd_ctx ctx, const float* states_dev, int n, float* flux_dev, int* used_hlld_dev);
 /* Interface capture for training data: while set, every stride-th face of the
  * CTU Riemann stages writes (wl, wr, bn, flux) to buf_dev[cap][22] (FP32
- * forms only); *count_dev counts attempted writes (writes stop at cap).
- * buf_dev == NULL turns capture off. */
+ * forms only; in the learned-flux form the flux the face used, network or
+ * HLLD); *count_dev counts attempted writes (writes stop at cap).
+ * buf_dev == NULL turns capture off.  Every call drops the graph captured by
+ * mhd_advance_graph (the capture settings are arguments of its kernels), so
+ * the next mhd_advance_graph captures again. */
 int mhd_set_capture(mhd_ctx ctx, float* buf_dev, long long cap, unsigned long long* count_dev, int stride);
 
 /* Wait for the context's stream and report sticky device-side errors

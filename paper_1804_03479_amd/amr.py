@@ -48,7 +48,7 @@ import numpy as np
 import torch
 
 from . import inputs
-from .mhd import Level, Solver
+from .mhd import Level, Solver, check_group_origins
 
 
 def nested_groups(n_root: int, counts, edge: int = 16, seed: int = 0):
@@ -102,15 +102,19 @@ class Hierarchy:
                 fine = Level(U, Bf, p["dx"] / (1 << lvl))
                 self.solvers[lvl].prolong(self.levels[-1], fine)     # whole level, initial data
                 if capacity is None:
+                    fine.group_edge = edge
                     fine.set_groups(torch.from_numpy(g).cuda())
                 else:
                     # at most every candidate group of the level
                     cap = min(capacity, int(np.prod(shape)) // edge ** 3)
                     if len(g) > cap:
                         raise ValueError("initial group list longer than the capacity")
+                    check_group_origins(g, shape, edge)
                     buf = torch.zeros((cap, 3), dtype=torch.int32, device="cuda")
                     buf[:len(g)] = torch.from_numpy(g).cuda()
-                    fine.set_groups(buf)
+                    fine.group_edge = edge
+                    # rows past the device count are unused padding
+                    fine.set_groups(buf, validate=False)
                     fine.n_groups_dev = torch.tensor([len(g)], dtype=torch.int32, device="cuda")
                 fine.group_edge = edge
                 self.levels.append(fine)
@@ -159,7 +163,8 @@ class Hierarchy:
                 cap = fine.groups.shape[0]
                 buf = self._new[:cap]
                 s.regrid_flag(coarse, threshold, buffer, self.edge, buf, self._count, self._wanted[lvl - 1:lvl])
-                new = Level(fine.U, fine.B, fine.dx, groups=buf, group_edge=self.edge)
+                # the list was written by the library's regridding kernels
+                new = Level(fine.U, fine.B, fine.dx, groups=buf, group_edge=self.edge, validate_groups=False)
                 new.n_groups_dev = self._count
                 s.prolong_new_groups(coarse, new, fine)
                 fine.groups.copy_(buf)

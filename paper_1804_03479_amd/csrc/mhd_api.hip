@@ -220,7 +220,7 @@ int build_occupancy_into(mhd_ctx_s* c, const mhd_level* lv, int** occ, long long
   k_occ_clear<<<(unsigned)((ng + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(*occ, ng);
   k_occ_set<<<(unsigned)((lv->n_groups + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
       *occ, lv->groups, lv->n_groups, lv->n_groups_dev, lv->group_edge, lv->nx / lv->group_edge,
-      lv->ny / lv->group_edge);
+      lv->ny / lv->group_edge, lv->nz / lv->group_edge);
   return MHD_OK;
 }
 
@@ -343,9 +343,12 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
   if constexpr (kMlp) {
     const unsigned nb = sblocks(wf1);
     const long long n7 = 7LL * wf1.NS;
-    k_flux_dir_mlp<0, false, L><<<nb, kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb);
-    k_flux_dir_mlp<1, false, L><<<nb, kBlock, 0, st>>>(wf1, QL + n7, QR + n7, B, F1, gam, c->mlpw, dp, drho, c->nfb);
-    k_flux_dir_mlp<2, false, L><<<nb, kBlock, 0, st>>>(wf1, QL + 2 * n7, QR + 2 * n7, B, F1, gam, c->mlpw, dp, drho, c->nfb);
+    k_flux_dir_mlp<0, false, L><<<nb, kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb,
+                                                  c->capture);
+    k_flux_dir_mlp<1, false, L><<<nb, kBlock, 0, st>>>(wf1, QL + n7, QR + n7, B, F1, gam, c->mlpw, dp, drho, c->nfb,
+                                                  c->capture);
+    k_flux_dir_mlp<2, false, L><<<nb, kBlock, 0, st>>>(wf1, QL + 2 * n7, QR + 2 * n7, B, F1, gam, c->mlpw, dp, drho, c->nfb,
+                                                  c->capture);
   } else
     k_flux_q<T, S, L><<<sblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->nfb, c->capture);
   mark(3);
@@ -357,11 +360,14 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
     float* Qc = (float*)c->Qc;
     const unsigned nb = sblocks(wf2);
     k_ctu_correct_dir<0, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
-    k_flux_dir_mlp<0, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
+    k_flux_dir_mlp<0, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
+                                                  c->capture);
     k_ctu_correct_dir<1, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
-    k_flux_dir_mlp<1, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
+    k_flux_dir_mlp<1, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
+                                                  c->capture);
     k_ctu_correct_dir<2, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
-    k_flux_dir_mlp<2, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb);
+    k_flux_dir_mlp<2, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
+                                                  c->capture);
   } else
     k_ctu_correct<T, S, L><<<sblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam,
                                                              c->nfb, c->capture);
@@ -948,13 +954,13 @@ int mhd_mlp_face_flux(mhd_ctx c, const float* states_dev, int n, float* flux_dev
 
 int mhd_set_capture(mhd_ctx c, float* buf_dev, long long cap, unsigned long long* count_dev, int stride) {
   if (!c) return MHD_ERR_INVALID_ARG;
-  if (!buf_dev) {
-    c->capture = Capture{nullptr, 0, nullptr, 1};
-    return MHD_OK;
-  }
-  if (cap <= 0 || !count_dev || stride <= 0) return MHD_ERR_INVALID_ARG;
-  if (c->cfg.prec == MHD_F64) return MHD_ERR_UNSUPPORTED;
-  c->capture = Capture{buf_dev, cap, count_dev, stride};
+  if (buf_dev && (cap <= 0 || !count_dev || stride <= 0)) return MHD_ERR_INVALID_ARG;
+  if (buf_dev && c->cfg.prec == MHD_F64) return MHD_ERR_UNSUPPORTED;
+  // the capture settings are kernel arguments of a captured step graph:
+  // drop it, so a replay neither writes to a released buffer nor misses a
+  // newly set one
+  drop_graph(c);
+  c->capture = buf_dev ? Capture{buf_dev, cap, count_dev, stride} : Capture{nullptr, 0, nullptr, 1};
   return MHD_OK;
 }
 

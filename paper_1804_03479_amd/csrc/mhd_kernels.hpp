@@ -794,11 +794,13 @@ __global__ void __launch_bounds__(kBlock) k_ctu_correct_dir(Work w, const float*
 // Learned flux (HLLD at strong jumps) of the D-faces from scratch states
 // QLd[m * NS + s], QRd[m * NS + s] (m = 0..6) and the normal field: the level's
 // B[D * N + p] (predictor) or the half-step scratch Bh[D * NS + s] (BN_SCRATCH).
+// With capture on, the face's states and the flux it used are recorded.
 template <int D, bool BN_SCRATCH, bool L>
 __global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __restrict__ QLd,
                                                          const float* __restrict__ QRd, const float* __restrict__ Bn,
                                                          float* __restrict__ F, float gam, const MlpWeights* mw,
-                                                         float dp, float drho, unsigned long long* nfb) {
+                                                         float dp, float drho, unsigned long long* nfb,
+                                                         Capture cp) {
   __shared__ MlpShared sh;
   mlp_load_weights(sh, mw);
   const long long N = w.N, NS = w.NS;
@@ -823,7 +825,10 @@ __global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __
     }
     if (active) bn = BN_SCRATCH ? Bn[D * NS + s] : Bn[D * N + p];
     fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
-    if (active) store_flux<float, D>(F, NS, s, f);
+    if (active) {
+      capture_face(cp, 3 * p + D, wl, wr, bn, f);
+      store_flux<float, D>(F, NS, s, f);
+    }
   }
   block_count_atomic(fb, nfb);
 }
@@ -835,11 +840,13 @@ __global__ void __launch_bounds__(kBlock) k_occ_clear(int* occ, long long n) {
 }
 
 __global__ void __launch_bounds__(kBlock) k_occ_set(int* occ, const int* groups, int n_groups, const int* n_dev,
-                                                    int edge, int gnx, int gny) {
+                                                    int edge, int gnx, int gny, int gnz) {
   const int g = blockIdx.x * kBlock + threadIdx.x;
   const int n = n_dev ? min(*n_dev, n_groups) : n_groups;
   if (g >= n) return;
   const int gi = groups[3 * g] / edge, gj = groups[3 * g + 1] / edge, gk = groups[3 * g + 2] / edge;
+  // origins outside the level are never written (the host binding rejects them)
+  if (groups[3 * g] < 0 || groups[3 * g + 1] < 0 || groups[3 * g + 2] < 0 || gi >= gnx || gj >= gny || gk >= gnz) return;
   occ[((long long)gk * gny + gj) * gnx + gi] = g + 1;   // 0: not listed, else group index + 1
 }
 

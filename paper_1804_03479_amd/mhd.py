@@ -124,6 +124,31 @@ def dtype_of(prec: int):
     return torch.float64 if prec == F64 else torch.float32
 
 
+def check_group_origins(origins, shape, edge: int):
+    """Raise ValueError unless every (x, y, z) origin row is a multiple of edge
+    inside the grid of shape (nz, ny, nx) and no origin is listed twice."""
+    import numpy as np
+    o = np.asarray(origins, dtype=np.int64).reshape(-1, 3)
+    nz, ny, nx = shape
+    if edge <= 0 or nx % edge or ny % edge or nz % edge:
+        raise ValueError(f"group edge {edge} must divide the grid {shape}")
+    if o.size == 0:
+        return
+    if (o < 0).any() or (o[:, 0] >= nx).any() or (o[:, 1] >= ny).any() or (o[:, 2] >= nz).any():
+        raise ValueError("group origins must lie inside the grid")
+    if (o % edge).any():
+        raise ValueError(f"group origins must be multiples of the group edge {edge}")
+    if len(np.unique(o, axis=0)) != len(o):
+        raise ValueError("group origins must be unique")
+
+
+def check_dt_tensor(t, what: str = "dt"):
+    """A device time step or time: one contiguous float64 element on the GPU."""
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+            and t.numel() >= 1):
+        raise ValueError(f"{what} must be a contiguous float64 device tensor")
+
+
 class Level:
     """A dense periodic level: conserved U (5, nz, ny, nx), face B (3, nz, ny, nx).
 
@@ -132,7 +157,7 @@ class Level:
     """
 
     def __init__(self, U: torch.Tensor, B: torch.Tensor, dx: float, groups: torch.Tensor | None = None,
-                 group_edge: int = 16, E64: torch.Tensor | None = None):
+                 group_edge: int = 16, E64: torch.Tensor | None = None, validate_groups: bool = True):
         if U.dim() != 4 or U.shape[0] != 5 or B.shape != (3,) + tuple(U.shape[1:]):
             raise ValueError("U must be (5, nz, ny, nx) and B (3, nz, ny, nx)")
         if not (U.is_cuda and B.is_cuda and U.is_contiguous() and B.is_contiguous()):
@@ -143,13 +168,21 @@ class Level:
         self.E64 = E64
         self.group_edge = int(group_edge)
         self.n_groups_dev = None
-        self.set_groups(groups)
+        self.set_groups(groups, validate=validate_groups)
 
-    def set_groups(self, groups):
+    def set_groups(self, groups, validate: bool = True):
+        """Group list of the level.  With validate (the default) the origins are
+        checked on the host: multiples of group_edge inside the grid, no
+        duplicates (a duplicate would update its cells twice in place).  Lists
+        written on the device by the library's regridding are valid by
+        construction and pass validate=False (their contents are not on the
+        host)."""
         if groups is not None:
             if groups.dtype != torch.int32 or not groups.is_cuda or groups.dim() != 2 or groups.shape[1] != 3:
                 raise ValueError("groups must be an int32 device tensor of shape (n, 3)")
             groups = groups.contiguous()
+            if validate:
+                check_group_origins(groups.cpu().numpy(), self.shape, self.group_edge)
         self.groups = groups
 
     @property
@@ -206,13 +239,17 @@ class Solver:
         return lv
 
     def prim_to_cons(self, lv: Level, W5: torch.Tensor):
+        self._check_level(lv)
         if W5.shape != lv.U.shape or W5.dtype != self.dtype or not W5.is_contiguous():
             raise ValueError("W5 must match U in shape and dtype")
         d = lv.desc()
         _check(self.lib.mhd_prim_to_cons(self.h, ctypes.byref(d), ctypes.c_void_p(W5.data_ptr())), "mhd_prim_to_cons")
 
     def _check_level(self, lv: Level):
-        if lv.U.dtype != self.dtype:
+        """dtype and shape checks the C side cannot make (it sees no element size)."""
+        if not isinstance(lv, Level):
+            raise ValueError("expected a Level")
+        if lv.U.dtype != self.dtype or lv.B.dtype != self.dtype:
             raise ValueError(f"level dtype {lv.U.dtype} does not match solver precision {self.dtype}")
         if self.prec == F32_MIXED:
             e = lv.E64
@@ -228,6 +265,8 @@ class Solver:
         return dt.value
 
     def cfl_dt_device(self, lv: Level, out: torch.Tensor):
+        self._check_level(lv)
+        check_dt_tensor(out, "out")
         d = lv.desc()
         _check(self.lib.mhd_cfl_dt(self.h, ctypes.byref(d), None, ctypes.c_void_p(out.data_ptr())), "mhd_cfl_dt")
 
@@ -237,11 +276,16 @@ class Solver:
         _check(self.lib.mhd_step(self.h, ctypes.byref(d), float(dt)), "mhd_step")
 
     def step_devdt(self, lv: Level, dt_dev: torch.Tensor):
+        self._check_level(lv)
+        check_dt_tensor(dt_dev, "dt_dev")
         d = lv.desc()
         _check(self.lib.mhd_step_devdt(self.h, ctypes.byref(d), ctypes.c_void_p(dt_dev.data_ptr())), "mhd_step_devdt")
 
     def advance(self, lv: Level, dt_dev: torch.Tensor | None = None, t_dev: torch.Tensor | None = None):
         self._check_level(lv)
+        for t, nm in ((dt_dev, "dt_dev"), (t_dev, "t_dev")):
+            if t is not None:
+                check_dt_tensor(t, nm)
         d = lv.desc()
         _check(self.lib.mhd_advance(self.h, ctypes.byref(d),
                                     None if dt_dev is None else ctypes.c_void_p(dt_dev.data_ptr()),
@@ -250,6 +294,9 @@ class Solver:
     def advance_graph(self, lv: Level, dt_dev: torch.Tensor | None = None, t_dev: torch.Tensor | None = None):
         """mhd_advance replayed from a captured HIP graph (needs a non-default stream)."""
         self._check_level(lv)
+        for t, nm in ((dt_dev, "dt_dev"), (t_dev, "t_dev")):
+            if t is not None:
+                check_dt_tensor(t, nm)
         d = lv.desc()
         _check(self.lib.mhd_advance_graph(self.h, ctypes.byref(d),
                                           None if dt_dev is None else ctypes.c_void_p(dt_dev.data_ptr()),
@@ -260,11 +307,15 @@ class Solver:
         _check(self.lib.mhd_set_launch(self.h, int(blocks_per_cu)), "mhd_set_launch")
 
     def cfl_dt_min(self, lv: Level, dt_dev: torch.Tensor, scale: float = 1.0):
+        self._check_level(lv)
+        check_dt_tensor(dt_dev, "dt_dev")
         d = lv.desc()
         _check(self.lib.mhd_cfl_dt_min(self.h, ctypes.byref(d), float(scale), ctypes.c_void_p(dt_dev.data_ptr())),
                "mhd_cfl_dt_min")
 
     def dt_subdivide(self, dt_coarse: torch.Tensor, parts: int, dt_fine: torch.Tensor):
+        check_dt_tensor(dt_coarse, "dt_coarse")
+        check_dt_tensor(dt_fine, "dt_fine")
         _check(self.lib.mhd_dt_subdivide(self.h, ctypes.c_void_p(dt_coarse.data_ptr()), int(parts),
                                          ctypes.c_void_p(dt_fine.data_ptr())), "mhd_dt_subdivide")
 
@@ -272,6 +323,10 @@ class Solver:
                 alpha: float = 1.0):
         """Fine level (or its ghost halos) from the coarse level; with coarse_old,
         from old + alpha (coarse - old)."""
+        self._check_level(coarse)
+        self._check_level(fine)
+        if coarse_old is not None:
+            self._check_level(coarse_old)
         dc, df = coarse.desc(), fine.desc()
         if coarse_old is None and alpha == 1.0:
             _check(self.lib.mhd_prolong(self.h, ctypes.byref(dc), ctypes.byref(df), int(halo)), "mhd_prolong")
@@ -282,6 +337,7 @@ class Solver:
 
     def workspace_bytes(self, lv: Level) -> int:
         """Device bytes of stage scratch this context needs to update lv."""
+        self._check_level(lv)
         d = lv.desc()
         v = ctypes.c_size_t()
         _check(self.lib.mhd_workspace_bytes(self.h, ctypes.byref(d), ctypes.byref(v)), "mhd_workspace_bytes")
@@ -296,6 +352,7 @@ class Solver:
                 raise ValueError("regrid outputs must be contiguous int32 device tensors")
         if groups_out.dim() != 2 or groups_out.shape[1] != 3:
             raise ValueError("groups_out must be (capacity, 3)")
+        self._check_level(coarse)
         d = coarse.desc()
         _check(self.lib.mhd_regrid_flag(self.h, ctypes.byref(d), float(threshold), int(buffer), int(fine_edge),
                                         ctypes.c_void_p(groups_out.data_ptr()), int(groups_out.shape[0]),
@@ -303,12 +360,15 @@ class Solver:
                "mhd_regrid_flag")
 
     def prolong_new_groups(self, coarse: Level, fine_new: Level, fine_old: Level | None):
+        for lv in (coarse, fine_new) + (() if fine_old is None else (fine_old,)):
+            self._check_level(lv)
         dc, dn = coarse.desc(), fine_new.desc()
         do = None if fine_old is None else ctypes.byref(fine_old.desc())
         _check(self.lib.mhd_prolong_new_groups(self.h, ctypes.byref(dc), ctypes.byref(dn), do),
                "mhd_prolong_new_groups")
 
     def accumulate_registers(self, lv: Level, weight: float, reset: bool):
+        self._check_level(lv)
         d = lv.desc()
         _check(self.lib.mhd_accumulate_registers(self.h, ctypes.byref(d), float(weight), int(bool(reset))),
                "mhd_accumulate_registers")
@@ -317,22 +377,29 @@ class Solver:
                 fine_registers: bool = False):
         """Coarse-fine flux and EMF correction after both levels covered the coarse
         step dt_dev (fine_registers: the fine level sub-cycled and accumulated)."""
+        self._check_level(coarse)
+        fine_solver._check_level(fine)
+        check_dt_tensor(dt_dev, "dt_dev")
         dc, df = coarse.desc(), fine.desc()
         _check(self.lib.mhd_correct(self.h, ctypes.byref(dc), fine_solver.h, ctypes.byref(df),
                                     ctypes.c_void_p(dt_dev.data_ptr()), int(bool(fine_registers))), "mhd_correct")
 
     def restrict(self, fine: Level, coarse: Level):
+        self._check_level(fine)
+        self._check_level(coarse)
         dc, df = coarse.desc(), fine.desc()
         _check(self.lib.mhd_restrict(self.h, ctypes.byref(df), ctypes.byref(dc)), "mhd_restrict")
 
     # -- diagnostics
     def divb(self, lv: Level):
+        self._check_level(lv)
         d = lv.desc()
         mx, l1 = ctypes.c_double(), ctypes.c_double()
         _check(self.lib.mhd_divB(self.h, ctypes.byref(d), ctypes.byref(mx), ctypes.byref(l1)), "mhd_divB")
         return mx.value, l1.value
 
     def sums(self, lv: Level):
+        self._check_level(lv)
         d = lv.desc()
         out = (ctypes.c_double * 7)()
         _check(self.lib.mhd_sums(self.h, ctypes.byref(d), ctypes.byref(out)), "mhd_sums")
@@ -348,6 +415,7 @@ class Solver:
 
     def profile_step(self, lv: Level, nrep: int = 5) -> dict:
         """Mean milliseconds per stage over nrep advancing steps."""
+        self._check_level(lv)
         n = self.lib.mhd_num_stages(self.h)
         out = (ctypes.c_double * n)()
         d = lv.desc()

@@ -1,10 +1,16 @@
 """GPU tests of the learned interface flux against the FP64 reference with
 the kernels' BF16 rounding points reproduced (oracle/mlp.py).
 
-Bars: normwise relative error <= 1e-3 for forward, backward and an Adam
-step (BF16 operands, FP32 accumulation); learned-flux faces that fall back
-use HLLD to FP32 round-off; with negative thresholds the MLP form
-reproduces the HLLD form bit for bit.
+Bars, element by element: |gpu - ref| <= RTOL |ref| + ATOL max|ref| per
+tensor for forward, backward and an Adam step.  Both sides round the same
+operands to BF16; what remains is the FP32 accumulation order, and where
+that moves an activation across a BF16 rounding boundary the activation
+differs by one BF16 ulp (2^-8 relative), which moves an output by 2^-8 of
+one of its 64 or more summed terms: far below ATOL = 2e-3 of the tensor's
+largest entry.  Learned-flux faces that fall back use HLLD to FP32
+round-off; the network inside a step (captured faces) matches the
+reference surrogate on the same face states; with negative thresholds the
+MLP form reproduces the HLLD form to FP32 round-off.
 """
 import numpy as np
 import pytest
@@ -24,6 +30,20 @@ from paper_1804_03479_amd.mhd import Level, MlpOps, Solver  # noqa: E402
 
 def nrel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+RTOL, ATOL = 1e-2, 2e-3
+
+
+def assert_elementwise(a, b, rtol=RTOL, atol=ATOL, what=""):
+    """Every element: |a - b| <= rtol |b| + atol max|b|; reports the worst."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    bound = rtol * np.abs(b) + atol * max(float(np.abs(b).max()), 1e-300)
+    ratio = np.abs(a - b) / bound
+    worst = float(ratio.max()) if ratio.size else 0.0
+    assert worst <= 1.0, (what, worst, int((ratio > 1).sum()), ratio.size)
+    return worst
 
 
 def dev(a):
@@ -52,7 +72,7 @@ def test_forward_matches_oracle(ops, theta, n):
     X = rng.standard_normal((n, 15)).astype(np.float32).astype(np.float64)
     Y = ops.forward(dev(theta), dev(X)).cpu().numpy()
     Yo, _ = omlp.forward(theta, X, bf16_ops=True)
-    assert nrel(Y, Yo) <= 1e-3
+    assert_elementwise(Y, Yo, what="forward")
 
 
 @pytest.mark.parametrize("n", [16, 513])
@@ -63,8 +83,8 @@ def test_backward_matches_oracle(ops, theta, n):
     G = ops.backward(dev(theta), dev(X), dev(dY)).cpu().numpy()
     _, cache = omlp.forward(theta, X, bf16_ops=True)
     Go = omlp.backward(theta, cache, dY, bf16_ops=True)
-    for a, b in zip(omlp.unpack(G), omlp.unpack(Go)):
-        assert nrel(a, b) <= 1e-3
+    for k, (a, b) in enumerate(zip(omlp.unpack(G), omlp.unpack(Go))):
+        assert_elementwise(a, b, what=f"gradient part {k}")
 
 
 def test_train_step_matches_oracle(ops, theta):
@@ -81,9 +101,18 @@ def test_train_step_matches_oracle(ops, theta):
     lo, go = omlp.mse_grad(theta, X, T, bf16_ops=True)
     to, _, _ = omlp.adam(theta, np.zeros_like(theta), np.zeros_like(theta), go, 1, 1e-3)
     assert abs(loss.item() - lo) <= 1e-3 * lo
-    # first Adam step moves every parameter by about lr * sign(g)
-    assert nrel(p.cpu().numpy() - theta, to - theta) <= 2e-2
-    assert nrel(g.cpu().numpy(), go) <= 1e-3
+    go32 = g.cpu().numpy()
+    assert_elementwise(go32, go, what="gradient")
+    # the first Adam step moves each parameter by lr * g / (|g| + eps'):
+    # lr * sign(g) wherever |g| >> eps.  Each element of the GPU step must be
+    # the Adam step of the GPU's own gradient element (FP32 arithmetic), and
+    # equal the reference's step wherever the two gradients share a sign.
+    own, _, _ = omlp.adam(theta, np.zeros_like(theta), np.zeros_like(theta), go32.astype(np.float64), 1, 1e-3)
+    step = p.cpu().numpy() - theta
+    assert_elementwise(step, own - theta, rtol=1e-4, atol=1e-4, what="Adam step of the GPU gradient")
+    same = np.sign(go32) == np.sign(go)
+    assert same.mean() > 0.99
+    assert_elementwise(step[same], (to - theta)[same], rtol=1e-2, atol=1e-3, what="Adam step")
 
 
 def smooth_states(rng, n, jump):
@@ -107,7 +136,7 @@ def test_face_flux_network_and_fallback(ops, theta):
     assert np.array_equal(used, fall)
     assert 0 < fall.sum() < n
     Fo = omlp.surrogate_flux(theta, wl[~fall], wr[~fall], bn[~fall], bf16_ops=True)
-    assert nrel(F[~fall], Fo) <= 1e-3
+    assert_elementwise(F[~fall], Fo, what="face flux")
     for i in np.flatnonzero(fall)[:40]:
         fo, _ = oracle.riemann(oracle.HLLD, wl[i], wr[i], bn[i])
         assert np.allclose(F[i], fo, rtol=2e-5, atol=2e-5 * np.abs(fo).max())
@@ -120,7 +149,7 @@ def abc_level(s, n, noise, seed):
     return s.level_from_primitives(W5, B, p["dx"])
 
 
-def test_negative_threshold_equals_hlld_bitwise(theta):
+def test_negative_threshold_equals_hlld_form(theta):
     # a negative threshold sends every face to HLLD, equal states included
     a = Solver("ctu", "ppm", "hlld", "f32")
     b = Solver("ctu", "ppm", "mlp", "f32", mlp_dp=-1.0, mlp_drho=-1.0)
@@ -134,10 +163,12 @@ def test_negative_threshold_equals_hlld_bitwise(theta):
     torch.cuda.synchronize()
     assert b.fallback_count() == 3 * 2 * 3 * 32 ** 3   # every face of both Riemann stages
     # the same HLLD source inlined into another kernel may contract its
-    # multiply-adds differently: FP32 round-off, not bits
+    # multiply-adds differently: FP32 round-off per element, not bits
     Ua, Ub = la.U.double().cpu().numpy(), lb.U.double().cpu().numpy()
     Ba, Bb = la.B.double().cpu().numpy(), lb.B.double().cpu().numpy()
-    assert nrel(Ub, Ua) <= 1e-6 and nrel(Bb, Ba) <= 1e-6
+    for m in range(5):
+        assert np.abs(Ub[m] - Ua[m]).max() <= 1e-5 * np.abs(Ua[m]).max(), m
+    assert np.abs(Bb - Ba).max() <= 1e-5 * np.abs(Ba).max()
 
 
 def test_prepare_matches_oracle_features_and_targets(ops):
@@ -244,3 +275,63 @@ def test_hlld_float_near_degenerate_faces():
         fo, _ = oracle.riemann(oracle.HLLD, wl[i], wr[i], bn[i])
         worst = max(worst, np.abs(F[i] - fo).max() / (1.0 + np.abs(fo).max()))
     assert worst <= 1e-4, worst
+
+
+def test_in_step_learned_flux_matches_oracle(theta):
+    """The network inside a step: every face of both Riemann stages of one
+    CTU step with the network active is captured with the face states the
+    kernel used and the flux it produced; the flux must equal the reference
+    surrogate on those states (HLLD where the face falls back)."""
+    n = 16
+    s = Solver("ctu", "ppm", "mlp", "f32")
+    ops = MlpOps(s)
+    ops.set_weights(dev(theta))
+    lv = abc_level(s, n, 0.1, 4)
+    nfaces = 2 * 3 * n ** 3
+    buf = torch.zeros((nfaces, 22), dtype=torch.float32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ops.set_capture(buf, count, 1)
+    s.step(lv, s.cfl_dt(lv))
+    ops.set_capture(None)
+    torch.cuda.synchronize()
+    assert int(count.item()) == nfaces
+    S = buf.cpu().numpy().astype(np.float64)
+    wl, wr, bn, F = S[:, :7], S[:, 7:14], S[:, 14], S[:, 15:]
+    fall = omlp.fallback(wl, wr)
+    assert (~fall).sum() > nfaces // 2
+    Fo = omlp.surrogate_flux(theta, wl[~fall], wr[~fall], bn[~fall], bf16_ops=True)
+    assert_elementwise(F[~fall], Fo, what="in-step network flux")
+    for i in np.flatnonzero(fall)[:40]:
+        fo, _ = oracle.riemann(oracle.HLLD, wl[i], wr[i], bn[i])
+        assert np.allclose(F[i], fo, rtol=2e-5, atol=2e-5 * np.abs(fo).max())
+
+
+def test_set_capture_drops_captured_graph():
+    """A step graph captured with capture on stops writing once capture is
+    turned off (the buffer may be released), and a capture set after a graph
+    exists is honoured."""
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s = Solver("ctu", "ppm", "hlld", "f32", stream=st)
+        ops = MlpOps(s)
+        lv = abc_level(s, 16, 0.1, 0)
+        buf = torch.zeros((1000, 22), dtype=torch.float32, device="cuda")
+        count = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ops.set_capture(buf, count, 7)
+        s.advance_graph(lv)
+        s.advance_graph(lv)
+        st.synchronize()
+        c1 = int(count.item())
+        assert c1 > 0
+        ops.set_capture(None)
+        s.advance_graph(lv)
+        s.advance_graph(lv)
+        st.synchronize()
+        assert int(count.item()) == c1
+        count2 = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ops.set_capture(buf, count2, 7)
+        s.advance_graph(lv)
+        st.synchronize()
+        assert int(count2.item()) == c1 // 2
+        ops.set_capture(None)
+        s.close()
