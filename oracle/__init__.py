@@ -67,6 +67,7 @@ def _load():
     lib.or_riemann.restype = I
     lib.or_riemann.argtypes = [I, D, P, P, D, P]
     lib.or_roe_eigen.argtypes = [D, P, P, D, P, P]
+    lib.or_ppm_edges.argtypes = [P, P, P]
     lib.or_set_threads.argtypes = [I]
     lib.or_get_threads.restype = I
     _lib = lib
@@ -202,6 +203,16 @@ def roe_eigen(wl, wr, bn, gamma: float = GAMMA):
     R = np.empty((7, 7))
     _load().or_roe_eigen(gamma, _p(wl), _p(wr), float(bn), _p(lam), _p(R))
     return lam, R
+
+
+def ppm_edges(q):
+    """PPM (limited, CW84) values at the lower and upper edge of the centre
+    cell of five consecutive cell averages q[0..4]."""
+    q = _f64(q)
+    assert q.shape == (5,)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _load().or_ppm_edges(_p(q), ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
 
 
 def initial_state(prob, gamma: float = GAMMA):

@@ -25,6 +25,7 @@ void or_u_to_w(double gam, const double* u, double bn, double* w);
 double or_fast_speed(double gam, const double* w, double bn);
 int or_riemann(int solver, double gam, const double* wl, const double* wr, double bn, double* f);
 void or_roe_eigen(double gam, const double* wl, const double* wr, double bn, double* lam, double* R);
+void or_ppm_edges(const double* q, double* qL, double* qR);
 
 /* shared between the oracle's own translation units */
 void or__primitives(int nx, int ny, int nz, double dx, double gam, const double* U, const double* B, double* W);

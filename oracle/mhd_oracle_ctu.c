@@ -12,15 +12,30 @@
  *    cell edge is the edge value minus, for every wave moving toward that
  *    edge, its share of the parabola's average over the wave's domain of
  *    dependence during dt.  With PLM the parabola is the minmod line.
+ *    With the HLL-family solvers (HLLE, HLLD), which do not resolve every
+ *    wave, waves moving away from an edge are traced too (the parabola
+ *    continued past the edge), so that both states of a face are
+ *    time-centred in every characteristic field; otherwise the jump left in
+ *    a field between a traced and an untraced state is dissipated at first
+ *    order.  Roe's solver upwinds each wave and takes waves moving toward
+ *    the edge only.
  *    The transverse field of each state then receives the multidimensional
  *    source term (dt/2) v_t dBn/dn, dBn/dn from the cell's own faces.
  *    A traced state with rho <= 0 or p <= 0 is replaced by the cell state.
  *  - Step 5: the hydrodynamic variables of each state are corrected by the
  *    transverse flux differences of step 2 over dt/2 in the cell the state
  *    comes from; its transverse field by the transverse part of the curl of
- *    the step-3 edge EMFs (averaged to the cell's faces).  Conversion to and
- *    from conserved variables uses the face's time-n normal field.  A
- *    corrected state with rho <= 0 or p <= 0 falls back to its step-1 value.
+ *    the step-3 edge EMFs (averaged to the cell's faces).  Conversion to
+ *    conserved variables uses the face's time-n normal field, conversion
+ *    back its half-step normal field (step 4), the field of the step-6
+ *    Riemann problem: the transverse energy fluxes carry the change of the
+ *    normal field's magnetic energy.  The transverse flux differences in
+ *    conserved form hold the div B terms of their own directions, -(dBt1/dt1
+ *    + dBt2/dt2) = dBn/dn times (0, B, v.B, v); the state's 1D tracing holds
+ *    none, so momentum and energy receive (dt/2)(B, v.B) dBn/dn from the
+ *    source cell's faces (the field's share is the step-1 source term).
+ *    A corrected state with rho <= 0 or p <= 0 falls back to its step-1
+ *    value.
  *  - Step 6 uses the half-step normal field of the face.
  */
 #include <math.h>
@@ -147,11 +162,15 @@ static void ppm_edges(const double q[5], double* qL, double* qR) {
   *qL = l; *qR = r;
 }
 
+/* PPM edge values of q[2] from the five cells q[0..4], exported for the
+ * unit pins of the reconstruction (no other caller) */
+void or_ppm_edges(const double* q, double* qL, double* qR) { ppm_edges(q, qL, qR); }
+
 /* Time-centred states at the two edges of cell c in direction d.
  * sl: state at the cell's lower edge (right state of its lower face);
  * sr: state at its upper edge (left state of its upper face). */
-static void traced_states(const ctu_grid* g, int recon, const double* W, const double* B, const int c[3],
-                          int d, double dt, double sl[7], double sr[7]) {
+static void traced_states(const ctu_grid* g, int recon, int all_waves, const double* W, const double* B,
+                          const int c[3], int d, double dt, double sl[7], double sr[7]) {
   size_t N = ncells(g);
   double q[5][7];
   for (int s = -2; s <= 2; ++s) w1d(W, N, idx_off(g, c, d, s), d, q[s + 2]);
@@ -185,10 +204,14 @@ static void traced_states(const ctu_grid* g, int recon, const double* W, const d
   double r = dt / g->dx;
   for (int k = 0; k < 7; ++k) {
     double xi = lam[k] * r;
-    if (xi > 0.0) {        /* moves toward the upper edge */
+    /* upper edge: the profile's average over [1 - xi, 1] (cell units); for a
+     * wave moving away (xi < 0) the parabola is continued past the edge */
+    if (xi > 0.0 || (all_waves && xi < 0.0)) {
       double amp = 0.5 * xi * (adq[k] - (1.0 - 2.0 * xi / 3.0) * aq6[k]);
       for (int m = 0; m < 7; ++m) sr[m] -= amp * R[m][k];
-    } else if (xi < 0.0) { /* moves toward the lower edge */
+    }
+    /* lower edge: the average over [0, -xi] */
+    if (xi < 0.0 || (all_waves && xi > 0.0)) {
       double ax = -xi;
       double amp = 0.5 * ax * (adq[k] + (1.0 - 2.0 * ax / 3.0) * aq6[k]);
       for (int m = 0; m < 7; ++m) sl[m] += amp * R[m][k];
@@ -205,9 +228,13 @@ static void traced_states(const ctu_grid* g, int recon, const double* W, const d
 }
 
 /* Transverse correction (step 5) of state s of direction d coming from cell c
- * and sitting on the face whose time-n normal field is bn. */
+ * and sitting on the face whose normal field is bn at time n and bnh after
+ * the half step (step 4).  The state enters conserved form with bn; the
+ * transverse energy fluxes then carry the change of the normal field's
+ * magnetic energy over dt/2, so the corrected state leaves conserved form
+ * with bnh, the field the step-6 Riemann problem uses. */
 static void correct_state(const ctu_grid* g, const double* const F[3], const double* E, const int c[3], int d,
-                          double bn, double dt, const double s[7], double out[7]) {
+                          double bn, double bnh, double dbn, double dt, const double s[7], double out[7]) {
   size_t N = ncells(g);
   double gam = g->gam;
   int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
@@ -222,6 +249,12 @@ static void correct_state(const ctu_grid* g, const double* const F[3], const dou
          0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
   size_t cc = idx3(g, c[0], c[1], c[2]);
   double hr = 0.5 * dt / g->dx;
+  /* the state's share of the multidimensional source: momentum B dBn/dn,
+   * energy (v.B) dBn/dn over dt/2, dbn = the source cell's normal-field
+   * difference (its transverse-field share is in the traced state) */
+  double vb = v[0] * b[0] + v[1] * b[1] + v[2] * b[2];
+  for (int a = 0; a < 3; ++a) u[1 + a] += hr * dbn * b[a];
+  u[4] += hr * dbn * vb;
   for (int tt = 0; tt < 2; ++tt) {
     int t = tt ? t2 : t1;
     size_t cp = idx_off(g, c, t, 1);
@@ -247,7 +280,8 @@ static void correct_state(const ctu_grid* g, const double* const F[3], const dou
     double sign = (d == (bax + 1) % 3) ? 1.0 : -1.0;
     b[bax] += 0.5 * dt * sign * dEd;
   }
-  /* back to primitives with the same normal field */
+  /* back to primitives with the half-step normal field */
+  b[d] = bnh;
   double w[7];
   w[0] = u[0];
   double vx = u[1] / u[0], vy = u[2] / u[0], vz = u[3] / u[0];
@@ -307,7 +341,7 @@ int or_ctu_step_impl(int nx, int ny, int nz, double dx, double gam, int recon, i
         for (int i = 0; i < nx; ++i) {
           int c[3] = {i, j, k};
           double sl[7], sr[7];
-          traced_states(&g, recon, W, B, c, d, dt, sl, sr);
+          traced_states(&g, recon, solver != OR_ROE, W, B, c, d, dt, sl, sr);
           size_t lo = idx3(&g, i, j, k), hi = idx_off(&g, c, d, 1);
           for (int m = 0; m < 7; ++m) {
             QR[((size_t)d * 7 + m) * N + lo] = sl[m];
@@ -351,8 +385,9 @@ int or_ctu_step_impl(int nx, int ny, int nz, double dx, double gam, int recon, i
             sr[m] = QR[((size_t)d * 7 + m) * N + p];
           }
           double bn = B[d * N + p];
-          correct_state(&g, Fsc, Es, cl, d, bn, dt, sl, wl);
-          correct_state(&g, Fsc, Es, c, d, bn, dt, sr, wr);
+          double bn_lo = B[d * N + idx_off(&g, c, d, -1)], bn_hi = B[d * N + idx_off(&g, c, d, 1)];
+          correct_state(&g, Fsc, Es, cl, d, bn, Bh[d * N + p], bn - bn_lo, dt, sl, wl);
+          correct_state(&g, Fsc, Es, c, d, bn, Bh[d * N + p], bn_hi - bn, dt, sr, wr);
           fbd += or__riemann(solver, wl, wr, Bh[d * N + p], gam, f);
           store_flux(Fc[d], N, p, d, f);
         }

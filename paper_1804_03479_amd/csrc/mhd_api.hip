@@ -336,7 +336,9 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
     k_prim<T, false, MIX, L><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   }
   mark(1);
-  k_ctu_states<T, R, L><<<sblocks(wq), kBlock, 0, st>>>(wq, W, B, QL, QR, dts, inv_dx, gam);
+  // the HLL-family solvers (HLLE, HLLD, the learned flux standing in for
+  // HLLD) take every wave in the tracing, Roe only those moving toward an edge
+  k_ctu_states<T, R, S != 0, L><<<sblocks(wq), kBlock, 0, st>>>(wq, W, B, QL, QR, dts, inv_dx, gam);
   mark(2);
   constexpr bool kMlp = S == 3 && std::is_same<T, float>::value;
   const float dp = (float)c->cfg.mlp_dp, drho = (float)c->cfg.mlp_drho;
@@ -359,13 +361,13 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
   if constexpr (kMlp) {
     float* Qc = (float*)c->Qc;
     const unsigned nb = sblocks(wf2);
-    k_ctu_correct_dir<0, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
+    k_ctu_correct_dir<0, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
     k_flux_dir_mlp<0, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
                                                   c->capture);
-    k_ctu_correct_dir<1, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
+    k_ctu_correct_dir<1, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
     k_flux_dir_mlp<1, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
                                                   c->capture);
-    k_ctu_correct_dir<2, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Qc, dts, inv_dx, gam);
+    k_ctu_correct_dir<2, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
     k_flux_dir_mlp<2, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
                                                   c->capture);
   } else

@@ -409,10 +409,13 @@ __device__ __forceinline__ void ppm_edges(T q0, T q1, T q2, T q3, T q4, T& ql, T
 // (bn_lo, bn_hi) the cell's two normal-face fields.  Each edge state starts
 // at the reconstructed edge value; every wave moving toward that edge
 // subtracts its share of the profile's average over its domain of dependence
-// during dt (xi = lam dt/dx).  RECON: 0 minmod PLM, 1 PPM.  Then the
+// during dt (xi = lam dt/dx).  ALLW (the HLL-family solvers, which do not
+// resolve every wave): waves moving away are traced as well, with the
+// profile continued past the edge, so both states of a face are
+// time-centred in every field.  RECON: 0 minmod PLM, 1 PPM.  Then the
 // transverse field gets (dt/2) v_t dBn/dn.  A non-physical result falls back
 // to the cell state.  sl: lower edge, sr: upper edge.
-template <typename T, int RECON>
+template <typename T, int RECON, bool ALLW>
 __device__ __forceinline__ void trace_cell(const T q[5][7], T bn_lo, T bn_hi, T dtdx, T gam, T sl[7],
                                            T sr[7]) {
   T dq[7], q6[7];
@@ -472,12 +475,13 @@ __device__ __forceinline__ void trace_cell(const T q[5][7], T bn_lo, T bn_hi, T 
   const T xv_d = b2 * dq[3] - b3 * dq[2], xb_d = b2 * dq[6] - b3 * dq[5];
   const T pv_6 = b2 * q6[2] + b3 * q6[3], pb_6 = b2 * q6[5] + b3 * q6[6];
   const T xv_6 = b2 * q6[3] - b3 * q6[2], xb_6 = b2 * q6[6] - b3 * q6[5];
-  // amplitudes toward the upper (R) and lower (L) edge of a wave with
-  // xi = lam dt/dx and projections (ad, a6); zero for waves moving away
+  // amplitudes at the upper (R) and lower (L) edge of a wave with
+  // xi = lam dt/dx and projections (ad, a6): zero for waves moving away,
+  // or (ALLW) the profile continued past the edge for them too
   auto amps = [&](T lam, T ad, T a6, T& aR, T& aL) {
     const T xi = lam * dtdx;
-    aR = T(0.5) * dmax(xi, T(0)) * (ad - (T(1) - T(2.0 / 3.0) * xi) * a6);
-    aL = T(0.5) * dmax(-xi, T(0)) * (ad + (T(1) + T(2.0 / 3.0) * xi) * a6);
+    aR = T(0.5) * (ALLW ? xi : dmax(xi, T(0))) * (ad - (T(1) - T(2.0 / 3.0) * xi) * a6);
+    aL = T(0.5) * (ALLW ? -xi : dmax(-xi, T(0))) * (ad + (T(1) + T(2.0 / 3.0) * xi) * a6);
   };
   // a wave pair (lam -+ c): returns the sums and differences of the amplitudes
   auto pair = [&](T c, T s_d, T a_d, T s_6, T a_6, T& sR, T& dR, T& sL, T& dL) {

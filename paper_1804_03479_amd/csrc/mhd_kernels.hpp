@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* 
 // direction.  Face-indexed outputs: QR[d][m][p] is the state above the lower
 // d-face of cell p (from cell p), QL[d][m][p] the state below it (from the
 // cell p - e_d; written by that cell as its upper-edge state).
-template <typename T, int D, int RECON, bool L>
+template <typename T, int D, int RECON, bool ALLW, bool L>
 __device__ __forceinline__ void cell_states(const Work& w, const T* __restrict__ W, const T* __restrict__ B,
                                             T* __restrict__ QL, T* __restrict__ QR, const Site& st, T dtdx,
                                             T gam) {
@@ -598,7 +598,7 @@ __device__ __forceinline__ void cell_states(const Work& w, const T* __restrict__
   const long long pu = nbr(w, st.i, st.j, st.k, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0);
   const long long su = snb<L>(w, st, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0);
   T sl[7], sr[7];
-  trace_cell<T, RECON>(q, B[D * N + st.p], B[D * N + pu], dtdx, gam, sl, sr);
+  trace_cell<T, RECON, ALLW>(q, B[D * N + st.p], B[D * N + pu], dtdx, gam, sl, sr);
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
     QR[((long long)D * 7 + m) * NS + st.s] = sl[m];
@@ -606,16 +606,17 @@ __device__ __forceinline__ void cell_states(const Work& w, const T* __restrict__
   }
 }
 
-template <typename T, int RECON, bool L>
+// ALLW: trace waves moving away from an edge too (HLL-family solvers)
+template <typename T, int RECON, bool ALLW, bool L>
 __global__ void __launch_bounds__(kBlock) k_ctu_states(Work w, const T* __restrict__ W, const T* __restrict__ B,
                                                        T* __restrict__ QL, T* __restrict__ QR, DtSrc dts,
                                                        T inv_dx, T gam) {
   const T dtdx = T(get_dt(dts)) * inv_dx;
   FOR_ITEMS(w, t) {
     const Site st = site_of<L>(w, t);
-    cell_states<T, 0, RECON, L>(w, W, B, QL, QR, st, dtdx, gam);
-    cell_states<T, 1, RECON, L>(w, W, B, QL, QR, st, dtdx, gam);
-    cell_states<T, 2, RECON, L>(w, W, B, QL, QR, st, dtdx, gam);
+    cell_states<T, 0, RECON, ALLW, L>(w, W, B, QL, QR, st, dtdx, gam);
+    cell_states<T, 1, RECON, ALLW, L>(w, W, B, QL, QR, st, dtdx, gam);
+    cell_states<T, 2, RECON, ALLW, L>(w, W, B, QL, QR, st, dtdx, gam);
   }
 }
 
@@ -661,14 +662,21 @@ __global__ void __launch_bounds__(kBlock) k_flux_q(Work w, const T* __restrict__
 }
 
 // Step 5: transverse correction of a state of direction D that comes from
-// cell (ci, cj, ck) and sits on a face with time-n normal field bn.  Hydro
-// variables: minus dt/2 times the transverse flux differences of step 2 in
-// that cell.  Transverse field: dt/2 times the transverse part of -curl E
-// with the step-3 edge EMFs E_D averaged to the cell's faces.  The normal
-// field of the conversion is kept.  Non-physical results keep the input.
+// cell (ci, cj, ck) and sits on a face with normal field bn at time n and bnh
+// after the half step.  Hydro variables: minus dt/2 times the transverse flux
+// differences of step 2 in that cell.  Transverse field: dt/2 times the
+// transverse part of -curl E with the step-3 edge EMFs E_D averaged to the
+// cell's faces.  The state enters conserved form with bn and leaves it with
+// bnh (the transverse energy fluxes carry the normal field's change of
+// magnetic energy).  The conserved transverse flux differences hold the
+// div B terms of their directions, dBn/dn (0, B, v.B, v): momentum and
+// energy get (dt/2)(B, v.B) dBn/dn with dbn the source cell's normal-field
+// difference (the field's share is in the traced state).  Non-physical
+// results keep the input.
 template <typename T, int D, bool L>
 __device__ __forceinline__ void correct_state(const Work& w, const T* __restrict__ F1, const T* __restrict__ E1,
-                                              const Site& src, T bn, T hr, T gam, const T s[7], T out[7]) {
+                                              const Site& src, T bn, T bnh, T dbn, T hr, T gam, const T s[7],
+                                              T out[7]) {
   constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
   const long long N = w.NS;
   T v[3], b[3];
@@ -681,6 +689,10 @@ __device__ __forceinline__ void correct_state(const Work& w, const T* __restrict
   u[3] = s[0] * v[2];
   u[4] = s[4] / (gam - T(1)) + T(0.5) * s[0] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) +
          T(0.5) * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  const T vb = v[0] * b[0] + v[1] * b[1] + v[2] * b[2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[1 + a] += hr * dbn * b[a];
+  u[4] += hr * dbn * vb;
   const long long c = src.s;
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt) {
@@ -703,6 +715,7 @@ __device__ __forceinline__ void correct_state(const Work& w, const T* __restrict
     const T sign = (D == (bax + 1) % 3) ? T(1) : T(-1);
     b[bax] += hr * sign * (up - lo);
   }
+  b[D] = bnh;
   const T id = T(1) / u[0];
   const T vx = u[1] * id, vy = u[2] * id, vz = u[3] * id;
   const T pr = (gam - T(1)) * (u[4] - T(0.5) * u[0] * (vx * vx + vy * vy + vz * vz) -
@@ -719,8 +732,8 @@ __device__ __forceinline__ void correct_state(const Work& w, const T* __restrict
 template <typename T, int D, bool L>
 __device__ __forceinline__ void corrected_states(const Work& w, const T* __restrict__ QL, const T* __restrict__ QR,
                                                  const T* __restrict__ F1, const T* __restrict__ E1,
-                                                 const T* __restrict__ B, const Site& st, T hr, T gam, T wl[7],
-                                                 T wr[7]) {
+                                                 const T* __restrict__ B, T bnh, const Site& st, T hr, T gam,
+                                                 T wl[7], T wr[7]) {
   const long long NS = w.NS;
   T sl[7], sr[7];
 #pragma unroll
@@ -729,8 +742,11 @@ __device__ __forceinline__ void corrected_states(const Work& w, const T* __restr
     sr[m] = QR[((long long)D * 7 + m) * NS + st.s];
   }
   const T bn = B[D * w.N + st.p];
-  correct_state<T, D, L>(w, F1, E1, site_nb<L>(w, st, -(D == 0), -(D == 1), -(D == 2)), bn, hr, gam, sl, wl);
-  correct_state<T, D, L>(w, F1, E1, st, bn, hr, gam, sr, wr);
+  const T bn_lo = B[D * w.N + nbr(w, st.i, st.j, st.k, -(D == 0), -(D == 1), -(D == 2))];
+  const T bn_hi = B[D * w.N + nbr(w, st.i, st.j, st.k, D == 0, D == 1, D == 2)];
+  correct_state<T, D, L>(w, F1, E1, site_nb<L>(w, st, -(D == 0), -(D == 1), -(D == 2)), bn, bnh, bn - bn_lo, hr,
+                         gam, sl, wl);
+  correct_state<T, D, L>(w, F1, E1, st, bn, bnh, bn_hi - bn, hr, gam, sr, wr);
 }
 
 template <typename T, int D, int SOLVER, bool L>
@@ -741,8 +757,8 @@ __device__ __forceinline__ int corrected_face_flux(const Work& w, const T* __res
                                                    const Capture& cp) {
   const long long NS = w.NS;
   T wl[7], wr[7], f[7];
-  corrected_states<T, D, L>(w, QL, QR, F1, E1, B, st, hr, gam, wl, wr);
   const T bn = Bh[D * NS + st.s];
+  corrected_states<T, D, L>(w, QL, QR, F1, E1, B, bn, st, hr, gam, wl, wr);
   const int fb = riemann<SOLVER>(wl, wr, bn, gam, f);
   if constexpr (sizeof(T) == 4) capture_face(cp, 3 * st.p + D, wl, wr, bn, f);
   store_flux<T, D>(F2, NS, st.s, f);
@@ -775,14 +791,14 @@ template <int D, bool L>
 __global__ void __launch_bounds__(kBlock) k_ctu_correct_dir(Work w, const float* __restrict__ QL,
                                                             const float* __restrict__ QR, const float* __restrict__ F1,
                                                             const float* __restrict__ E1, const float* __restrict__ B,
-                                                            float* __restrict__ Qc, DtSrc dts, float inv_dx,
-                                                            float gam) {
+                                                            const float* __restrict__ Bh, float* __restrict__ Qc,
+                                                            DtSrc dts, float inv_dx, float gam) {
   const float hr = float(0.5 * get_dt(dts)) * inv_dx;
   const long long NS = w.NS;
   FOR_ITEMS(w, t) {
     const Site st = site_of<L>(w, t);
     float wl[7], wr[7];
-    corrected_states<float, D, L>(w, QL, QR, F1, E1, B, st, hr, gam, wl, wr);
+    corrected_states<float, D, L>(w, QL, QR, F1, E1, B, Bh[D * NS + st.s], st, hr, gam, wl, wr);
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
       Qc[(long long)m * NS + st.s] = wl[m];

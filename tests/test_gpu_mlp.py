@@ -22,6 +22,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
+from flip_mask import check_outside, sensitive_mask  # noqa: E402
 from oracle import mlp as omlp  # noqa: E402
 from paper_1804_03479_amd import inputs  # noqa: E402
 from paper_1804_03479_amd import surrogate  # noqa: E402
@@ -156,19 +157,32 @@ def test_negative_threshold_equals_hlld_form(theta):
     MlpOps(b).set_weights(dev(theta))
     la, lb = abc_level(a, 32, 0.1, 0), abc_level(b, 32, 0.1, 0)
     b.fallback_count()
+    dts = []
     for _ in range(3):
         dt = a.cfl_dt(la)
+        dts.append(dt)
         a.step(la, dt)
         b.step(lb, dt)
     torch.cuda.synchronize()
     assert b.fallback_count() == 3 * 2 * 3 * 32 ** 3   # every face of both Riemann stages
-    # the same HLLD source inlined into another kernel may contract its
-    # multiply-adds differently: FP32 round-off per element, not bits
+    # The same HLLD source inlined into another kernel may contract its
+    # multiply-adds differently: FP32 round-off per value, not bits, except
+    # next to a discontinuous decision (PPM extremum test, EMF upwind
+    # choice) within float rounding of its switch, which the two kernels may
+    # take differently.  Those values are the oracle's flip set of the same
+    # three steps; the per-value bar holds everywhere else.
     Ua, Ub = la.U.double().cpu().numpy(), lb.U.double().cpu().numpy()
     Ba, Bb = la.B.double().cpu().numpy(), lb.B.double().cpu().numpy()
-    for m in range(5):
-        assert np.abs(Ub[m] - Ua[m]).max() <= 1e-5 * np.abs(Ua[m]).max(), m
-    assert np.abs(Bb - Ba).max() <= 1e-5 * np.abs(Ba).max()
+    p = inputs.abc_problem(32, 0.1, seed=0)
+    U0, B0 = oracle.initial_state(p)
+    U0, B0 = U0.astype(np.float32).astype(np.float64), B0.astype(np.float32).astype(np.float64)
+
+    def run(u, b):
+        for dt in dts:
+            u, b = oracle.step(u, b, dt, p["dx"], scheme=oracle.CTU, recon=oracle.PPM, riemann=oracle.HLLD)
+        return u, b
+    mu, mb, su, sb = sensitive_mask(run, U0, B0)
+    check_outside(Ub, Bb, Ua, Ba, mu, mb, su, sb, what="learned-flux form at threshold < 0 vs HLLD form, 3 steps")
 
 
 def test_prepare_matches_oracle_features_and_targets(ops):

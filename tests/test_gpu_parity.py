@@ -2,7 +2,12 @@
 
 Bars: FP64 results within 1e-12 relative (per component, infinity norm over
 the grid divided by the component's infinity norm), FP32 within 1e-5 per
-step, integer decisions (solver fallbacks, non-physical flags) identical.
+step and per value (momentum against the flow's momentum scale), integer
+decisions (solver fallbacks, non-physical flags) identical.  On inputs with
+cell-scale noise the FP32 bar is held at every value outside the set where
+a float-rounding perturbation moves the oracle's own result past the bar
+(a discontinuous decision within rounding of its switch: tests/flip_mask.py);
+that set is counted and bounded.
 """
 import numpy as np
 import pytest
@@ -14,6 +19,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
+from flip_mask import check_outside, sensitive_mask  # noqa: E402
 from paper_1804_03479_amd import inputs  # noqa: E402
 from paper_1804_03479_amd.mhd import Level, MHDError, Solver  # noqa: E402
 
@@ -143,14 +149,18 @@ def test_one_step_f32_smooth(solver):
 
 @pytest.mark.parametrize("solver", sorted(SOLVERS))
 def test_one_step_f32(solver):
-    # cell-scale noise: a minmod or upwind decision within FP32 rounding of
-    # its switch may flip and move one face value by a slope-sized amount,
-    # so the bar is stated in L1, with a loose infinity-norm guard
-    Ug, Bg, Uo, Bo, dt, dx = vl_f32_step(inputs.abc_problem(32, 0.01, seed=1), solver)
+    # cell-scale noise: an upwind decision within FP32 rounding of its switch
+    # may flip and move nearby values by a slope-sized amount; the per-value
+    # bar holds outside the oracle's own flip set, which stays small
+    p = inputs.abc_problem(32, 0.01, seed=1)
+    Ug, Bg, Uo, Bo, dt, dx = vl_f32_step(p, solver)
+    U, B = oracle.initial_state(p)
+    U = U.astype(np.float32).astype(np.float64)
+    B = B.astype(np.float32).astype(np.float64)
+    mu, mb, su, sb = sensitive_mask(lambda u, b: oracle.step(u, b, dt, dx, riemann=SOLVERS[solver]), U, B)
+    check_outside(Ug, Bg, Uo, Bo, mu, mb, su, sb, what=f"VL+PLM+{solver} FP32, 32^3 ABC noise 0.01")
     assert l1_rel(Ug, Uo) <= 1e-5
     assert l1_rel(Bg, Bo) <= 1e-5
-    assert rel_err_f32(Ug, Uo, dt, dx) <= 1e-3
-    assert rel_err(Bg, Bo) <= 1e-3
 
 
 def test_diagnostics_parity():
@@ -354,15 +364,22 @@ def test_ctu_one_step_f32_smooth(solver):
 
 @pytest.mark.parametrize("solver", ["hlld", "roe"])
 def test_ctu_one_step_f32_noisy_abc(solver):
-    # cell-scale noise puts some of PPM's discontinuous extremum tests within
-    # FP32 rounding of their threshold; a flipped decision moves one edge
-    # value by a slope-sized amount, so the bar is stated in L1, with a loose
-    # infinity-norm guard
-    Ug, Bg, Uo, Bo, dt, dx = ctu_f32_step(inputs.abc_problem(32, 0.1, seed=1), solver)
+    # cell-scale noise puts some of PPM's discontinuous extremum tests and
+    # EMF upwind choices within FP32 rounding of their switch; a flipped
+    # decision moves nearby values by a slope-sized amount.  The per-value
+    # bar holds outside the oracle's own flip set, which stays small.
+    p = inputs.abc_problem(32, 0.1, seed=1)
+    Ug, Bg, Uo, Bo, dt, dx = ctu_f32_step(p, solver)
+    U, B = oracle.initial_state(p)
+    U = U.astype(np.float32).astype(np.float64)
+    B = B.astype(np.float32).astype(np.float64)
+
+    def run(u, b):
+        return oracle.step(u, b, dt, dx, scheme=oracle.CTU, recon=oracle.PPM, riemann=SOLVERS[solver])
+    mu, mb, su, sb = sensitive_mask(run, U, B)
+    check_outside(Ug, Bg, Uo, Bo, mu, mb, su, sb, what=f"CTU+PPM+{solver} FP32, 32^3 ABC noise 0.1")
     assert l1_rel(Ug, Uo) <= 1e-5
     assert l1_rel(Bg, Bo) <= 1e-5
-    assert rel_err_f32(Ug, Uo, dt, dx) <= 1e-3
-    assert rel_err(Bg, Bo) <= 1e-3
 
 
 def test_ctu_group_list_subset():

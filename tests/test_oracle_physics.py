@@ -227,13 +227,19 @@ def test_ctu_divergence_unchanged_for_any_face_field(orc):
     assert np.abs(orc.divb(B1, dx) - d0).max() * dx < 1e-13
 
 
-@pytest.mark.parametrize("wave", ["alfven", "slow"])
-def test_ctu_linear_wave_second_order_unlimited(orc, wave):
-    # unlimited fourth-order PPM edges isolate the integrator's order (the
-    # transverse corrections of CTU step 5 included)
-    e8 = ctu_wave_l1(orc, 8, wave, 4, 2)
-    e16 = ctu_wave_l1(orc, 16, wave, 4, 2)
-    assert e16 < e8 / 3.8
+@pytest.mark.parametrize("wave, solver", [("fast", 2), ("alfven", 2), ("slow", 2), ("slow", 0)])
+def test_ctu_linear_wave_second_order_unlimited(orc, wave, solver):
+    # Unlimited fourth-order PPM edges isolate the integrator's order (the
+    # transverse corrections of CTU step 5 included).  At 16 -> 32 cells each
+    # first-order inconsistency of the CTU states shows (measured ratios):
+    # corrected states converted back with the time-n normal field instead of
+    # the half-step one (Alfven 3.2, 2.4 at 32 -> 64); no momentum and energy
+    # div B source in the transverse correction (slow 2.9 HLLD, 2.4 Roe);
+    # HLLD with waves moving away from an edge left untraced (1D slow wave
+    # 2.0).  With all three: 4.1 - 4.7.
+    e16 = ctu_wave_l1(orc, 16, wave, 4, solver)
+    e32 = ctu_wave_l1(orc, 32, wave, 4, solver)
+    assert e32 < e16 / 3.8, (e16, e32)
 
 
 @pytest.mark.parametrize("wave", ["fast", "alfven", "slow"])
