@@ -41,9 +41,19 @@ PAPER_F64 = 5.5e7   # same, FP64
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK = 2500.0                          # TFLOP/s, dense BF16
 MLP_FLOP_PER_FACE = 2 * (15 * 64 + 64 * 64 + 64 * 7)   # one 15-64-64-7 inference
+# Vector ALU issue ceiling in wave64 instructions per second: the FP32 vector
+# peak 157.3 TFLOP/s is 256 CUs x 2.4 GHz x 256 FLOP per clock, i.e. two
+# 64-lane FMA instructions (128 FLOP each) per clock per CU; FP64 (78.6
+# TFLOP/s) one.  Every counted VALU instruction takes one such slot.
+VALU_PEAK_WAVE_INSTR = {4: 157.3e12 / 128.0, 8: 78.6e12 / 128.0}
 
-# Algorithmic words per cell of each stage kernel: every array element the
-# stage must read or write, counted once (neighbour re-reads excluded).
+# The words that define a cell update (Sec. 5.2 counts cell updates): the
+# 5 conserved values and 3 face fields of a cell read once and written once.
+CELL_UPDATE_WORDS = 16
+
+# Scratch words per cell of each stage kernel: every array element the stage
+# reads or writes, intermediates included, counted once (neighbour re-reads
+# excluded).  Implementation traffic of the stage split, not algorithmic.
 STAGE_WORDS = {
     "prim": 8 + 8,                        # U(5) + B(3) in, W(8) out
     "states": 8 + 3 + 42,                 # W, B in; QL, QR (2 x 3 x 7) out
@@ -426,29 +436,56 @@ def l1_vs_oracle(wl: dict, n: int, seed: int, nsteps: int, precs):
     return out, t_cpu
 
 
-def measured_traffic(workload: str, kernel: str):
-    """Counter-measured HBM bytes per launch of a stage (profiles/hbm_traffic.json),
-    or None when the kernel sources changed since the counters were taken."""
+def counter_record(name: str, workload: str, prec: str):
+    """A committed counter summary (profiles/<name>.json) of this workload and
+    precision, or None when the kernel sources changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()
     for s in rec["sources"]:
         h.update(open(os.path.join(ROOT, s), "rb").read())
-    if h.hexdigest() != rec["sources_sha256"] or rec["workload"] != workload:
+    if h.hexdigest() != rec["sources_sha256"] or rec["workload"] != workload or rec.get("prec") != prec:
         return None
-    return rec["bytes_per_launch"].get(kernel)
+    return rec
 
 
-def roofline_of(stages: dict, words: dict, elem: int, cells: int, workload: str) -> dict:
+def roofline_of(stages: dict, step_ms: float, words: dict, elem: int, cells: int, workload: str, prec: str) -> dict:
+    """HBM roofline of the dominant stage kernel (live hipEvent times on the
+    library's stream): algorithmic bytes = 16 words per cell update x cells
+    per launch; beside it the whole step at the same bytes, the stage's
+    scratch traffic, the counter-measured traffic and the VALU issue rate."""
     dom = max(stages, key=stages.get)
-    bytes_launch = words[dom] * elem * cells
-    achieved = bytes_launch / (stages[dom] * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, dom),
-            "stage_ms": {k: round(v, 4) for k, v in stages.items()}, "bytes_per_launch": bytes_launch}
+    alg = CELL_UPDATE_WORDS * elem * cells
+    achieved = alg / (stages[dom] * 1e-3) / 1e9
+    step_rate = alg / (step_ms * 1e-3) / 1e9
+    scratch = words[dom] * elem * cells
+    hbm = counter_record("hbm_traffic", workload, prec)
+    valu = counter_record("valu_counters", workload, prec)
+    out = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": None if hbm is None else hbm["bytes_per_launch"].get(dom),
+           "algorithmic_bytes_per_launch": alg,
+           "step": {"achieved": round(step_rate, 1), "frac": round(step_rate / HBM_PEAK_GBS, 4),
+                    "ms": round(step_ms, 4)},
+           "scratch": {"words_per_cell": words[dom], "bytes_per_launch": scratch,
+                       "achieved": round(scratch / (stages[dom] * 1e-3) / 1e9, 1)},
+           "stage_ms": {k: round(v, 4) for k, v in stages.items()}}
+    if valu is not None:
+        peak = VALU_PEAK_WAVE_INSTR[elem]
+        per = {}
+        for k, n_instr in valu["wave_instructions_per_launch"].items():
+            if k in stages:
+                r = n_instr / (stages[k] * 1e-3)
+                per[k] = {"wave_instructions": n_instr, "rate": round(r, 0), "frac": round(r / peak, 4)}
+        out["valu"] = {"kernel": dom, "frac": per.get(dom, {}).get("frac"), "peak_wave_instr_per_s": peak,
+                       "step_frac": round(sum(v["wave_instructions"] for v in per.values()) / (step_ms * 1e-3) / peak, 4),
+                       "per_stage": per, "summary": valu.get("summary")}
+    else:
+        out["valu"] = None
+    return out
 
 
 def main():
@@ -609,7 +646,8 @@ def main():
         return
     head = results[head_key]["f32"]
     words = CTU_WORDS if head_key == "ctu" else STAGE_WORDS
-    roofline = roofline_of(head["stages"], words, 4, cells, WORKLOADS[head_key]["name"].format(n=n))
+    roofline = roofline_of(head["stages"], head["ms_per_step"], words, 4, cells,
+                           WORKLOADS[head_key]["name"].format(n=n), "f32")
     wl = WORKLOADS[head_key]
     line = {
         "metric": "cell-updates/s/GPU: FP64 vs FP32 vs MLP-flux at fixed L1 err; HBM GB/s",
