@@ -48,6 +48,10 @@ extern "C" {
 #define MHD_ERR_NONPHYSICAL -5
 #define MHD_ERR_NO_DEVICE -6
 #define MHD_ERR_OUT_OF_MEMORY -7
+#define MHD_ERR_SCRATCH_LIMIT -8   /* mhd_step_noalloc: the level needs more than MHD_NOALLOC_SCRATCH_BYTES */
+
+/* size of the static stage scratch of mhd_step_noalloc, per device */
+#define MHD_NOALLOC_SCRATCH_BYTES (64ull << 20)
 
 /* unsplit integrators, paper Sec. 3.2 */
 enum { MHD_VL = 0, MHD_CTU = 1 };
@@ -135,6 +139,23 @@ int mhd_step(mhd_ctx ctx, const mhd_level* lv, double dt);
 
 /* Same, with dt read from device memory at run time (graph-capturable). */
 int mhd_step_devdt(mhd_ctx ctx, const mhd_level* lv, const double* dt_dev);
+
+/* mhd_step_devdt for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the stage scratch taken from a static
+ * device array of MHD_NOALLOC_SCRATCH_BYTES (64 MiB) that each device holds
+ * from its first mhd_init until the process ends; no hipMalloc, hipFree or
+ * allocating library call.  A level whose scratch (mhd_workspace_bytes)
+ * exceeds the array returns MHD_ERR_SCRATCH_LIMIT before any HIP call: e.g.
+ * FP32 CTU up to about 171k cells (48^3), FP64 VL up to about 240k (32^3
+ * and beyond).  Every call on a device shares that device's array, which
+ * keeps the last call's contents (each step writes every scratch value it
+ * reads; the group occupancy map is cleared by a kernel): calls that
+ * overlap on one device race, so serialise them, e.g. on one stream.  The
+ * fluxes and EMFs stay in the static array, so mhd_correct and
+ * mhd_accumulate_registers (which read the context's scratch) do not follow
+ * this step. */
+int mhd_step_noalloc(mhd_ctx ctx, const mhd_level* lv, const double* dt_dev);
 
 /* CFL step plus update in one call, with no host synchronisation: computes
  * dt from the current state on the device, writes it to dt_dev (device,

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -25,6 +26,13 @@
 #include "mhd_amr.hpp"
 
 using namespace mhd;
+
+// Stage scratch of mhd_step_noalloc: a file-scope device array, one copy per
+// device, held until the process ends.  Host code never passes its name to a
+// kernel (on the host it is a stand-in, not a device address): mhd_init looks
+// up this device's address once with hipGetSymbolAddress and every use goes
+// through that pointer.
+static __device__ __align__(256) unsigned char scratch[MHD_NOALLOC_SCRATCH_BYTES];
 
 struct mhd_ctx_s {
   mhd_config cfg;
@@ -68,6 +76,7 @@ struct mhd_ctx_s {
   mhd_level graph_key;
   double* graph_dt;
   double* graph_t;
+  unsigned char* static_scratch;   // this device's copy of the file-scope scratch array
 };
 
 namespace {
@@ -206,10 +215,25 @@ Work stage_work(const mhd_level* lv, int lo, int hi, int ghost) {
   return w;
 }
 
+// groups of a level's occupancy map (list mode)
+long long occupancy_cells(const mhd_level* lv) {
+  return (long long)(lv->nx / lv->group_edge) * (lv->ny / lv->group_edge) * (lv->nz / lv->group_edge);
+}
+
+// fill an occupancy map of occupancy_cells(lv) ints (list mode only): clear
+// with a kernel, then mark the listed groups
+void fill_occupancy(mhd_ctx_s* c, const mhd_level* lv, int* occ) {
+  const long long ng = occupancy_cells(lv);
+  k_occ_clear<<<(unsigned)((ng + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(occ, ng);
+  k_occ_set<<<(unsigned)((lv->n_groups + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+      occ, lv->groups, lv->n_groups, lv->n_groups_dev, lv->group_edge, lv->nx / lv->group_edge,
+      lv->ny / lv->group_edge, lv->nz / lv->group_edge);
+}
+
 // occupancy map of a level's group list (list mode only) into *occ
 int build_occupancy_into(mhd_ctx_s* c, const mhd_level* lv, int** occ, long long* cap) {
   if (!lv->groups || lv->n_groups <= 0) return MHD_OK;
-  const long long ng = (long long)(lv->nx / lv->group_edge) * (lv->ny / lv->group_edge) * (lv->nz / lv->group_edge);
+  const long long ng = occupancy_cells(lv);
   if (ng > *cap) {
     hipFree(*occ);
     *occ = nullptr;
@@ -217,10 +241,7 @@ int build_occupancy_into(mhd_ctx_s* c, const mhd_level* lv, int** occ, long long
     if (hipMalloc(occ, ng * sizeof(int)) != hipSuccess) return MHD_ERR_OUT_OF_MEMORY;
     *cap = ng;
   }
-  k_occ_clear<<<(unsigned)((ng + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(*occ, ng);
-  k_occ_set<<<(unsigned)((lv->n_groups + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-      *occ, lv->groups, lv->n_groups, lv->n_groups_dev, lv->group_edge, lv->nx / lv->group_edge,
-      lv->ny / lv->group_edge, lv->nz / lv->group_edge);
+  fill_occupancy(c, lv, *occ);
   return MHD_OK;
 }
 
@@ -250,24 +271,35 @@ const char* stage_name(const mhd_ctx_s* c, int s) {
   return c->cfg.scheme == MHD_CTU ? kStageNamesCTU[s] : kStageNamesVL[s];
 }
 
+// Stage scratch of one step: the context's (allocated on demand) or carved
+// from the static array of the allocation-free entry point.
+struct StepBufs {
+  void *W, *Bh, *F, *E, *QL, *QR, *F2, *Qc;
+  int* occ;
+};
+
+StepBufs ctx_bufs(const mhd_ctx_s* c) {
+  return StepBufs{c->W, c->Bh, c->F, c->E, c->QL, c->QR, c->F2, c->Qc, c->occ};
+}
+
 // ev (optional): kNumStages + 1 events recorded around the stage kernels
 template <typename T, int S, bool MIX, bool L>
-void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
+void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev, const StepBufs& sb) {
   const Mix mix{MIX ? lv->E64 : nullptr, c->cfg.beta_fp64};
   hipStream_t st = c->stream;
   T* U = (T*)lv->U;
   T* B = (T*)lv->B;
-  T* W = (T*)c->W;
-  T* Bh = (T*)c->Bh;
-  T* F = (T*)c->F;
-  T* E = (T*)c->E;
+  T* W = (T*)sb.W;
+  T* Bh = (T*)sb.Bh;
+  T* F = (T*)sb.F;
+  T* E = (T*)sb.E;
   const T gam = (T)c->cfg.gamma;
   const T inv_dx = (T)(1.0 / lv->dx);
   constexpr int G = 3;   // ghost cells of VL + PLM
   const Work wp = stage_work(lv, 3, 3, G), wf1 = stage_work(lv, 3, 3, G), we1 = stage_work(lv, 2, 3, G);
   const Work wh = stage_work(lv, 2, 2, G), wf2 = stage_work(lv, 1, 1, G), we2 = stage_work(lv, 0, 1, G);
   Work wu = stage_work(lv, 0, 0, G);
-  wu.occ = c->occ;
+  wu.occ = sb.occ;
   auto mark = [&](int s) {
     if (ev) (void)hipEventRecord(ev[s], st);
   };
@@ -305,18 +337,18 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
 // Group halos (cells below, above each group): 4,4 / 2,2 / 2,2 / 1,2 / 1,1 /
 // 1,1 / 0,1 / 0,0, i.e. 4 ghost cells of U^n.
 template <typename T, int S, int R, bool MIX, bool L>
-void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
+void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev, const StepBufs& sb) {
   const Mix mix{MIX ? lv->E64 : nullptr, c->cfg.beta_fp64};
   hipStream_t st = c->stream;
   T* U = (T*)lv->U;
   T* B = (T*)lv->B;
-  T* W = (T*)c->W;
-  T* Bh = (T*)c->Bh;
-  T* F1 = (T*)c->F;
-  T* F2 = (T*)c->F2;
-  T* E = (T*)c->E;
-  T* QL = (T*)c->QL;
-  T* QR = (T*)c->QR;
+  T* W = (T*)sb.W;
+  T* Bh = (T*)sb.Bh;
+  T* F1 = (T*)sb.F;
+  T* F2 = (T*)sb.F2;
+  T* E = (T*)sb.E;
+  T* QL = (T*)sb.QL;
+  T* QR = (T*)sb.QR;
   const T gam = (T)c->cfg.gamma;
   const T inv_dx = (T)(1.0 / lv->dx);
   constexpr int G = 4;   // ghost cells of CTU + PPM
@@ -324,7 +356,7 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
   const Work we1 = stage_work(lv, 1, 2, G), wh = stage_work(lv, 1, 1, G), wf2 = stage_work(lv, 1, 1, G);
   const Work we2 = stage_work(lv, 0, 1, G);
   Work wu = stage_work(lv, 0, 0, G);
-  wu.occ = c->occ;
+  wu.occ = sb.occ;
   auto mark = [&](int s) {
     if (ev) (void)hipEventRecord(ev[s], st);
   };
@@ -359,7 +391,7 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
   k_half<T, MIX, L><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F1, E, dts, inv_dx, gam, W, Bh);
   mark(5);
   if constexpr (kMlp) {
-    float* Qc = (float*)c->Qc;
+    float* Qc = (float*)sb.Qc;
     const unsigned nb = sblocks(wf2);
     k_ctu_correct_dir<0, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
     k_flux_dir_mlp<0, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
@@ -381,33 +413,42 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
 }
 
 template <typename T, int S, bool MIX, bool L>
-void launch_method(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
+void launch_method(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev, const StepBufs& sb) {
   if constexpr (S == 3) {
     // learned flux: CTU only (validated at mhd_init)
-    if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX, L>(c, lv, dts, cfl, ev);
-    else launch_ctu<T, S, 0, MIX, L>(c, lv, dts, cfl, ev);
+    if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX, L>(c, lv, dts, cfl, ev, sb);
+    else launch_ctu<T, S, 0, MIX, L>(c, lv, dts, cfl, ev, sb);
     return;
   }
-  if (c->cfg.scheme == MHD_VL) launch_step<T, S, MIX, L>(c, lv, dts, cfl, ev);
-  else if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX, L>(c, lv, dts, cfl, ev);
-  else launch_ctu<T, S, 0, MIX, L>(c, lv, dts, cfl, ev);
+  if (c->cfg.scheme == MHD_VL) launch_step<T, S, MIX, L>(c, lv, dts, cfl, ev, sb);
+  else if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX, L>(c, lv, dts, cfl, ev, sb);
+  else launch_ctu<T, S, 0, MIX, L>(c, lv, dts, cfl, ev, sb);
 }
 
 // group lists use per-group scratch boxes, whole grids the level's addressing
 template <typename T, int S, bool MIX>
-void launch_scheme(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
-  if (list_mode(lv)) launch_method<T, S, MIX, true>(c, lv, dts, cfl, ev);
-  else launch_method<T, S, MIX, false>(c, lv, dts, cfl, ev);
+void launch_scheme(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev, const StepBufs& sb) {
+  if (list_mode(lv)) launch_method<T, S, MIX, true>(c, lv, dts, cfl, ev, sb);
+  else launch_method<T, S, MIX, false>(c, lv, dts, cfl, ev, sb);
 }
 
 template <typename T, bool MIX>
-void launch_step_t(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev) {
+void launch_step_t(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev, const StepBufs& sb) {
   switch (c->cfg.riemann) {
-    case MHD_ROE: launch_scheme<T, 0, MIX>(c, lv, dts, cfl, ev); break;
-    case MHD_HLLE: launch_scheme<T, 1, MIX>(c, lv, dts, cfl, ev); break;
-    case MHD_HLLD: launch_scheme<T, 2, MIX>(c, lv, dts, cfl, ev); break;
-    default: launch_scheme<T, 3, MIX>(c, lv, dts, cfl, ev); break;
+    case MHD_ROE: launch_scheme<T, 0, MIX>(c, lv, dts, cfl, ev, sb); break;
+    case MHD_HLLE: launch_scheme<T, 1, MIX>(c, lv, dts, cfl, ev, sb); break;
+    case MHD_HLLD: launch_scheme<T, 2, MIX>(c, lv, dts, cfl, ev, sb); break;
+    default: launch_scheme<T, 3, MIX>(c, lv, dts, cfl, ev, sb); break;
   }
+}
+
+// the stage kernels of one step on the given scratch
+int run_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev, const StepBufs& sb) {
+  g_max_blocks = c->max_blocks;
+  if (c->cfg.prec == MHD_F64) launch_step_t<double, false>(c, lv, dts, cfl, ev, sb);
+  else if (c->cfg.prec == MHD_F32) launch_step_t<float, false>(c, lv, dts, cfl, ev, sb);
+  else launch_step_t<float, true>(c, lv, dts, cfl, ev, sb);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 
 int do_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev = nullptr) {
@@ -418,11 +459,47 @@ int do_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* 
   if (rc) return rc;
   rc = build_occupancy(c, lv);
   if (rc) return rc;
-  g_max_blocks = c->max_blocks;
-  if (c->cfg.prec == MHD_F64) launch_step_t<double, false>(c, lv, dts, cfl, ev);
-  else if (c->cfg.prec == MHD_F32) launch_step_t<float, false>(c, lv, dts, cfl, ev);
-  else launch_step_t<float, true>(c, lv, dts, cfl, ev);
-  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_ERR_HIP;
+  return run_step(c, lv, dts, cfl, ev, ctx_bufs(c));
+}
+
+// ---- allocation-free step: stage scratch in a file-scope device array
+constexpr size_t kStaticScratchBytes = (size_t)MHD_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kStaticAlign = 256;
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mutex;
+unsigned char* g_static_ptr[kMaxDevices];   // per device: its copy's device address
+
+// scratch words per cell of a context's step (W, Bh, F, E; CTU adds QL, QR,
+// F2; the learned flux Qc)
+long long step_words(const mhd_ctx_s* c) {
+  long long words = 8 + 3 + 21 + 3;
+  if (c->cfg.scheme == MHD_CTU) words += 63;
+  if (c->cfg.riemann == MHD_MLP) words += 14;
+  return words;
+}
+
+size_t align_up(size_t x) { return (x + kStaticAlign - 1) / kStaticAlign * kStaticAlign; }
+
+// carve the step's buffers out of base[0 .. kStaticScratchBytes); returns
+// the bytes used (which may exceed the array: then nothing is carved)
+size_t carve_static(const mhd_ctx_s* c, const mhd_level* lv, unsigned char* base, StepBufs* sb) {
+  const long long cells = scratch_cells(lv, c->cfg.scheme == MHD_CTU ? 4 : 3);
+  const size_t e = c->elem;
+  const bool ctu = c->cfg.scheme == MHD_CTU, mlp = c->cfg.riemann == MHD_MLP;
+  const size_t n[8] = {8, 3, 21, 3, ctu ? 21u : 0u, ctu ? 21u : 0u, ctu ? 21u : 0u, mlp ? 14u : 0u};
+  void** dst[8] = {&sb->W, &sb->Bh, &sb->F, &sb->E, &sb->QL, &sb->QR, &sb->F2, &sb->Qc};
+  size_t off = 0;
+  size_t at[9];
+  for (int q = 0; q < 8; ++q) {
+    at[q] = off;
+    off = align_up(off + n[q] * (size_t)cells * e);
+  }
+  at[8] = off;
+  if (list_mode(lv)) off = align_up(off + (size_t)occupancy_cells(lv) * sizeof(int));
+  if (off > kStaticScratchBytes) return off;
+  for (int q = 0; q < 8; ++q) *dst[q] = n[q] ? (void*)(base + at[q]) : nullptr;
+  sb->occ = list_mode(lv) ? (int*)(base + at[8]) : nullptr;
+  return off;
 }
 
 int read_flag(mhd_ctx_s* c, int* flag) {
@@ -444,6 +521,7 @@ const char* mhd_strerror(int status) {
     case MHD_ERR_INVALID_ARG: return "invalid argument";
     case MHD_ERR_UNSUPPORTED: return "unsupported combination of scheme, reconstruction, solver or precision";
     case MHD_ERR_GHOST_TOO_SMALL: return "ghost width smaller than the stencil of one step";
+    case MHD_ERR_SCRATCH_LIMIT: return "level needs more stage scratch than the allocation-free step's static array holds";
     case MHD_ERR_HIP: return "HIP runtime error";
     case MHD_ERR_NONPHYSICAL: return "non-physical state (rho <= 0 or p <= 0)";
     case MHD_ERR_NO_DEVICE: return "no HIP device";
@@ -488,6 +566,23 @@ int mhd_init(const mhd_config* cfg, void* hip_stream, mhd_ctx* out) {
   c->stream = (hipStream_t)hip_stream;
   HIP_TRY(hipGetDevice(&c->device));
   c->elem = cfg->prec == MHD_F64 ? sizeof(double) : sizeof(float);
+  {
+    // this device's copy of the static scratch array, looked up once per device
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    if (c->device < 0 || c->device >= kMaxDevices) {
+      delete c;
+      return MHD_ERR_NO_DEVICE;
+    }
+    if (!g_static_ptr[c->device]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        delete c;
+        return MHD_ERR_HIP;
+      }
+      g_static_ptr[c->device] = (unsigned char*)ptr;
+    }
+    c->static_scratch = g_static_ptr[c->device];
+  }
   c->capture = Capture{nullptr, 0, nullptr, 1};
   {
     hipDeviceProp_t prop;
@@ -591,6 +686,19 @@ int mhd_step_devdt(mhd_ctx c, const mhd_level* lv, const double* dt_dev) {
   if (!c || !dt_dev) return MHD_ERR_INVALID_ARG;
   DtSrc s{0.0, dt_dev, nullptr, 0.0};
   return do_step(c, lv, s, false);
+}
+
+int mhd_step_noalloc(mhd_ctx c, const mhd_level* lv, const double* dt_dev) {
+  if (!c || !dt_dev) return MHD_ERR_INVALID_ARG;
+  int rc = check_level(c, lv);
+  if (rc) return rc;
+  if (c->cfg.riemann == MHD_MLP && !c->mlp_ready) return MHD_ERR_INVALID_ARG;
+  if (!c->static_scratch) return MHD_ERR_HIP;
+  StepBufs sb{};
+  if (carve_static(c, lv, c->static_scratch, &sb) > kStaticScratchBytes) return MHD_ERR_SCRATCH_LIMIT;
+  if (list_mode(lv)) fill_occupancy(c, lv, sb.occ);
+  DtSrc s{0.0, dt_dev, nullptr, 0.0};
+  return run_step(c, lv, s, false, nullptr, sb);
 }
 
 int mhd_advance(mhd_ctx c, const mhd_level* lv, double* dt_dev, double* t_dev) {

@@ -26,7 +26,8 @@ SOLVERS = {"roe": ROE, "hlle": HLLE, "hlld": HLLD, "mlp": MLP}
 PRECS = {"f64": F64, "f32": F32, "f32_mixed": F32_MIXED}
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "ghost too small", -4: "HIP error",
-          -5: "non-physical state", -6: "no device", -7: "out of memory"}
+          -5: "non-physical state", -6: "no device", -7: "out of memory", -8: "static scratch too small"}
+SCRATCH_LIMIT = -8
 
 
 class MHDError(RuntimeError):
@@ -58,7 +59,7 @@ EXPORTS = ["mhd_abi_version", "mhd_strerror", "mhd_required_ghost", "mhd_init", 
            "mhd_mlp_train_step", "mhd_mlp_prepare", "mhd_mlp_face_flux", "mhd_set_capture", "mhd_correct",
            "mhd_advance_graph", "mhd_set_launch", "mhd_cfl_dt_min", "mhd_prolong", "mhd_restrict",
            "mhd_prolong_time", "mhd_accumulate_registers", "mhd_dt_subdivide", "mhd_regrid_flag",
-           "mhd_prolong_new_groups", "mhd_workspace_bytes"]
+           "mhd_prolong_new_groups", "mhd_workspace_bytes", "mhd_step_noalloc"]
 
 
 def load(path: str = LIB_PATH):
@@ -80,6 +81,7 @@ def load(path: str = LIB_PATH):
     lib.mhd_cfl_dt.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(D), P]
     lib.mhd_step.argtypes = [P, ctypes.POINTER(LevelDesc), D]
     lib.mhd_step_devdt.argtypes = [P, ctypes.POINTER(LevelDesc), P]
+    lib.mhd_step_noalloc.argtypes = [P, ctypes.POINTER(LevelDesc), P]
     lib.mhd_advance.argtypes = [P, ctypes.POINTER(LevelDesc), P, P]
     lib.mhd_divB.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.mhd_sums.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(D * 7)]
@@ -280,6 +282,14 @@ class Solver:
         check_dt_tensor(dt_dev, "dt_dev")
         d = lv.desc()
         _check(self.lib.mhd_step_devdt(self.h, ctypes.byref(d), ctypes.c_void_p(dt_dev.data_ptr())), "mhd_step_devdt")
+
+    def step_noalloc(self, lv: Level, dt_dev: torch.Tensor):
+        """mhd_step_devdt with the library's static scratch (no device allocation)."""
+        self._check_level(lv)
+        check_dt_tensor(dt_dev, "dt_dev")
+        d = lv.desc()
+        _check(self.lib.mhd_step_noalloc(self.h, ctypes.byref(d), ctypes.c_void_p(dt_dev.data_ptr())),
+               "mhd_step_noalloc")
 
     def advance(self, lv: Level, dt_dev: torch.Tensor | None = None, t_dev: torch.Tensor | None = None):
         self._check_level(lv)
