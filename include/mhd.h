@@ -43,7 +43,8 @@ extern "C" {
 #define MHD_OK 0
 #define MHD_ERR_INVALID_ARG -1
 #define MHD_ERR_UNSUPPORTED -2
-#define MHD_ERR_GHOST_TOO_SMALL -3
+/* -3 is not used: ghost zones are the level's own cells around a listed
+ * group (see mhd_level), so a caller cannot hand over too few of them */
 #define MHD_ERR_HIP -4
 #define MHD_ERR_NONPHYSICAL -5
 #define MHD_ERR_NO_DEVICE -6
@@ -98,8 +99,9 @@ typedef struct {
                               the list changed */
 } mhd_level;
 
-/* Ghost width a staged patch group needs for one full step of the given
- * integrator and reconstruction (stencil count: 3 for PLM, 4 for PPM). */
+/* Ghost width a patch group needs for one full step of the given integrator
+ * and reconstruction (stencil count: 3 for PLM, 4 for PPM): the cells around
+ * a listed group that must hold valid ghost data (mhd_prolong fills them). */
 int mhd_required_ghost(int scheme, int recon);
 
 /* Device bytes the context's stage scratch takes to update lv (in

@@ -520,7 +520,6 @@ const char* mhd_strerror(int status) {
     case MHD_OK: return "ok";
     case MHD_ERR_INVALID_ARG: return "invalid argument";
     case MHD_ERR_UNSUPPORTED: return "unsupported combination of scheme, reconstruction, solver or precision";
-    case MHD_ERR_GHOST_TOO_SMALL: return "ghost width smaller than the stencil of one step";
     case MHD_ERR_SCRATCH_LIMIT: return "level needs more stage scratch than the allocation-free step's static array holds";
     case MHD_ERR_HIP: return "HIP runtime error";
     case MHD_ERR_NONPHYSICAL: return "non-physical state (rho <= 0 or p <= 0)";

@@ -25,7 +25,7 @@ RECONS = {"plm": PLM, "ppm": PPM}
 SOLVERS = {"roe": ROE, "hlle": HLLE, "hlld": HLLD, "mlp": MLP}
 PRECS = {"f64": F64, "f32": F32, "f32_mixed": F32_MIXED}
 
-ERRORS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "ghost too small", -4: "HIP error",
+ERRORS = {0: "ok", -1: "invalid argument", -2: "unsupported", -4: "HIP error",
           -5: "non-physical state", -6: "no device", -7: "out of memory", -8: "static scratch too small"}
 SCRATCH_LIMIT = -8
 
