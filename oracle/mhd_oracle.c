@@ -427,7 +427,10 @@ static double minmod(double a, double b) {
  * 5 E_t1, 6 E_t2 (the edge-parallel EMFs carried by the face:
  * E_t1 = F_n[B_t2], E_t2 = -F_n[B_t1], from E = -V x B).
  * recon: OR_FIRST_ORDER uses the two cell states, OR_PLM minmod-limited
- * linear states in primitive variables. */
+ * linear states in primitive variables, OR_PPM the limited parabolas of
+ * Colella & Woodward (the upper edge value of the left cell and the lower
+ * edge value of the right cell, in primitive variables, no tracing: the VL
+ * predictor already centres the data in time). */
 static void face_fluxes(const grid_t* g, int d, int recon, int solver, const double* W,
                         const double* B, double* F, int* nfallback) {
   size_t N = ncell(g);
@@ -443,7 +446,20 @@ static void face_fluxes(const grid_t* g, int d, int recon, int solver, const dou
         double wl[7], wr[7];
         cell_w1d(W, N, cL, d, wl);
         cell_w1d(W, N, cR, d, wr);
-        if (recon == OR_PLM || recon == OR_PLM_UNLIMITED) {
+        if (recon == OR_PPM) {
+          /* cells -3 .. 2 relative to the face's upper cell */
+          double c6[6][7];
+          for (int s = -3; s <= 2; ++s) cell_w1d(W, N, at_shift(g, i, j, k, d, s), d, c6[s + 3]);
+          for (int m = 0; m < 7; ++m) {
+            double lo, hi;
+            double ql[5] = {c6[0][m], c6[1][m], c6[2][m], c6[3][m], c6[4][m]};
+            double qr[5] = {c6[1][m], c6[2][m], c6[3][m], c6[4][m], c6[5][m]};
+            or_ppm_edges(ql, &lo, &hi);
+            wl[m] = hi;                       /* upper edge of the left cell */
+            or_ppm_edges(qr, &lo, &hi);
+            wr[m] = lo;                       /* lower edge of the right cell */
+          }
+        } else if (recon == OR_PLM || recon == OR_PLM_UNLIMITED) {
           double wll[7], wrr[7];
           cell_w1d(W, N, at_shift(g, i, j, k, d, -2), d, wll);
           cell_w1d(W, N, at_shift(g, i, j, k, d, 1), d, wrr);
@@ -724,7 +740,9 @@ int or_step(int nx, int ny, int nz, double dx, double gam, int scheme, int recon
   int fb = 0;
   int rc;
   if (scheme == OR_VL) {
-    if (recon != OR_PLM && recon != OR_FIRST_ORDER && recon != OR_PLM_UNLIMITED) return -1;
+    /* no unlimited PPM: without limiting or tracing both sides of a face
+     * take the same interface value, a central scheme without dissipation */
+    if (recon != OR_PLM && recon != OR_FIRST_ORDER && recon != OR_PLM_UNLIMITED && recon != OR_PPM) return -1;
     rc = vl_step(&g, recon, solver, U, B, dt, Uo, Bo, &fb);
   } else if (scheme == OR_CTU) {
     rc = or_ctu_step_impl(nx, ny, nz, dx, gam, recon, solver, U, B, dt, Uo, Bo, &fb);
