@@ -91,8 +91,6 @@ int check_config(const mhd_config* c) {
   if (c->prec < MHD_F64 || c->prec > MHD_F32_MIXED) return MHD_ERR_INVALID_ARG;
   if (!valid_gamma(c->gamma)) return MHD_ERR_INVALID_ARG;
   if (!(c->courant > 0.0 && c->courant <= 1.0)) return MHD_ERR_INVALID_ARG;
-  // implemented combinations: VL with PLM; CTU with PLM or PPM
-  if (c->scheme == MHD_VL && c->recon != MHD_PLM) return MHD_ERR_UNSUPPORTED;
   // the learned flux runs in FP32 inside the CTU Riemann stages
   if (c->riemann == MHD_MLP && (c->scheme != MHD_CTU || c->prec == MHD_F64)) return MHD_ERR_UNSUPPORTED;
   if (c->riemann == MHD_MLP && !(std::isfinite(c->mlp_dp) && std::isfinite(c->mlp_drho))) return MHD_ERR_INVALID_ARG;
@@ -196,6 +194,9 @@ Work make_work(const mhd_level* lv, int lo, int hi) {
 // Work of an update stage whose items reach lo / hi cells below / above each
 // group; with a group list the stage scratch is addressed per group, in boxes
 // of edge + 2 ghost cells (ghost >= lo, hi).
+// ghost cells a step reads around a group: 4 for CTU and for PPM, 3 for VL + PLM
+int step_ghost(const mhd_ctx_s* c) { return c->cfg.scheme == MHD_CTU || c->cfg.recon == MHD_PPM ? 4 : 3; }
+
 long long scratch_box(const mhd_level* lv, int ghost) { return (long long)lv->group_edge + 2 * ghost; }
 bool list_mode(const mhd_level* lv) { return lv->groups && lv->n_groups > 0; }
 
@@ -282,8 +283,9 @@ StepBufs ctx_bufs(const mhd_ctx_s* c) {
   return StepBufs{c->W, c->Bh, c->F, c->E, c->QL, c->QR, c->F2, c->Qc, c->occ};
 }
 
-// ev (optional): kNumStages + 1 events recorded around the stage kernels
-template <typename T, int S, bool MIX, bool L>
+// ev (optional): kNumStages + 1 events recorded around the stage kernels.
+// R: 1 = PLM (minmod), 2 = PPM at the half step.
+template <typename T, int S, int R, bool MIX, bool L>
 void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev, const StepBufs& sb) {
   const Mix mix{MIX ? lv->E64 : nullptr, c->cfg.beta_fp64};
   hipStream_t st = c->stream;
@@ -295,9 +297,11 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
   T* E = (T*)sb.E;
   const T gam = (T)c->cfg.gamma;
   const T inv_dx = (T)(1.0 / lv->dx);
-  constexpr int G = 3;   // ghost cells of VL + PLM
-  const Work wp = stage_work(lv, 3, 3, G), wf1 = stage_work(lv, 3, 3, G), we1 = stage_work(lv, 2, 3, G);
-  const Work wh = stage_work(lv, 2, 2, G), wf2 = stage_work(lv, 1, 1, G), we2 = stage_work(lv, 0, 1, G);
+  // ghost cells: 3 for PLM (the corrector's faces reach 2 cells below and 1
+  // above), 4 for PPM (3 below and 2 above), and one more for each stage back
+  constexpr int G = R == 2 ? 4 : 3;
+  const Work wp = stage_work(lv, G, G, G), wf1 = stage_work(lv, G, G, G), we1 = stage_work(lv, G - 1, G, G);
+  const Work wh = stage_work(lv, G - 1, G - 1, G), wf2 = stage_work(lv, 1, 1, G), we2 = stage_work(lv, 0, 1, G);
   Work wu = stage_work(lv, 0, 0, G);
   wu.occ = sb.occ;
   auto mark = [&](int s) {
@@ -317,7 +321,7 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
   mark(3);
   k_half<T, MIX, L><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F, E, dts, inv_dx, gam, W, Bh);
   mark(4);
-  k_flux<T, 1, S, L><<<sblocks(wf2), kBlock, 0, st>>>(wf2, W, Bh, F, gam, c->nfb);
+  k_flux<T, R, S, L><<<sblocks(wf2), kBlock, 0, st>>>(wf2, W, Bh, F, gam, c->nfb);
   mark(5);
   k_emf<T, L><<<sblocks(we2), kBlock, 0, st>>>(we2, F, W, E);
   mark(6);
@@ -420,7 +424,10 @@ void launch_method(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEv
     else launch_ctu<T, S, 0, MIX, L>(c, lv, dts, cfl, ev, sb);
     return;
   }
-  if (c->cfg.scheme == MHD_VL) launch_step<T, S, MIX, L>(c, lv, dts, cfl, ev, sb);
+  if (c->cfg.scheme == MHD_VL) {
+    if (c->cfg.recon == MHD_PPM) launch_step<T, S, 2, MIX, L>(c, lv, dts, cfl, ev, sb);
+    else launch_step<T, S, 1, MIX, L>(c, lv, dts, cfl, ev, sb);
+  }
   else if (c->cfg.recon == MHD_PPM) launch_ctu<T, S, 1, MIX, L>(c, lv, dts, cfl, ev, sb);
   else launch_ctu<T, S, 0, MIX, L>(c, lv, dts, cfl, ev, sb);
 }
@@ -455,7 +462,7 @@ int do_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* 
   int rc = check_level(c, lv);
   if (rc) return rc;
   if (c->cfg.riemann == MHD_MLP && !c->mlp_ready) return MHD_ERR_INVALID_ARG;
-  rc = ensure_capacity(c, scratch_cells(lv, c->cfg.scheme == MHD_CTU ? 4 : 3));
+  rc = ensure_capacity(c, scratch_cells(lv, step_ghost(c)));
   if (rc) return rc;
   rc = build_occupancy(c, lv);
   if (rc) return rc;
@@ -483,7 +490,7 @@ size_t align_up(size_t x) { return (x + kStaticAlign - 1) / kStaticAlign * kStat
 // carve the step's buffers out of base[0 .. kStaticScratchBytes); returns
 // the bytes used (which may exceed the array: then nothing is carved)
 size_t carve_static(const mhd_ctx_s* c, const mhd_level* lv, unsigned char* base, StepBufs* sb) {
-  const long long cells = scratch_cells(lv, c->cfg.scheme == MHD_CTU ? 4 : 3);
+  const long long cells = scratch_cells(lv, step_ghost(c));
   const size_t e = c->elem;
   const bool ctu = c->cfg.scheme == MHD_CTU, mlp = c->cfg.riemann == MHD_MLP;
   const size_t n[8] = {8, 3, 21, 3, ctu ? 21u : 0u, ctu ? 21u : 0u, ctu ? 21u : 0u, mlp ? 14u : 0u};
@@ -540,7 +547,7 @@ int mhd_workspace_bytes(mhd_ctx c, const mhd_level* lv, size_t* bytes) {
   if (!c || !bytes) return MHD_ERR_INVALID_ARG;
   const int rc = check_level(c, lv);
   if (rc) return rc;
-  const int ghost = c->cfg.scheme == MHD_CTU ? 4 : 3;
+  const int ghost = step_ghost(c);
   long long words = 35;
   if (c->cfg.scheme == MHD_CTU) words += 63;
   if (c->cfg.riemann == MHD_MLP) words += 14;
@@ -773,7 +780,7 @@ int mhd_advance_graph(mhd_ctx c, const mhd_level* lv, double* dt_dev, double* t_
   if (!same) {
     drop_graph(c);
     // allocations happen before the capture
-    rc = ensure_capacity(c, scratch_cells(lv, c->cfg.scheme == MHD_CTU ? 4 : 3));
+    rc = ensure_capacity(c, scratch_cells(lv, step_ghost(c)));
     if (rc) return rc;
     if (lv->groups && lv->n_groups > 0) {
       const long long ng =

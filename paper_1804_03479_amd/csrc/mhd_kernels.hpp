@@ -329,9 +329,11 @@ __device__ __forceinline__ void load_w1d(const T* __restrict__ W, long long N, l
   w[6] = W[(5 + t2) * N + q];
 }
 
-// RECON: 0 = first order (cell states), 1 = PLM with minmod on primitives.
-// The normal field Bn is the level's B (predictor: Bn[D N + p]) or the
-// half-step scratch Bh (corrector: Bn[D NS + s]); RECON 1 is the corrector.
+// RECON: 0 = first order (cell states), 1 = PLM with minmod on primitives,
+// 2 = PPM (the limited parabolas' upper edge of the left cell and lower edge
+// of the right cell, no tracing: the VL predictor centres the data in time).
+// The normal field Bn is the level's B (predictor, RECON 0: Bn[D N + p]) or
+// the half-step scratch Bh (corrector, RECON 1 and 2: Bn[D NS + s]).
 template <typename T, int D, int RECON, int SOLVER, bool L>
 __device__ __forceinline__ int face_flux(const Work& w, const T* __restrict__ W, const T* __restrict__ Bn,
                                          T* __restrict__ F, const Site& st, T gam) {
@@ -354,8 +356,23 @@ __device__ __forceinline__ int face_flux(const Work& w, const T* __restrict__ W,
       wl[m] = wl[m] + T(0.5) * sL;
       wr[m] = wr[m] - T(0.5) * sR;
     }
+  } else if (RECON == 2) {
+    // cells -3, -2 and 1, 2 around the face (-1 and 0 are wl, wr)
+    T q3[7], q2[7], p1[7], p2[7];
+    load_w1d<T, D>(W, NS, snb<L>(w, st, D == 0 ? -3 : 0, D == 1 ? -3 : 0, D == 2 ? -3 : 0), q3);
+    load_w1d<T, D>(W, NS, snb<L>(w, st, D == 0 ? -2 : 0, D == 1 ? -2 : 0, D == 2 ? -2 : 0), q2);
+    load_w1d<T, D>(W, NS, snb<L>(w, st, D == 0 ? 1 : 0, D == 1 ? 1 : 0, D == 2 ? 1 : 0), p1);
+    load_w1d<T, D>(W, NS, snb<L>(w, st, D == 0 ? 2 : 0, D == 1 ? 2 : 0, D == 2 ? 2 : 0), p2);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      T lo, hi, lo2, hi2;
+      ppm_edges(q3[m], q2[m], wl[m], wr[m], p1[m], lo, hi);     // cell -1
+      ppm_edges(q2[m], wl[m], wr[m], p1[m], p2[m], lo2, hi2);   // cell 0
+      wl[m] = hi;
+      wr[m] = lo2;
+    }
   }
-  const T bn = RECON == 1 ? Bn[D * NS + st.s] : Bn[D * w.N + st.p];
+  const T bn = RECON != 0 ? Bn[D * NS + st.s] : Bn[D * w.N + st.p];
   T f[7];
   const int fb = riemann<SOLVER>(wl, wr, bn, gam, f);
   constexpr int n = D, t1 = (D + 1) % 3, t2 = (D + 2) % 3;
@@ -385,7 +402,7 @@ __device__ __forceinline__ void block_count_atomic(int v, unsigned long long* co
 }
 
 // VL flux stage; B is the level's field for RECON 0 and the half-step
-// scratch Bh for RECON 1 (see face_flux).
+// scratch Bh for RECON 1 and 2 (see face_flux).
 template <typename T, int RECON, int SOLVER, bool L>
 __global__ void __launch_bounds__(kBlock) k_flux(Work w, const T* __restrict__ W, const T* __restrict__ B,
                                                  T* __restrict__ F, T gam, unsigned long long* nfb) {

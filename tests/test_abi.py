@@ -39,8 +39,9 @@ def test_header_matches_exports(mhd):
 def test_abi_version_and_strings(mhd):
     lib = mhd.load()
     assert lib.mhd_abi_version() == 2
-    for s in (0, -1, -2, -3, -4, -5, -6, -7):
-        assert len(lib.mhd_strerror(s)) > 0
+    for s in (0, -1, -2, -4, -5, -6, -7, -8):
+        assert len(lib.mhd_strerror(s)) > 0 and lib.mhd_strerror(s) != b"unknown status"
+    assert lib.mhd_strerror(-3) == b"unknown status"      # retired code
     assert lib.mhd_strerror(-999) == b"unknown status"
 
 
@@ -48,6 +49,7 @@ def test_required_ghost(mhd):
     lib = mhd.load()
     assert lib.mhd_required_ghost(mhd.VL, mhd.PLM) == 3
     assert lib.mhd_required_ghost(mhd.CTU, mhd.PPM) == 4
+    assert lib.mhd_required_ghost(mhd.VL, mhd.PPM) == 4
     assert lib.mhd_required_ghost(7, mhd.PLM) == -1
     assert lib.mhd_required_ghost(mhd.VL, 9) == -1
 

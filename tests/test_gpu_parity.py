@@ -163,6 +163,81 @@ def test_one_step_f32(solver):
     assert l1_rel(Bg, Bo) <= 1e-5
 
 
+# ---------------------------------------------------------------- VL + PPM
+@pytest.mark.parametrize("solver", ["roe", "hlld"])
+@pytest.mark.parametrize("prob", sorted(PROBLEMS))
+def test_vl_ppm_one_step_f64(prob, solver):
+    p = PROBLEMS[prob]()
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx, recon=oracle.PPM, riemann=SOLVERS[solver])
+    s = Solver("vl", "ppm", solver)
+    lv = level_from(U, B, dx)
+    s.step(lv, dt)
+    Ug, Bg = fetch(lv)
+    assert rel_err(Ug, Uo) <= 1e-12
+    assert rel_err(Bg, Bo) <= 1e-12
+
+
+def test_vl_ppm_ten_steps_abc32_f64():
+    p = inputs.abc_problem(32, 0.1, seed=2)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    Uo, Bo, t_o, _ = oracle.run(U, B, 10, dx, recon=oracle.PPM, riemann=oracle.HLLD)
+    s = Solver("vl", "ppm", "hlld")
+    lv = level_from(U, B, dx)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(10):
+        s.advance(lv, t_dev=t)
+    Ug, Bg = fetch(lv)
+    assert abs(t.item() - t_o) <= 1e-13 * t_o
+    assert rel_err(Ug, Uo) <= 1e-12
+    assert rel_err(Bg, Bo) <= 1e-12
+
+
+def test_vl_ppm_group_list_subset():
+    p = inputs.smooth_problem(48, 32, 32, seed=5)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+    Uo, Bo = oracle.step(U, B, dt, dx, recon=oracle.PPM, riemann=oracle.HLLD)
+    s = Solver("vl", "ppm", "hlld")
+    origins = [(16, 0, 0), (32, 16, 16)]
+    g = torch.tensor(origins, dtype=torch.int32, device="cuda")
+    lv = level_from(U, B, dx, groups=g)
+    s.step(lv, dt)
+    Ug, Bg = fetch(lv)
+    mask = np.zeros(U.shape[1:], bool)
+    for (i, j, k) in origins:
+        mask[k:k + 16, j:j + 16, i:i + 16] = True
+    for m in range(5):
+        assert np.abs(Ug[m][mask] - Uo[m][mask]).max() <= 1e-12 * np.abs(Uo[m]).max()
+        assert np.array_equal(Ug[m][~mask], U[m][~mask])
+    for a in range(3):
+        assert np.abs(Bg[a][mask] - Bo[a][mask]).max() <= 1e-12 * np.abs(Bo[a]).max()
+
+
+@pytest.mark.parametrize("solver", ["hlld", "roe"])
+def test_vl_ppm_one_step_f32_noisy_abc(solver):
+    p = inputs.abc_problem(32, 0.1, seed=1)
+    U, B = oracle.initial_state(p)
+    U = U.astype(np.float32).astype(np.float64)
+    B = B.astype(np.float32).astype(np.float64)
+    dx = p["dx"]
+    dt = oracle.cfl_dt(U, B, dx)
+
+    def run(u, b):
+        return oracle.step(u, b, dt, dx, recon=oracle.PPM, riemann=SOLVERS[solver])
+    Uo, Bo = run(U, B)
+    s = Solver("vl", "ppm", solver, prec="f32")
+    lv = level_from(U, B, dx, torch.float32)
+    s.step(lv, dt)
+    Ug, Bg = fetch(lv)
+    mu, mb, su, sb = sensitive_mask(run, U, B)
+    check_outside(Ug, Bg, Uo, Bo, mu, mb, su, sb, what=f"VL+PPM+{solver} FP32, 32^3 ABC noise 0.1")
+
+
 def test_diagnostics_parity():
     p = inputs.smooth_problem(24, 20, 16, seed=7)
     U, B = oracle.initial_state(p)
