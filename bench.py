@@ -250,8 +250,11 @@ def run_amr(n_root: int, counts, steps: int, warmup: int, seed: int, tune: bool)
             "ms_per_step_eager": ms_eager, "value": sum(cells) / (ms_graph * 1e-3),
             "per_level_ms": per_level,
             "per_level_value": [c / (t * 1e-3) for c, t in zip(cells, per_level)],
-            "launch_blocks_per_cu": None if not tuned else tuned["shapes"],
-            "autotune_ms": None if not tuned else tuned["ms"], "candidates": autotune.CANDIDATES,
+            "launch_shapes": None if not tuned else [list(x) for x in tuned["shapes"]],
+            "autotune": None if not tuned else [
+                {"shape_fields": ["blocks_per_cu", "threads", "batch"],
+                 "table": [list(c) + [round(ms, 4)] for c, ms in zip(cands, mss)]}
+                for cands, mss in zip(tuned["candidates"], tuned["ms"])],
             "max_divb_dx_listed": divb,
             "subcycled": {"updates_per_root_step": upd, "ms_per_root_step_graph": ms_sub,
                           "value": sum(upd) / (ms_sub * 1e-3)}}
@@ -436,6 +439,56 @@ def l1_vs_oracle(wl: dict, n: int, seed: int, nsteps: int, precs):
     return out, t_cpu
 
 
+def l1_vs_oracle_run(wl: dict, n: int, seed: int, nsteps: int, precs, log_every: int = 20):
+    """The FP64 oracle run for nsteps CFL steps on the host, then each GPU form
+    stepped with the oracle's own dt sequence (so both sit at the same times);
+    relative L1 (rho, e, B) of each form against the oracle and its max |div B|."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1804_03479_amd import inputs
+    from paper_1804_03479_amd.mhd import Level, Solver
+    p = inputs.abc_problem(n, wl["noise"], seed=seed)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    kw = dict(scheme=oracle.CTU if wl["scheme"] == "ctu" else oracle.VL,
+              recon=oracle.PPM if wl["recon"] == "ppm" else oracle.PLM,
+              riemann={"roe": oracle.ROE, "hlle": oracle.HLLE, "hlld": oracle.HLLD}[wl["riemann"]])
+    t0 = time.perf_counter()
+    Uo, Bo, dts = U, B, []
+    for k in range(nsteps):
+        dt = oracle.cfl_dt(Uo, Bo, dx)
+        dts.append(dt)
+        Uo, Bo = oracle.step(Uo, Bo, dt, dx, **kw)
+        if log_every and (k + 1) % log_every == 0:
+            print(f"oracle step {k + 1}/{nsteps} ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    t_cpu = time.perf_counter() - t0
+    out = {"steps": nsteps, "t": float(sum(dts)), "oracle_seconds": round(t_cpu, 1),
+           "oracle_threads": oracle.get_threads()}
+    for prec in precs:
+        dtype = torch.float64 if prec == "f64" else torch.float32
+        s = Solver(wl["scheme"], wl["recon"], wl["riemann"], prec)
+        E64 = torch.from_numpy(U[4].copy()).to("cuda") if prec == "f32_mixed" else None
+        lv = Level(torch.from_numpy(U).to("cuda", dtype).contiguous(),
+                   torch.from_numpy(B).to("cuda", dtype).contiguous(), dx, E64=E64)
+        for dt in dts:
+            s.step(lv, dt)
+        torch.cuda.synchronize()
+        mx, _ = s.divb(lv)
+        Ug, Bg = lv.U.double().cpu().numpy(), lv.B.double().cpu().numpy()
+        if E64 is not None:
+            Ug[4] = E64.cpu().numpy()
+        out[prec] = {
+            "rho": float(np.abs(Ug[0] - Uo[0]).mean() / np.abs(Uo[0]).mean()),
+            "e": float(np.abs(Ug[4] - Uo[4]).mean() / np.abs(Uo[4]).mean()),
+            "B": float(np.abs(Bg - Bo).mean() / np.abs(Bo).mean()),
+            "max_divb_dx": mx * dx,
+        }
+        s.close()
+    out["oracle_max_divb_dx"] = float(np.abs(oracle.divb(Bo, dx)).max() * dx)
+    return out
+
+
 def counter_record(name: str, workload: str, prec: str):
     """A committed counter summary (profiles/<name>.json) of this workload and
     precision, or None when the kernel sources changed since it was taken."""
@@ -499,6 +552,10 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain device-to-device copy run first (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--oracle-l1-steps", type=int, default=0,
+                    help="also run the FP64 oracle this many steps on the headline workload and report the "
+                         "L1 of every precision form against it (200: the precision form's full length, "
+                         "about 2 minutes on 16 host cores)")
     ap.add_argument("--only", choices=["ctu", "vl", "mlp", "amr"], default=None, help="time one workload only")
     ap.add_argument("--l1-steps", type=int, default=200,
                     help="steps of the FP32 / mixed forms against the FP64 form (precision form)")
@@ -602,6 +659,11 @@ def main():
             forms[f"{key}_{prec}"] = e
         if key != head_key and "stages" in r["f32"]:
             forms[f"{key}_f32"]["stage_ms"] = {k: round(x, 4) for k, x in r["f32"]["stages"].items()}
+
+    if args.oracle_l1_steps > 0 and head_key is not None:
+        precs = ("f64", "f32", "f32_mixed") if head_key == "ctu" else ("f64", "f32")
+        forms[f"{head_key}_l1_vs_oracle_full"] = l1_vs_oracle_run(WORKLOADS[head_key], n, args.seed,
+                                                                   args.oracle_l1_steps, precs)
 
     if "mlp" in todo:
         from paper_1804_03479_amd.mhd import MlpOps

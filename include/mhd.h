@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MHD_ABI_VERSION 2
+#define MHD_ABI_VERSION 3
 
 /* status codes */
 #define MHD_OK 0
@@ -171,11 +171,23 @@ int mhd_advance(mhd_ctx ctx, const mhd_level* lv, double* dt_dev, double* t_dev)
  * replay needs no host work.  A different description re-captures. */
 int mhd_advance_graph(mhd_ctx ctx, const mhd_level* lv, double* dt_dev, double* t_dev);
 
-/* Launch shape of the stage kernels: at most blocks_per_cu 256-thread blocks
- * per compute unit walk the work with a grid-wide stride (0 = one thread per
- * work item, no cap).  Drops any captured graph.  The reduction kernels of
- * mhd_divB and mhd_sums keep their fixed shape (bitwise-stable results). */
-int mhd_set_launch(mhd_ctx ctx, int blocks_per_cu);
+/* Launch shape of the stage kernels (the batched level update):
+ *   blocks_per_cu      at most this many blocks per compute unit walk the
+ *                      work with a grid-wide stride (0 = one thread per work
+ *                      item, no cap);
+ *   threads_per_block  64 .. 512, a multiple of 64 (0 = 256); the learned
+ *                      flux's network kernels keep 256;
+ *   batch_groups       with a group list, the stages between the primitive
+ *                      pass (which also reduces the CFL maximum over the whole
+ *                      list) and the final update run batch by batch, each
+ *                      batch of at most this many groups through all of them,
+ *                      so its intermediates can stay in the caches (paper
+ *                      Sec. 4 sends patch groups to the GPU in batches);
+ *                      0 = the whole list in one launch per stage.
+ * Every shape gives bit-identical results.  Drops any captured graph.  The
+ * reduction kernels of mhd_divB and mhd_sums and the AMR transfer kernels
+ * keep their fixed shape. */
+int mhd_set_launch(mhd_ctx ctx, int blocks_per_cu, int threads_per_block, int batch_groups);
 
 /* Minimum of scale times the level's CFL time step and *dt_dev, written to
  * *dt_dev, without a host sync: scale 1 on every level gives a shared step;

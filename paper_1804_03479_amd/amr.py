@@ -215,9 +215,10 @@ class Hierarchy:
         return [c << (l if self.subcycle else 0) for l, c in enumerate(self.cells_per_level())]
 
     def set_launch(self, shapes):
-        """Blocks per CU of each level's persistent launches (0 = one item per thread)."""
+        """Launch shape of each level: blocks per CU of the persistent launches
+        (0 = one item per thread), or a (blocks_per_cu, threads, batch) tuple."""
         for s, b in zip(self.solvers, shapes):
-            s.set_launch(int(b))
+            s.set_launch(*(tuple(b) if isinstance(b, (tuple, list)) else (int(b),)))
 
     def shared_dt(self, dt_max: float = float("inf")):
         """Device steps of all levels: the shared CFL minimum, or with

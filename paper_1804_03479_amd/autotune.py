@@ -1,23 +1,45 @@
 """Launch-shape autotuner of the batched level update.
 
-Each level's stage kernels are persistent: a grid of at most
-blocks_per_cu x CUs blocks walks the level's work items (the cells of its
-listed patch groups and their halos) with a grid-wide stride, so one launch
-covers any number of groups.  The shape decides how many groups one sweep of
-the grid holds (blocks x 256 threads / 16^3 cells per group) and how much of
-the chip a small level occupies.  The tuner times each candidate on the
-level itself (ghost refill plus update, HIP events, median of a few reps)
-and keeps the fastest; results are cached in a JSON file keyed by device,
-method, precision, level shape and group count.
+A level's stage kernels have three launch parameters (mhd_set_launch):
+blocks per CU of the persistent grid that walks the level's work items (the
+cells of its listed patch groups and their halos) with a grid-wide stride,
+threads per block, and, for a group list, the batch of groups that runs
+through the middle stages together (so that a batch's intermediates can stay
+in the caches between stages; paper Sec. 4 sends patch groups to the GPU in
+batches).  The tuner times each candidate shape on the level itself (ghost
+refill plus update, HIP events, median of a few reps) and keeps the fastest;
+results are cached in a JSON file keyed by device, method, precision, level
+shape and group count.  Every shape gives bit-identical results.
 """
 from __future__ import annotations
 
+import itertools
 import json
 import os
 
 import torch
 
+BLOCKS_PER_CU = (0, 2, 8)
+THREADS = (128, 256, 512)
+BATCHES = (16, 32, 64, 128, 256, 512, 1024, 2048, 4096)
+# the former one-parameter sweep (blocks per CU at 256 threads, whole list)
 CANDIDATES = (0, 1, 2, 4, 8, 16)
+
+
+def shape(c):
+    """(blocks_per_cu, threads, batch) of a candidate given as an int or a tuple."""
+    if isinstance(c, (tuple, list)):
+        b, t, n = (tuple(c) + (0, 0))[:3]
+        return int(b), int(t), int(n)
+    return int(c), 0, 0
+
+
+def level_candidates(n_groups: int):
+    """Shapes swept on a level with n_groups listed groups (0: whole grid):
+    blocks per CU x threads per block x batch (the whole list, and every
+    batch of 16 .. 4096 groups smaller than the list)."""
+    batches = (0,) + tuple(b for b in BATCHES if b < n_groups)
+    return [(b, t, n) for b, t, n in itertools.product(BLOCKS_PER_CU, THREADS, batches)]
 
 
 def default_cache_path() -> str:
@@ -25,13 +47,17 @@ def default_cache_path() -> str:
     return os.path.join(base, "paper_1804_03479_amd", "autotune.json")
 
 
+def n_listed(h, lvl: int) -> int:
+    lv = h.levels[lvl]
+    return 0 if lv.groups is None else int(lv.groups.shape[0])
+
+
 def level_key(h, lvl: int) -> str:
     s, lv = h.solvers[lvl], h.levels[lvl]
     dev = torch.cuda.get_device_properties(0)
     arch = getattr(dev, "gcnArchName", dev.name)
-    n = 0 if lv.groups is None else int(lv.groups.shape[0])
     c = s.cfg
-    return f"{arch}|s{c.scheme}r{c.recon}f{c.riemann}p{c.prec}|{'x'.join(map(str, lv.shape))}|g{n}"
+    return f"{arch}|s{c.scheme}r{c.recon}f{c.riemann}p{c.prec}|{'x'.join(map(str, lv.shape))}|g{n_listed(h, lvl)}"
 
 
 def time_level(h, lvl: int, reps: int = 5, inner: int = 3) -> float:
@@ -51,9 +77,12 @@ def time_level(h, lvl: int, reps: int = 5, inner: int = 3) -> float:
     return times[len(times) // 2]
 
 
-def tune(h, candidates=CANDIDATES, reps: int = 5, cache: str | None = None, use_cache: bool = False):
-    """Pick each level's blocks_per_cu; sets it on the hierarchy and returns
-    {"shapes": [...], "ms": [[candidate ms...] per level], "keys": [...]}.
+def tune(h, candidates=None, reps: int = 5, cache: str | None = None, use_cache: bool = False):
+    """Pick each level's launch shape; sets it on the hierarchy and returns
+    {"shapes": [(blocks_per_cu, threads, batch) per level], "candidates":
+    [[shape...] per level], "ms": [[ms per candidate] per level], "keys": [...]}.
+    candidates: None (level_candidates of each level) or one list of shapes
+    (ints: blocks per CU at the default threads and batch) for every level.
 
     The timing runs advance the levels' state (it is a real update); tune
     before the measured run, not inside it."""
@@ -64,22 +93,25 @@ def tune(h, candidates=CANDIDATES, reps: int = 5, cache: str | None = None, use_
             store = json.load(open(path))
         except (OSError, ValueError):
             store = {}
-    shapes, table, keys = [], [], []
+    shapes, table, cands, keys = [], [], [], []
     for lvl in range(len(h.levels)):
-        key = level_key(h, lvl)
+        cl = [shape(c) for c in (candidates if candidates is not None else level_candidates(n_listed(h, lvl)))]
+        key = level_key(h, lvl) + "|" + ",".join("%d/%d/%d" % c for c in cl)
         keys.append(key)
         if use_cache and key in store:
-            shapes.append(int(store[key]["blocks_per_cu"]))
+            shapes.append(tuple(store[key]["shape"]))
             table.append(store[key]["ms"])
+            cands.append(cl)
             continue
         ms = []
-        for b in candidates:
-            h.solvers[lvl].set_launch(b)
+        for c in cl:
+            h.solvers[lvl].set_launch(*c)
             ms.append(time_level(h, lvl, reps))
-        best = candidates[min(range(len(ms)), key=ms.__getitem__)]
-        shapes.append(int(best))
+        best = cl[min(range(len(ms)), key=ms.__getitem__)]
+        shapes.append(best)
         table.append(ms)
-        store[key] = {"blocks_per_cu": int(best), "candidates": list(candidates), "ms": ms}
+        cands.append(cl)
+        store[key] = {"shape": list(best), "candidates": [list(c) for c in cl], "ms": ms}
     h.set_launch(shapes)
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -87,4 +119,4 @@ def tune(h, candidates=CANDIDATES, reps: int = 5, cache: str | None = None, use_
             json.dump(store, f, indent=1, sort_keys=True)
     except OSError:
         pass
-    return {"shapes": shapes, "candidates": list(candidates), "ms": table, "keys": keys}
+    return {"shapes": shapes, "candidates": cands, "ms": table, "keys": keys}

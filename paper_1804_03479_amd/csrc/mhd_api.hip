@@ -71,6 +71,8 @@ struct mhd_ctx_s {
   long long cap_mlp;      // batch capacity of mlp_ws
   int num_cu;             // compute units of the device
   long long max_blocks;   // cap on stage-kernel grids (0: none)
+  int threads;            // threads per block of the stage kernels (64 .. 512)
+  int batch;              // group-list batch: groups per launch of the middle stages (0: all)
   hipGraph_t graph;       // captured mhd_advance
   hipGraphExec_t graph_exec;
   mhd_level graph_key;
@@ -185,6 +187,8 @@ Work make_work(const mhd_level* lv, int lo, int hi) {
   w.occ = nullptr;
   w.n_dev = (lv->groups && lv->n_groups > 0) ? lv->n_groups_dev : nullptr;
   w.oshift = 0;
+  w.gbase = 0;
+  w.gcount = 1 << 30;
   w.NS = w.N;
   w.sb = 0;
   w.soff = 0;
@@ -255,10 +259,32 @@ unsigned nblocks(const Work& w) { return (unsigned)((w.items + kBlock - 1) / kBl
 
 // grid of a stage kernel: capped by the context's launch shape
 thread_local long long g_max_blocks = 0;
-unsigned sblocks(const Work& w) {
-  long long b = (w.items + kBlock - 1) / kBlock;
+thread_local int g_threads = kBlock;
+unsigned sblocks(const Work& w, int threads = g_threads) {
+  long long b = (w.items + threads - 1) / threads;
   if (g_max_blocks > 0 && b > g_max_blocks) b = g_max_blocks;
+  if (b < 1) b = 1;
   return (unsigned)b;
+}
+
+// Batches of a group list: the middle stages (between the primitive pass,
+// which also reduces the CFL maximum over the whole list, and the final
+// update, which writes the level in place) run batch by batch, each batch
+// of at most `batch` groups through all of them, so a batch's intermediates
+// can still be in the chip's caches when the next stage reads them.  Each
+// group's scratch box holds its own halo, so batches are independent.
+int num_batches(const Work& w, int batch) {
+  if (!w.groups || batch <= 0) return 1;
+  const long long n = w.items / ((long long)w.box * w.box * w.box);
+  return (int)((n + batch - 1) / batch);
+}
+Work batch_of(Work w, int b, int batch) {
+  if (!w.groups || batch <= 0) return w;
+  const long long n = w.items / ((long long)w.box * w.box * w.box);
+  w.gbase = b * batch;
+  w.gcount = (int)(n - w.gbase < batch ? n - w.gbase : batch);
+  w.items = (long long)w.gcount * w.box * w.box * w.box;
+  return w;
 }
 
 // Stage names in launch order (used by mhd_profile_step).
@@ -310,22 +336,28 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
   mark(0);
   if (cfl) {
     k_reset_smax<<<1, 1, 0, st>>>(c->smax);
-    k_prim<T, true, MIX, L><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
+    k_prim<T, true, MIX, L><<<sblocks(wp), g_threads, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   } else {
-    k_prim<T, false, MIX, L><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
+    k_prim<T, false, MIX, L><<<sblocks(wp), g_threads, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   }
   mark(1);
-  k_flux<T, 0, S, L><<<sblocks(wf1), kBlock, 0, st>>>(wf1, W, B, F, gam, c->nfb);
-  mark(2);
-  k_emf<T, L><<<sblocks(we1), kBlock, 0, st>>>(we1, F, W, E);
-  mark(3);
-  k_half<T, MIX, L><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F, E, dts, inv_dx, gam, W, Bh);
-  mark(4);
-  k_flux<T, R, S, L><<<sblocks(wf2), kBlock, 0, st>>>(wf2, W, Bh, F, gam, c->nfb);
-  mark(5);
-  k_emf<T, L><<<sblocks(we2), kBlock, 0, st>>>(we2, F, W, E);
-  mark(6);
-  k_final<T, MIX, L><<<sblocks(wu), kBlock, 0, st>>>(wu, U, B, mix, F, E, dts, inv_dx);
+  const int nt = g_threads;
+  const int batch = ev ? 0 : c->batch;   // profiling times whole stages
+  for (int b = 0; b < num_batches(wf1, batch); ++b) {
+    const Work f1 = batch_of(wf1, b, batch), e1 = batch_of(we1, b, batch), h = batch_of(wh, b, batch);
+    const Work f2 = batch_of(wf2, b, batch), e2 = batch_of(we2, b, batch);
+    k_flux<T, 0, S, L><<<sblocks(f1), nt, 0, st>>>(f1, W, B, F, gam, c->nfb);
+    mark(2);
+    k_emf<T, L><<<sblocks(e1), nt, 0, st>>>(e1, F, W, E);
+    mark(3);
+    k_half<T, MIX, L><<<sblocks(h), nt, 0, st>>>(h, U, B, mix, F, E, dts, inv_dx, gam, W, Bh);
+    mark(4);
+    k_flux<T, R, S, L><<<sblocks(f2), nt, 0, st>>>(f2, W, Bh, F, gam, c->nfb);
+    mark(5);
+    k_emf<T, L><<<sblocks(e2), nt, 0, st>>>(e2, F, W, E);
+    mark(6);
+  }
+  k_final<T, MIX, L><<<sblocks(wu), nt, 0, st>>>(wu, U, B, mix, F, E, dts, inv_dx);
   mark(7);
 }
 
@@ -367,52 +399,59 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
   mark(0);
   if (cfl) {
     k_reset_smax<<<1, 1, 0, st>>>(c->smax);
-    k_prim<T, true, MIX, L><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
+    k_prim<T, true, MIX, L><<<sblocks(wp), g_threads, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   } else {
-    k_prim<T, false, MIX, L><<<sblocks(wp), kBlock, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
+    k_prim<T, false, MIX, L><<<sblocks(wp), g_threads, 0, st>>>(wp, U, B, mix, W, gam, c->smax, c->flag);
   }
   mark(1);
-  // the HLL-family solvers (HLLE, HLLD, the learned flux standing in for
-  // HLLD) take every wave in the tracing, Roe only those moving toward an edge
-  k_ctu_states<T, R, S != 0, L><<<sblocks(wq), kBlock, 0, st>>>(wq, W, B, QL, QR, dts, inv_dx, gam);
-  mark(2);
   constexpr bool kMlp = S == 3 && std::is_same<T, float>::value;
   const float dp = (float)c->cfg.mlp_dp, drho = (float)c->cfg.mlp_drho;
-  if constexpr (kMlp) {
-    const unsigned nb = sblocks(wf1);
-    const long long n7 = 7LL * wf1.NS;
-    k_flux_dir_mlp<0, false, L><<<nb, kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb,
-                                                  c->capture);
-    k_flux_dir_mlp<1, false, L><<<nb, kBlock, 0, st>>>(wf1, QL + n7, QR + n7, B, F1, gam, c->mlpw, dp, drho, c->nfb,
-                                                  c->capture);
-    k_flux_dir_mlp<2, false, L><<<nb, kBlock, 0, st>>>(wf1, QL + 2 * n7, QR + 2 * n7, B, F1, gam, c->mlpw, dp, drho, c->nfb,
-                                                  c->capture);
-  } else
-    k_flux_q<T, S, L><<<sblocks(wf1), kBlock, 0, st>>>(wf1, QL, QR, B, F1, gam, c->nfb, c->capture);
-  mark(3);
-  k_emf<T, L><<<sblocks(we1), kBlock, 0, st>>>(we1, F1, W, E);
-  mark(4);
-  k_half<T, MIX, L><<<sblocks(wh), kBlock, 0, st>>>(wh, U, B, mix, F1, E, dts, inv_dx, gam, W, Bh);
-  mark(5);
-  if constexpr (kMlp) {
-    float* Qc = (float*)sb.Qc;
-    const unsigned nb = sblocks(wf2);
-    k_ctu_correct_dir<0, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
-    k_flux_dir_mlp<0, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
-                                                  c->capture);
-    k_ctu_correct_dir<1, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
-    k_flux_dir_mlp<1, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
-                                                  c->capture);
-    k_ctu_correct_dir<2, L><<<nb, kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
-    k_flux_dir_mlp<2, true, L><<<nb, kBlock, 0, st>>>(wf2, Qc, Qc + 7 * wf2.NS, Bh, F2, gam, c->mlpw, dp, drho, c->nfb,
-                                                  c->capture);
-  } else
-    k_ctu_correct<T, S, L><<<sblocks(wf2), kBlock, 0, st>>>(wf2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam,
-                                                             c->nfb, c->capture);
-  mark(6);
-  k_emf<T, L><<<sblocks(we2), kBlock, 0, st>>>(we2, F2, W, E);
-  mark(7);
-  k_final<T, MIX, L><<<sblocks(wu), kBlock, 0, st>>>(wu, U, B, mix, F2, E, dts, inv_dx);
+  const int nt = g_threads;
+  const int batch = ev ? 0 : c->batch;   // profiling times whole stages
+  for (int b = 0; b < num_batches(wq, batch); ++b) {
+    const Work q = batch_of(wq, b, batch), f1 = batch_of(wf1, b, batch), e1 = batch_of(we1, b, batch);
+    const Work h = batch_of(wh, b, batch), f2 = batch_of(wf2, b, batch), e2 = batch_of(we2, b, batch);
+    // the HLL-family solvers (HLLE, HLLD, the learned flux standing in for
+    // HLLD) take every wave in the tracing, Roe only those moving toward an edge
+    k_ctu_states<T, R, S != 0, L><<<sblocks(q), nt, 0, st>>>(q, W, B, QL, QR, dts, inv_dx, gam);
+    mark(2);
+    if constexpr (kMlp) {
+      // the network kernels keep 256-thread blocks (one LDS stage per wave)
+      const unsigned nb = sblocks(f1, kBlock);
+      const long long n7 = 7LL * f1.NS;
+      k_flux_dir_mlp<0, false, L><<<nb, kBlock, 0, st>>>(f1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb,
+                                                         c->capture);
+      k_flux_dir_mlp<1, false, L><<<nb, kBlock, 0, st>>>(f1, QL + n7, QR + n7, B, F1, gam, c->mlpw, dp, drho,
+                                                         c->nfb, c->capture);
+      k_flux_dir_mlp<2, false, L><<<nb, kBlock, 0, st>>>(f1, QL + 2 * n7, QR + 2 * n7, B, F1, gam, c->mlpw, dp,
+                                                         drho, c->nfb, c->capture);
+    } else
+      k_flux_q<T, S, L><<<sblocks(f1), nt, 0, st>>>(f1, QL, QR, B, F1, gam, c->nfb, c->capture);
+    mark(3);
+    k_emf<T, L><<<sblocks(e1), nt, 0, st>>>(e1, F1, W, E);
+    mark(4);
+    k_half<T, MIX, L><<<sblocks(h), nt, 0, st>>>(h, U, B, mix, F1, E, dts, inv_dx, gam, W, Bh);
+    mark(5);
+    if constexpr (kMlp) {
+      float* Qc = (float*)sb.Qc;
+      const unsigned nc = sblocks(f2), nb = sblocks(f2, kBlock);
+      k_ctu_correct_dir<0, L><<<nc, nt, 0, st>>>(f2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
+      k_flux_dir_mlp<0, true, L><<<nb, kBlock, 0, st>>>(f2, Qc, Qc + 7 * f2.NS, Bh, F2, gam, c->mlpw, dp, drho,
+                                                        c->nfb, c->capture);
+      k_ctu_correct_dir<1, L><<<nc, nt, 0, st>>>(f2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
+      k_flux_dir_mlp<1, true, L><<<nb, kBlock, 0, st>>>(f2, Qc, Qc + 7 * f2.NS, Bh, F2, gam, c->mlpw, dp, drho,
+                                                        c->nfb, c->capture);
+      k_ctu_correct_dir<2, L><<<nc, nt, 0, st>>>(f2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
+      k_flux_dir_mlp<2, true, L><<<nb, kBlock, 0, st>>>(f2, Qc, Qc + 7 * f2.NS, Bh, F2, gam, c->mlpw, dp, drho,
+                                                        c->nfb, c->capture);
+    } else
+      k_ctu_correct<T, S, L><<<sblocks(f2), nt, 0, st>>>(f2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->nfb,
+                                                          c->capture);
+    mark(6);
+    k_emf<T, L><<<sblocks(e2), nt, 0, st>>>(e2, F2, W, E);
+    mark(7);
+  }
+  k_final<T, MIX, L><<<sblocks(wu), nt, 0, st>>>(wu, U, B, mix, F2, E, dts, inv_dx);
   mark(8);
 }
 
@@ -452,6 +491,7 @@ void launch_step_t(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEv
 // the stage kernels of one step on the given scratch
 int run_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev, const StepBufs& sb) {
   g_max_blocks = c->max_blocks;
+  g_threads = c->threads;
   if (c->cfg.prec == MHD_F64) launch_step_t<double, false>(c, lv, dts, cfl, ev, sb);
   else if (c->cfg.prec == MHD_F32) launch_step_t<float, false>(c, lv, dts, cfl, ev, sb);
   else launch_step_t<float, true>(c, lv, dts, cfl, ev, sb);
@@ -572,6 +612,8 @@ int mhd_init(const mhd_config* cfg, void* hip_stream, mhd_ctx* out) {
   c->stream = (hipStream_t)hip_stream;
   HIP_TRY(hipGetDevice(&c->device));
   c->elem = cfg->prec == MHD_F64 ? sizeof(double) : sizeof(float);
+  c->threads = kBlock;
+  c->batch = 0;
   {
     // this device's copy of the static scratch array, looked up once per device
     std::lock_guard<std::mutex> lock(g_static_mutex);
@@ -762,9 +804,13 @@ static void drop_graph(mhd_ctx_s* c) {
   c->graph = nullptr;
 }
 
-int mhd_set_launch(mhd_ctx c, int blocks_per_cu) {
-  if (!c || blocks_per_cu < 0) return MHD_ERR_INVALID_ARG;
+int mhd_set_launch(mhd_ctx c, int blocks_per_cu, int threads_per_block, int batch_groups) {
+  if (!c || blocks_per_cu < 0 || batch_groups < 0) return MHD_ERR_INVALID_ARG;
+  if (threads_per_block == 0) threads_per_block = kBlock;
+  if (threads_per_block < 64 || threads_per_block > kMaxBlock || threads_per_block % 64) return MHD_ERR_INVALID_ARG;
   c->max_blocks = blocks_per_cu > 0 ? (long long)blocks_per_cu * c->num_cu : 0;
+  c->threads = threads_per_block;
+  c->batch = batch_groups;
   drop_graph(c);
   return MHD_OK;
 }

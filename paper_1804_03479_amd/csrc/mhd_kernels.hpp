@@ -28,7 +28,8 @@
 
 namespace mhd {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 256;      // threads per block of the fixed-shape kernels
+constexpr int kMaxBlock = 512;   // largest block of the step's stage kernels (tuned per context)
 
 struct Work {
   int nx, ny, nz;
@@ -41,6 +42,8 @@ struct Work {
   const int* occ;       // group occupancy map (list mode), gnx*gny*gnz
   int gnx, gny, gnz;    // groups per dimension
   const int* n_dev;     // list mode: number of groups read from device memory, or nullptr
+  int gbase;            // list mode: first group of this launch (a batch of the list)
+  int gcount;           // list mode: groups of this launch at most
   int oshift;           // list mode: group origins are divided by 2^oshift (coarse footprint)
   // Stage scratch (W, F, E, Q, Bh, ...) addressing.  Whole grid: like the
   // level (slot = cell index, stride N).  Group list: each group owns a
@@ -80,20 +83,21 @@ __device__ __forceinline__ unsigned block_rank() {
   return b < (q << 3) ? (b & 7u) * q + (b >> 3) : b;
 }
 
-__device__ __forceinline__ long long block_linear_id() { return (long long)block_rank() * kBlock + threadIdx.x; }
+__device__ __forceinline__ long long block_linear_id() { return (long long)block_rank() * blockDim.x + threadIdx.x; }
 
 // Persistent launches: a grid of at most a tuned number of blocks walks the
 // work items with a grid-wide stride; the item count of a group list may be
 // read from device memory, so a captured graph replays over a changed list.
 __device__ __forceinline__ long long work_items(const Work& w) {
   if (w.n_dev) {
-    const long long n = *w.n_dev;
+    long long n = (long long)*w.n_dev - w.gbase;
+    n = n < 0 ? 0 : (n > w.gcount ? w.gcount : n);
     const long long m = (long long)w.box * w.box * w.box * n;
     return m < w.items ? m : w.items;
   }
   return w.items;
 }
-__device__ __forceinline__ long long item_stride() { return (long long)gridDim.x * kBlock; }
+__device__ __forceinline__ long long item_stride() { return (long long)gridDim.x * blockDim.x; }
 
 // cell of work item t.  (a, b, c) is the position inside the unit's box (the
 // cell itself for a whole grid).
@@ -111,9 +115,10 @@ __device__ __forceinline__ void cell_of(const Work& w, long long t, int& i, int&
     a = l % w.box;
     b = (l / w.box) % w.box;
     c = l / (w.box * w.box);
-    i = wrapc((w.groups[3 * g + 0] >> w.oshift) - w.halo + a, w.nx);
-    j = wrapc((w.groups[3 * g + 1] >> w.oshift) - w.halo + b, w.ny);
-    k = wrapc((w.groups[3 * g + 2] >> w.oshift) - w.halo + c, w.nz);
+    const int* o = w.groups + 3LL * (w.gbase + g);
+    i = wrapc((o[0] >> w.oshift) - w.halo + a, w.nx);
+    j = wrapc((o[1] >> w.oshift) - w.halo + b, w.ny);
+    k = wrapc((o[2] >> w.oshift) - w.halo + c, w.nz);
   }
 }
 
@@ -131,7 +136,7 @@ __device__ __forceinline__ Site site_of(const Work& w, long long t) {
   st.p = lin(w, st.i, st.j, st.k);
   if constexpr (L) {
     const long long per = (long long)w.box * w.box * w.box;
-    const long long g = t / per;
+    const long long g = t / per + w.gbase;
     const long long sb = w.sb;
     st.s = (g + 1) * sb * sb * sb + ((long long)(st.c + w.soff) * sb + (st.b + w.soff)) * sb + (st.a + w.soff);
   } else {
@@ -252,14 +257,14 @@ __device__ __forceinline__ double signal_speed(const T q[8], T gam) {
 }
 
 __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* smax) {
-  __shared__ double red[kBlock / 64];
+  __shared__ double red[kMaxBlock / 64];
   v = wave_max(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) red[wid] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = red[0];
-    for (int q = 1; q < kBlock / 64; ++q) m = fmax(m, red[q]);
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, red[q]);
     // most blocks see a maximum already reached: skip their atomic
     const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
     if (m > 0.0 && bits > *(volatile unsigned long long*)smax) atomicMax(smax, bits);
@@ -269,7 +274,7 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* s
 // Primitive state of every cell; optionally the CFL maximum signal speed and
 // the sticky non-physical flag.
 template <typename T, bool CFL, bool MIX, bool L>
-__global__ void __launch_bounds__(kBlock) k_prim(Work w, const T* __restrict__ U, const T* __restrict__ B, Mix mix,
+__global__ void __launch_bounds__(kMaxBlock) k_prim(Work w, const T* __restrict__ U, const T* __restrict__ B, Mix mix,
                                                  T* __restrict__ W, T gam, unsigned long long* smax,
                                                  int* flag) {
   double s = 0.0;
@@ -388,7 +393,7 @@ __device__ __forceinline__ int face_flux(const Work& w, const T* __restrict__ W,
 }
 
 __device__ __forceinline__ void block_count_atomic(int v, unsigned long long* counter) {
-  __shared__ int red[kBlock / 64];
+  __shared__ int red[kMaxBlock / 64];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -396,7 +401,7 @@ __device__ __forceinline__ void block_count_atomic(int v, unsigned long long* co
   __syncthreads();
   if (threadIdx.x == 0) {
     int s = 0;
-    for (int q = 0; q < kBlock / 64; ++q) s += red[q];
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
     if (s) atomicAdd(counter, (unsigned long long)s);
   }
 }
@@ -404,7 +409,7 @@ __device__ __forceinline__ void block_count_atomic(int v, unsigned long long* co
 // VL flux stage; B is the level's field for RECON 0 and the half-step
 // scratch Bh for RECON 1 and 2 (see face_flux).
 template <typename T, int RECON, int SOLVER, bool L>
-__global__ void __launch_bounds__(kBlock) k_flux(Work w, const T* __restrict__ W, const T* __restrict__ B,
+__global__ void __launch_bounds__(kMaxBlock) k_flux(Work w, const T* __restrict__ W, const T* __restrict__ B,
                                                  T* __restrict__ F, T gam, unsigned long long* nfb) {
   int fb = 0;
   FOR_ITEMS(w, t) {
@@ -459,7 +464,7 @@ __device__ __forceinline__ T edge_emf(const Work& w, const T* __restrict__ F, co
 }
 
 template <typename T, bool L>
-__global__ void __launch_bounds__(kBlock) k_emf(Work w, const T* __restrict__ F, const T* __restrict__ W,
+__global__ void __launch_bounds__(kMaxBlock) k_emf(Work w, const T* __restrict__ F, const T* __restrict__ W,
                                                 T* __restrict__ E) {
   FOR_ITEMS(w, t) {
     const Site st = site_of<L>(w, t);
@@ -521,7 +526,7 @@ __device__ __forceinline__ void face_update(const Work& w, const T* __restrict__
 // and EMFs, written as primitives Wh (cell-centred field from the updated
 // faces, including the upper faces owned by the neighbours) and Bh.
 template <typename T, bool MIX, bool L>
-__global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U, const T* __restrict__ B, Mix mix,
+__global__ void __launch_bounds__(kMaxBlock) k_half(Work w, const T* __restrict__ U, const T* __restrict__ B, Mix mix,
                                                  const T* __restrict__ F, const T* __restrict__ E, DtSrc dts,
                                                  T inv_dx, T gam, T* __restrict__ Wh, T* __restrict__ Bh) {
   const T r = T(0.5 * get_dt(dts)) * inv_dx;
@@ -559,7 +564,7 @@ __global__ void __launch_bounds__(kBlock) k_half(Work w, const T* __restrict__ U
 // listed (occupancy map), so every face of a listed group advances exactly
 // once and no face is read after another thread has written it.
 template <typename T, bool MIX, bool L>
-__global__ void __launch_bounds__(kBlock) k_final(Work w, T* __restrict__ U, T* __restrict__ B, Mix mix,
+__global__ void __launch_bounds__(kMaxBlock) k_final(Work w, T* __restrict__ U, T* __restrict__ B, Mix mix,
                                                   const T* __restrict__ F, const T* __restrict__ E, DtSrc dts,
                                                   T inv_dx) {
   const T r = T(get_dt(dts)) * inv_dx;
@@ -625,7 +630,7 @@ __device__ __forceinline__ void cell_states(const Work& w, const T* __restrict__
 
 // ALLW: trace waves moving away from an edge too (HLL-family solvers)
 template <typename T, int RECON, bool ALLW, bool L>
-__global__ void __launch_bounds__(kBlock) k_ctu_states(Work w, const T* __restrict__ W, const T* __restrict__ B,
+__global__ void __launch_bounds__(kMaxBlock) k_ctu_states(Work w, const T* __restrict__ W, const T* __restrict__ B,
                                                        T* __restrict__ QL, T* __restrict__ QR, DtSrc dts,
                                                        T inv_dx, T gam) {
   const T dtdx = T(get_dt(dts)) * inv_dx;
@@ -652,7 +657,7 @@ __device__ __forceinline__ void store_flux(T* __restrict__ F, long long N, long 
 
 // Step 2: Riemann fluxes from the stored states with the time-n normal field
 template <typename T, int SOLVER, bool L>
-__global__ void __launch_bounds__(kBlock) k_flux_q(Work w, const T* __restrict__ QL, const T* __restrict__ QR,
+__global__ void __launch_bounds__(kMaxBlock) k_flux_q(Work w, const T* __restrict__ QL, const T* __restrict__ QR,
                                                    const T* __restrict__ B, T* __restrict__ F, T gam,
                                                    unsigned long long* nfb, Capture cp) {
   int fb = 0;
@@ -784,7 +789,7 @@ __device__ __forceinline__ int corrected_face_flux(const Work& w, const T* __res
 
 // Steps 5-6: corrected states and Riemann fluxes with the half-step normal field
 template <typename T, int SOLVER, bool L>
-__global__ void __launch_bounds__(kBlock) k_ctu_correct(Work w, const T* __restrict__ QL, const T* __restrict__ QR,
+__global__ void __launch_bounds__(kMaxBlock) k_ctu_correct(Work w, const T* __restrict__ QL, const T* __restrict__ QR,
                                                         const T* __restrict__ F1, const T* __restrict__ E1,
                                                         const T* __restrict__ B, const T* __restrict__ Bh,
                                                         T* __restrict__ F2, DtSrc dts, T inv_dx, T gam,
@@ -805,7 +810,7 @@ __global__ void __launch_bounds__(kBlock) k_ctu_correct(Work w, const T* __restr
 // then the network (or HLLD at strong jumps) turns them into fluxes.  Split
 // so that neither kernel holds the correction and the network at once.
 template <int D, bool L>
-__global__ void __launch_bounds__(kBlock) k_ctu_correct_dir(Work w, const float* __restrict__ QL,
+__global__ void __launch_bounds__(kMaxBlock) k_ctu_correct_dir(Work w, const float* __restrict__ QL,
                                                             const float* __restrict__ QR, const float* __restrict__ F1,
                                                             const float* __restrict__ E1, const float* __restrict__ B,
                                                             const float* __restrict__ Bh, float* __restrict__ Qc,

@@ -14,7 +14,7 @@ import oracle  # noqa: E402
 from oracle import amr as oamr  # noqa: E402
 from paper_1804_03479_amd import inputs  # noqa: E402
 from paper_1804_03479_amd.amr import Hierarchy, nested_groups  # noqa: E402
-from paper_1804_03479_amd.mhd import Level, Solver  # noqa: E402
+from paper_1804_03479_amd.mhd import Level, MHDError, Solver  # noqa: E402
 
 
 def lvl(U, B, dx, dtype=torch.float64, groups=None):
@@ -22,14 +22,14 @@ def lvl(U, B, dx, dtype=torch.float64, groups=None):
                  torch.from_numpy(B).to("cuda", dtype).contiguous(), dx, groups=groups)
 
 
-@pytest.mark.parametrize("blocks_per_cu", [0, 1, 3])
-def test_launch_shape_does_not_change_results(blocks_per_cu):
+@pytest.mark.parametrize("shape", [(0, 0, 0), (1, 0, 0), (3, 0, 0), (0, 64, 0), (0, 512, 0), (2, 128, 0)])
+def test_launch_shape_does_not_change_results(shape):
     p = inputs.abc_problem(32, 0.1, seed=4)
     U, B = oracle.initial_state(p)
     ref = Solver("ctu", "ppm", "hlld")
     a = lvl(U, B, p["dx"])
     s = Solver("ctu", "ppm", "hlld")
-    s.set_launch(blocks_per_cu)
+    s.set_launch(*shape)
     b = lvl(U, B, p["dx"])
     for _ in range(3):
         ref.advance(a)
@@ -164,6 +164,32 @@ def test_hierarchy_graph_replay_matches_eager(subcycle):
             assert torch.equal(a.U, b.U) and torch.equal(a.B, b.B), rep
 
 
+@pytest.mark.parametrize("scheme, recon, solver", [("ctu", "ppm", "hlld"), ("vl", "plm", "roe"), ("vl", "ppm", "hlld")])
+@pytest.mark.parametrize("shape", [(0, 0, 1), (2, 512, 3), (0, 64, 5), (1, 256, 8)])
+def test_group_batches_do_not_change_results(scheme, recon, solver, shape):
+    # a list of 7 groups stepped with the whole list per launch and in batches
+    p = inputs.abc_problem(64, 0.1, seed=5)
+    U, B = oracle.initial_state(p)
+    g = torch.tensor([(0, 0, 0), (16, 0, 0), (48, 16, 0), (0, 32, 16), (32, 32, 32), (16, 48, 48), (48, 48, 48)],
+                     dtype=torch.int32, device="cuda")
+    ref = Solver(scheme, recon, solver)
+    s = Solver(scheme, recon, solver)
+    s.set_launch(*shape)
+    a, b = lvl(U, B, p["dx"], groups=g), lvl(U, B, p["dx"], groups=g)
+    for _ in range(2):
+        ref.advance(a)
+        s.advance(b)
+    torch.cuda.synchronize()
+    assert torch.equal(a.U, b.U) and torch.equal(a.B, b.B)
+
+
+def test_invalid_launch_shapes_are_refused():
+    s = Solver("ctu", "ppm", "hlld")
+    for bad in ((-1, 0, 0), (0, 32, 0), (0, 1024, 0), (0, 100, 0), (0, 0, -2)):
+        with pytest.raises(MHDError):
+            s.set_launch(*bad)
+
+
 def test_nested_groups_are_octree_consistent():
     gs = nested_groups(128, [64, 511], edge=16, seed=3)
     assert len(gs[0]) == 64 and len(gs[1]) == 511
@@ -177,7 +203,7 @@ def test_autotuner_picks_a_candidate_and_shapes_keep_results(tmp_path):
     from paper_1804_03479_amd import autotune
     h = Hierarchy(32, [5, 9], prec="f32", seed=4)
     r = autotune.tune(h, candidates=(0, 1, 4), reps=2, cache=str(tmp_path / "tune.json"))
-    assert len(r["shapes"]) == 3 and all(b in (0, 1, 4) for b in r["shapes"])
+    assert len(r["shapes"]) == 3 and all(b[0] in (0, 1, 4) for b in r["shapes"])
     assert all(len(ms) == 3 and min(ms) > 0 for ms in r["ms"])
     again = autotune.tune(h, candidates=(0, 1, 4), cache=str(tmp_path / "tune.json"), use_cache=True)
     assert again["shapes"] == r["shapes"]
@@ -185,7 +211,7 @@ def test_autotuner_picks_a_candidate_and_shapes_keep_results(tmp_path):
     # the tuned shapes give the same bits as the default shape
     a = Hierarchy(32, [5, 9], prec="f32", seed=4)
     b = Hierarchy(32, [5, 9], prec="f32", seed=4)
-    b.set_launch([1, 4, 1])
+    b.set_launch([(1, 512, 0), (4, 128, 2), (1, 64, 3)])
     for _ in range(2):
         a.step()
         b.step()
