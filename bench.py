@@ -175,14 +175,23 @@ def train_surrogate(n_capture: int, seed: int, n_samples: int, epochs: int):
     stride = max(1, (6 * n_capture ** 3 * len(at)) // (2 * n_samples))
     samples = surrogate.capture(n=n_capture, steps=452, noise=0.1, seed=seed + 1, stride=stride,
                                 cap=2 * n_samples, capture_at=at)
+    # strong (near-threshold) faces: a noise-0.3 run once compressions have
+    # formed (its first steps carry velocity jumps only)
+    strong = surrogate.capture(n=n_capture, steps=121, noise=0.3, seed=seed + 2, stride=2,
+                               cap=n_samples, capture_at=[20, 40, 80, 120])
+    samples = torch.cat([samples, strong])
+    del strong
     s = Solver("ctu", "ppm", "mlp", "f32")
     ops = MlpOps(s)
     X, T, info = surrogate.training_set(ops, samples, n_samples, seed=seed)
-    params, hist = surrogate.train(ops, X, T, epochs=epochs, batch=4096, lr0=3e-3, seed=seed)
+    cls = info.pop("cls")
+    params, hist = surrogate.train(ops, X, T, epochs=epochs, batch=4096, lr0=3e-3, seed=seed, cls=cls)
     torch.cuda.synchronize()
     s.close()
     return params, {"samples": n_samples, "captured": int(samples.shape[0]), "epochs": epochs,
-                    "val_loss": hist[-1]["val_loss"], "val_loss_first_epoch": hist[0]["val_loss"],
+                    "val_loss": hist[-1]["val_loss"], "val_loss_smooth": hist[-1].get("val_loss_smooth"),
+                    "val_loss_strong": hist[-1].get("val_loss_strong"),
+                    "val_loss_first_epoch": hist[0]["val_loss"],
                     "seconds": round(_t.perf_counter() - t0, 2), "mix": info}
 
 
@@ -560,8 +569,8 @@ def main():
     ap.add_argument("--l1-steps", type=int, default=200,
                     help="steps of the FP32 / mixed forms against the FP64 form (precision form)")
     ap.add_argument("--mlp-l1-steps", type=int, default=500, help="steps of the MLP form against pure HLLD")
-    ap.add_argument("--mlp-samples", type=int, default=2_000_000)
-    ap.add_argument("--mlp-epochs", type=int, default=60)
+    ap.add_argument("--mlp-samples", type=int, default=10_000_000)
+    ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--amr-counts", default="511,1024",
                     help="patch groups (16^3 cells) of each refined level; also runs 7,64")
     ap.add_argument("--no-tune", action="store_true")

@@ -433,17 +433,13 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
     k_half<T, MIX, L><<<sblocks(h), nt, 0, st>>>(h, U, B, mix, F1, E, dts, inv_dx, gam, W, Bh);
     mark(5);
     if constexpr (kMlp) {
-      float* Qc = (float*)sb.Qc;
-      const unsigned nc = sblocks(f2), nb = sblocks(f2, kBlock);
-      k_ctu_correct_dir<0, L><<<nc, nt, 0, st>>>(f2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
-      k_flux_dir_mlp<0, true, L><<<nb, kBlock, 0, st>>>(f2, Qc, Qc + 7 * f2.NS, Bh, F2, gam, c->mlpw, dp, drho,
-                                                        c->nfb, c->capture);
-      k_ctu_correct_dir<1, L><<<nc, nt, 0, st>>>(f2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
-      k_flux_dir_mlp<1, true, L><<<nb, kBlock, 0, st>>>(f2, Qc, Qc + 7 * f2.NS, Bh, F2, gam, c->mlpw, dp, drho,
-                                                        c->nfb, c->capture);
-      k_ctu_correct_dir<2, L><<<nc, nt, 0, st>>>(f2, QL, QR, F1, E, B, Bh, Qc, dts, inv_dx, gam);
-      k_flux_dir_mlp<2, true, L><<<nb, kBlock, 0, st>>>(f2, Qc, Qc + 7 * f2.NS, Bh, F2, gam, c->mlpw, dp, drho,
-                                                        c->nfb, c->capture);
+      const unsigned nb = sblocks(f2, kBlock);
+      k_ctu_correct_mlp<0, L><<<nb, kBlock, 0, st>>>(f2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->mlpw, dp,
+                                                     drho, c->nfb, c->capture);
+      k_ctu_correct_mlp<1, L><<<nb, kBlock, 0, st>>>(f2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->mlpw, dp,
+                                                     drho, c->nfb, c->capture);
+      k_ctu_correct_mlp<2, L><<<nb, kBlock, 0, st>>>(f2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->mlpw, dp,
+                                                     drho, c->nfb, c->capture);
     } else
       k_ctu_correct<T, S, L><<<sblocks(f2), nt, 0, st>>>(f2, QL, QR, F1, E, B, Bh, F2, dts, inv_dx, gam, c->nfb,
                                                           c->capture);

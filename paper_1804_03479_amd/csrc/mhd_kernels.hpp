@@ -871,6 +871,50 @@ __global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __
   block_count_atomic(fb, nfb);
 }
 
+// Learned-flux form of steps 5-6 for the D-faces in one kernel: each lane
+// corrects its face's two states (as k_ctu_correct does), then the network
+// (or HLLD at strong jumps) gives the flux with the half-step normal field.
+template <int D, bool L>
+__global__ void __launch_bounds__(kBlock) k_ctu_correct_mlp(Work w, const float* __restrict__ QL,
+                                                            const float* __restrict__ QR, const float* __restrict__ F1,
+                                                            const float* __restrict__ E1, const float* __restrict__ B,
+                                                            const float* __restrict__ Bh, float* __restrict__ F2,
+                                                            DtSrc dts, float inv_dx, float gam, const MlpWeights* mw,
+                                                            float dp, float drho, unsigned long long* nfb, Capture cp) {
+  __shared__ MlpShared sh;
+  mlp_load_weights(sh, mw);
+  const float hr = float(0.5 * get_dt(dts)) * inv_dx;
+  const long long NS = w.NS;
+  const long long nitems = work_items(w);
+  int fb = 0;
+  // block-uniform trips: every lane of a wave takes part in the network
+  for (long long base = block_linear_id() - threadIdx.x; base < nitems; base += item_stride()) {
+    const long long t = base + threadIdx.x;
+    const bool active = t < nitems;
+    long long p = 0, s = 0;
+    float wl[7], wr[7], f[7];
+    float bn = 1.0f;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      wl[m] = 1.0f;
+      wr[m] = 1.0f;
+    }
+    if (active) {
+      const Site st = site_of<L>(w, t);
+      p = st.p;
+      s = st.s;
+      bn = Bh[D * NS + s];
+      corrected_states<float, D, L>(w, QL, QR, F1, E1, B, bn, st, hr, gam, wl, wr);
+    }
+    fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
+    if (active) {
+      capture_face(cp, 3 * p + D, wl, wr, bn, f);
+      store_flux<float, D>(F2, NS, s, f);
+    }
+  }
+  block_count_atomic(fb, nfb);
+}
+
 // group occupancy map of a list: clear, then mark
 __global__ void __launch_bounds__(kBlock) k_occ_clear(int* occ, long long n) {
   const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;

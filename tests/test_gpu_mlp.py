@@ -234,7 +234,8 @@ def test_trained_network_gain():
     s = Solver("ctu", "ppm", "mlp", "f32")
     ops = MlpOps(s)
     X, T, info = surrogate.training_set(ops, samples, 2_000_000, seed=0)
-    params, hist = surrogate.train(ops, X, T, epochs=60, batch=4096, lr0=3e-3, seed=0)
+    cls = info.pop("cls")
+    params, hist = surrogate.train(ops, X, T, epochs=60, batch=4096, lr0=3e-3, seed=0, cls=cls)
     assert hist[-1]["val_loss"] < 0.2 * hist[0]["val_loss"]
     ops.set_weights(params)
     s.fallback_count()
