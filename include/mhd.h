@@ -106,7 +106,7 @@ int mhd_required_ghost(int scheme, int recon);
 
 /* Device bytes the context's stage scratch takes to update lv (in
  * *bytes): W, Bh, F, E (35 words per scratch cell; CTU adds QL, QR, F2: 98;
- * the learned flux adds Qc: 112) times the scratch cells (the level's cells,
+ * the learned flux needs no more) times the scratch cells (the level's cells,
  * or (groups + 2) boxes of (edge + 2 ghost)^3 cells for a group list), plus
  * the group occupancy map.  The context allocates this on the first update
  * of a level that needs more than it holds; the time-mean registers of

@@ -48,7 +48,6 @@ struct mhd_ctx_s {
   void* QL;               // CTU: 21 * cap, states below each face
   void* QR;               // CTU: 21 * cap, states above each face
   void* F2;               // CTU: 21 * cap, corrector fluxes
-  void* Qc;               // learned flux: 14 * cap, corrected states of one direction
   void* RF;               // time-averaged final fluxes of a sub-cycled level: 21 * cap_reg
   void* RE;               // time-averaged final EMFs: 3 * cap_reg
   long long cap_reg;
@@ -125,7 +124,7 @@ int check_level(const mhd_ctx_s* ctx, const mhd_level* lv) {
   } while (0)
 
 void free_scratch(mhd_ctx_s* c) {
-  void** bufs[] = {&c->W, &c->Bh, &c->F, &c->E, &c->QL, &c->QR, &c->F2, &c->Qc};
+  void** bufs[] = {&c->W, &c->Bh, &c->F, &c->E, &c->QL, &c->QR, &c->F2};
   for (void** b : bufs) {
     hipFree(*b);
     *b = nullptr;
@@ -142,7 +141,6 @@ int ensure_capacity(mhd_ctx_s* c, long long cells) {
   if (ok && c->cfg.scheme == MHD_CTU)
     ok = hipMalloc(&c->QL, 21 * cells * e) == hipSuccess && hipMalloc(&c->QR, 21 * cells * e) == hipSuccess &&
          hipMalloc(&c->F2, 21 * cells * e) == hipSuccess;
-  if (ok && c->cfg.riemann == MHD_MLP) ok = hipMalloc(&c->Qc, 14 * cells * e) == hipSuccess;
   if (!ok) {
     free_scratch(c);
     return MHD_ERR_OUT_OF_MEMORY;
@@ -301,12 +299,12 @@ const char* stage_name(const mhd_ctx_s* c, int s) {
 // Stage scratch of one step: the context's (allocated on demand) or carved
 // from the static array of the allocation-free entry point.
 struct StepBufs {
-  void *W, *Bh, *F, *E, *QL, *QR, *F2, *Qc;
+  void *W, *Bh, *F, *E, *QL, *QR, *F2;
   int* occ;
 };
 
 StepBufs ctx_bufs(const mhd_ctx_s* c) {
-  return StepBufs{c->W, c->Bh, c->F, c->E, c->QL, c->QR, c->F2, c->Qc, c->occ};
+  return StepBufs{c->W, c->Bh, c->F, c->E, c->QL, c->QR, c->F2, c->occ};
 }
 
 // ev (optional): kNumStages + 1 events recorded around the stage kernels.
@@ -419,11 +417,11 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
       // the network kernels keep 256-thread blocks (one LDS stage per wave)
       const unsigned nb = sblocks(f1, kBlock);
       const long long n7 = 7LL * f1.NS;
-      k_flux_dir_mlp<0, false, L><<<nb, kBlock, 0, st>>>(f1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb,
+      k_flux_dir_mlp<0, L><<<nb, kBlock, 0, st>>>(f1, QL, QR, B, F1, gam, c->mlpw, dp, drho, c->nfb,
                                                          c->capture);
-      k_flux_dir_mlp<1, false, L><<<nb, kBlock, 0, st>>>(f1, QL + n7, QR + n7, B, F1, gam, c->mlpw, dp, drho,
+      k_flux_dir_mlp<1, L><<<nb, kBlock, 0, st>>>(f1, QL + n7, QR + n7, B, F1, gam, c->mlpw, dp, drho,
                                                          c->nfb, c->capture);
-      k_flux_dir_mlp<2, false, L><<<nb, kBlock, 0, st>>>(f1, QL + 2 * n7, QR + 2 * n7, B, F1, gam, c->mlpw, dp,
+      k_flux_dir_mlp<2, L><<<nb, kBlock, 0, st>>>(f1, QL + 2 * n7, QR + 2 * n7, B, F1, gam, c->mlpw, dp,
                                                          drho, c->nfb, c->capture);
     } else
       k_flux_q<T, S, L><<<sblocks(f1), nt, 0, st>>>(f1, QL, QR, B, F1, gam, c->nfb, c->capture);
@@ -512,12 +510,10 @@ constexpr int kMaxDevices = 64;
 std::mutex g_static_mutex;
 unsigned char* g_static_ptr[kMaxDevices];   // per device: its copy's device address
 
-// scratch words per cell of a context's step (W, Bh, F, E; CTU adds QL, QR,
-// F2; the learned flux Qc)
+// scratch words per cell of a context's step (W, Bh, F, E; CTU adds QL, QR, F2)
 long long step_words(const mhd_ctx_s* c) {
   long long words = 8 + 3 + 21 + 3;
   if (c->cfg.scheme == MHD_CTU) words += 63;
-  if (c->cfg.riemann == MHD_MLP) words += 14;
   return words;
 }
 
@@ -528,20 +524,20 @@ size_t align_up(size_t x) { return (x + kStaticAlign - 1) / kStaticAlign * kStat
 size_t carve_static(const mhd_ctx_s* c, const mhd_level* lv, unsigned char* base, StepBufs* sb) {
   const long long cells = scratch_cells(lv, step_ghost(c));
   const size_t e = c->elem;
-  const bool ctu = c->cfg.scheme == MHD_CTU, mlp = c->cfg.riemann == MHD_MLP;
-  const size_t n[8] = {8, 3, 21, 3, ctu ? 21u : 0u, ctu ? 21u : 0u, ctu ? 21u : 0u, mlp ? 14u : 0u};
-  void** dst[8] = {&sb->W, &sb->Bh, &sb->F, &sb->E, &sb->QL, &sb->QR, &sb->F2, &sb->Qc};
+  const bool ctu = c->cfg.scheme == MHD_CTU;
+  const size_t n[7] = {8, 3, 21, 3, ctu ? 21u : 0u, ctu ? 21u : 0u, ctu ? 21u : 0u};
+  void** dst[7] = {&sb->W, &sb->Bh, &sb->F, &sb->E, &sb->QL, &sb->QR, &sb->F2};
   size_t off = 0;
-  size_t at[9];
-  for (int q = 0; q < 8; ++q) {
+  size_t at[8];
+  for (int q = 0; q < 7; ++q) {
     at[q] = off;
     off = align_up(off + n[q] * (size_t)cells * e);
   }
-  at[8] = off;
+  at[7] = off;
   if (list_mode(lv)) off = align_up(off + (size_t)occupancy_cells(lv) * sizeof(int));
   if (off > kStaticScratchBytes) return off;
-  for (int q = 0; q < 8; ++q) *dst[q] = n[q] ? (void*)(base + at[q]) : nullptr;
-  sb->occ = list_mode(lv) ? (int*)(base + at[8]) : nullptr;
+  for (int q = 0; q < 7; ++q) *dst[q] = n[q] ? (void*)(base + at[q]) : nullptr;
+  sb->occ = list_mode(lv) ? (int*)(base + at[7]) : nullptr;
   return off;
 }
 
@@ -584,10 +580,7 @@ int mhd_workspace_bytes(mhd_ctx c, const mhd_level* lv, size_t* bytes) {
   const int rc = check_level(c, lv);
   if (rc) return rc;
   const int ghost = step_ghost(c);
-  long long words = 35;
-  if (c->cfg.scheme == MHD_CTU) words += 63;
-  if (c->cfg.riemann == MHD_MLP) words += 14;
-  long long total = words * scratch_cells(lv, ghost) * (long long)c->elem;
+  long long total = step_words(c) * scratch_cells(lv, ghost) * (long long)c->elem;
   if (list_mode(lv))
     total += (long long)(lv->nx / lv->group_edge) * (lv->ny / lv->group_edge) * (lv->nz / lv->group_edge) *
              (long long)sizeof(int);

@@ -805,35 +805,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_ctu_correct(Work w, const T* __re
   if (SOLVER == 0) block_count_atomic(fb, nfb);
 }
 
-// Learned-flux form of steps 5-6, one direction D per launch pair: the
-// corrected states of the D-faces go to Qc (14 words per cell: L then R),
-// then the network (or HLLD at strong jumps) turns them into fluxes.  Split
-// so that neither kernel holds the correction and the network at once.
+// Learned flux (HLLD at strong jumps) of the D-faces in step 2 from the
+// traced states QLd[m * NS + s], QRd[m * NS + s] (m = 0..6) and the level's
+// time-n normal field B[D * N + p].  With capture on, the face's states and
+// the flux it used are recorded.
 template <int D, bool L>
-__global__ void __launch_bounds__(kMaxBlock) k_ctu_correct_dir(Work w, const float* __restrict__ QL,
-                                                            const float* __restrict__ QR, const float* __restrict__ F1,
-                                                            const float* __restrict__ E1, const float* __restrict__ B,
-                                                            const float* __restrict__ Bh, float* __restrict__ Qc,
-                                                            DtSrc dts, float inv_dx, float gam) {
-  const float hr = float(0.5 * get_dt(dts)) * inv_dx;
-  const long long NS = w.NS;
-  FOR_ITEMS(w, t) {
-    const Site st = site_of<L>(w, t);
-    float wl[7], wr[7];
-    corrected_states<float, D, L>(w, QL, QR, F1, E1, B, Bh[D * NS + st.s], st, hr, gam, wl, wr);
-#pragma unroll
-    for (int m = 0; m < 7; ++m) {
-      Qc[(long long)m * NS + st.s] = wl[m];
-      Qc[(long long)(7 + m) * NS + st.s] = wr[m];
-    }
-  }
-}
-
-// Learned flux (HLLD at strong jumps) of the D-faces from scratch states
-// QLd[m * NS + s], QRd[m * NS + s] (m = 0..6) and the normal field: the level's
-// B[D * N + p] (predictor) or the half-step scratch Bh[D * NS + s] (BN_SCRATCH).
-// With capture on, the face's states and the flux it used are recorded.
-template <int D, bool BN_SCRATCH, bool L>
 __global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __restrict__ QLd,
                                                          const float* __restrict__ QRd, const float* __restrict__ Bn,
                                                          float* __restrict__ F, float gam, const MlpWeights* mw,
@@ -861,7 +837,7 @@ __global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __
       wl[m] = active ? QLd[(long long)m * NS + s] : 1.0f;
       wr[m] = active ? QRd[(long long)m * NS + s] : 1.0f;
     }
-    if (active) bn = BN_SCRATCH ? Bn[D * NS + s] : Bn[D * N + p];
+    if (active) bn = Bn[D * N + p];
     fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
     if (active) {
       capture_face(cp, 3 * p + D, wl, wr, bn, f);
