@@ -26,9 +26,9 @@ from paper_1804_03479_amd.mhd import Solver  # noqa: E402
 from linear_wave import wave_setup  # noqa: E402
 
 
-def l1_error(n, wave):
+def l1_error(n, wave, recon="plm", solver="roe"):
     W5, B, T, dx = wave_setup(n, wave)
-    s = Solver("ctu", "plm", "roe", "f64")
+    s = Solver("ctu", recon, solver, "f64")
     lv = s.level_from_primitives(torch.from_numpy(W5), torch.from_numpy(B), dx)
     U0 = lv.U.cpu().numpy()
     W0 = oracle.cons_to_prim(U0, B)
@@ -48,5 +48,17 @@ def test_linear_waves_converge_at_second_order(wave):
     e = [l1_error(n, wave) for n in (32, 64, 128)]
     order = [math.log2(e[i] / e[i + 1]) for i in range(2)]
     print(wave, e, order)
-    assert e[1] / e[2] > 3.2 and order[1] > order[0], (wave, e)
+    # measured e64 / e128 = 3.54 - 3.58 (order 1.82 - 1.84, rising as the
+    # minmod limiter stops clipping the extrema)
+    assert e[1] / e[2] > 3.4 and order[1] > order[0], (wave, e)
     assert e[2] < 1e-7, (wave, e)     # well below the 1e-6 amplitude (summed over the five fields)
+
+
+@pytest.mark.parametrize("wave", ["slow", "alfven", "fast"])
+def test_benchmark_scheme_linear_waves_converge(wave):
+    # the precision form's scheme, CTU + PPM + HLLD, on the same waves
+    e = [l1_error(n, wave, "ppm", "hlld") for n in (32, 64, 128)]
+    order = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    print("ppm+hlld", wave, e, order)
+    assert e[1] / e[2] > 3.0, (wave, e)
+    assert e[2] < 1e-7, (wave, e)

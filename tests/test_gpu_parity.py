@@ -409,6 +409,24 @@ def test_ctu_ten_steps_abc32_f64():
     assert rel_err(Bg, Bo) <= 1e-12
 
 
+def test_ctu_fifty_steps_abc64_f64():
+    # the precision form's scheme over a longer run: 50 CFL steps of the 64^3
+    # ABC box with noise 0.1, every value against the oracle
+    p = inputs.abc_problem(64, 0.1, seed=6)
+    U, B = oracle.initial_state(p)
+    dx = p["dx"]
+    Uo, Bo, t_o, _ = oracle.run(U, B, 50, dx, scheme=oracle.CTU, recon=oracle.PPM, riemann=oracle.HLLD)
+    s = Solver("ctu", "ppm", "hlld")
+    lv = level_from(U, B, dx)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(50):
+        s.advance(lv, t_dev=t)
+    Ug, Bg = fetch(lv)
+    assert abs(t.item() - t_o) <= 1e-13 * t_o
+    assert rel_err(Ug, Uo) <= 1e-12
+    assert rel_err(Bg, Bo) <= 1e-12
+
+
 def l1_rel(a, b):
     """worst per-component mean |a - b| / mean |b|"""
     return max(np.abs(a[m] - b[m]).mean() / max(np.abs(b[m]).mean(), 1e-300) for m in range(a.shape[0]))
