@@ -261,7 +261,7 @@ def run_amr(n_root: int, counts, steps: int, warmup: int, seed: int, tune: bool)
             "per_level_value": [c / (t * 1e-3) for c, t in zip(cells, per_level)],
             "launch_shapes": None if not tuned else [list(x) for x in tuned["shapes"]],
             "autotune": None if not tuned else [
-                {"shape_fields": ["blocks_per_cu", "threads", "batch"],
+                {"shape_fields": ["blocks_per_cu", "threads", "batch", "lds_tiles"],
                  "table": [list(c) + [round(ms, 4)] for c, ms in zip(cands, mss)]}
                 for cands, mss in zip(tuned["candidates"], tuned["ms"])],
             "max_divb_dx_listed": divb,
@@ -668,6 +668,20 @@ def main():
             forms[f"{key}_{prec}"] = e
         if key != head_key and "stages" in r["f32"]:
             forms[f"{key}_f32"]["stage_ms"] = {k: round(x, 4) for k, x in r["f32"]["stages"].items()}
+
+    if "ctu" in results:
+        # the reconstruction stage on LDS tiles (a launch-shape option): same
+        # bits, timed beside the per-cell form
+        wl = WORKLOADS["ctu"]
+        tiles = {}
+        for prec in ("f32", "f64"):
+            r = run_form(wl, prec, n, args.steps, args.warmup, args.seed, profile=True,
+                         setup=lambda s: s.set_launch(tiles=1))
+            base = results["ctu"][prec]
+            tiles[prec] = {"ms_per_step": round(r["ms_per_step"], 4), "states_ms": round(r["stages"]["states"], 4),
+                           "per_cell_states_ms": round(base["stages"]["states"], 4) if "stages" in base else None,
+                           "step_vs_per_cell": round(base["ms_per_step"] / r["ms_per_step"], 4)}
+        forms["ctu_lds_tiles"] = {"workload": wl["name"].format(n=n), "tile": [16, 4, 4], **tiles}
 
     if args.oracle_l1_steps > 0 and head_key is not None:
         precs = ("f64", "f32", "f32_mixed") if head_key == "ctu" else ("f64", "f32")

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MHD_ABI_VERSION 3
+#define MHD_ABI_VERSION 4
 
 /* status codes */
 #define MHD_OK 0
@@ -184,10 +184,22 @@ int mhd_advance_graph(mhd_ctx ctx, const mhd_level* lv, double* dt_dev, double* 
  *                      so its intermediates can stay in the caches (paper
  *                      Sec. 4 sends patch groups to the GPU in batches);
  *                      0 = the whole list in one launch per stage.
- * Every shape gives bit-identical results.  Drops any captured graph.  The
- * reduction kernels of mhd_divB and mhd_sums and the AMR transfer kernels
- * keep their fixed shape. */
-int mhd_set_launch(mhd_ctx ctx, int blocks_per_cu, int threads_per_block, int batch_groups);
+ *   lds_tiles          CTU with PPM, step 1 (reconstruction and characteristic
+ *                      tracing): 0 = one thread per cell, each computing its
+ *                      own stencil's MC slopes and PPM interface values;
+ *                      1 = blocks of 16 x 4 x 4 cells (20 x 5 x 5 on the item
+ *                      boxes of 16^3 groups; other group sizes keep the
+ *                      per-cell form) that stage their primitives with two
+ *                      ghost layers per direction in LDS and compute each
+ *                      slope and interface value once (fewer VALU
+ *                      instructions, but block barriers between the stages);
+ *                      other configurations ignore it.  The same arithmetic
+ *                      compiled in another code layout: results agree with
+ *                      the per-cell form to rounding, not bit for bit.
+ * For a given lds_tiles, every shape gives bit-identical results.  Drops any
+ * captured graph.  The reduction kernels of mhd_divB and mhd_sums and the
+ * AMR transfer kernels keep their fixed shape. */
+int mhd_set_launch(mhd_ctx ctx, int blocks_per_cu, int threads_per_block, int batch_groups, int lds_tiles);
 
 /* Minimum of scale times the level's CFL time step and *dt_dev, written to
  * *dt_dev, without a host sync: scale 1 on every level gives a shared step;

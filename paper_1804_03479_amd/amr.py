@@ -216,7 +216,8 @@ class Hierarchy:
 
     def set_launch(self, shapes):
         """Launch shape of each level: blocks per CU of the persistent launches
-        (0 = one item per thread), or a (blocks_per_cu, threads, batch) tuple."""
+        (0 = one item per thread), or a (blocks_per_cu, threads, batch[,
+        tiles]) tuple."""
         for s, b in zip(self.solvers, shapes):
             s.set_launch(*(tuple(b) if isinstance(b, (tuple, list)) else (int(b),)))
 

@@ -72,6 +72,7 @@ struct mhd_ctx_s {
   long long max_blocks;   // cap on stage-kernel grids (0: none)
   int threads;            // threads per block of the stage kernels (64 .. 512)
   int batch;              // group-list batch: groups per launch of the middle stages (0: all)
+  int lds_tiles;          // CTU + PPM step 1 on LDS tiles (1) or per cell (0)
   hipGraph_t graph;       // captured mhd_advance
   hipGraphExec_t graph_exec;
   mhd_level graph_key;
@@ -370,6 +371,32 @@ void launch_step(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEven
 //   k_final        U^n, B^n, F2, E      -> U^{n+1}, B^{n+1}   step 8
 // Group halos (cells below, above each group): 4,4 / 2,2 / 2,2 / 1,2 / 1,1 /
 // 1,1 / 0,1 / 0,0, i.e. 4 ghost cells of U^n.
+// CTU step 1 with PPM on LDS tiles: 16 x 4 x 4 cells on a whole grid, 20 x 5
+// x 5 on the 20^3 item boxes of 16^3 groups; false (nothing launched) for
+// other group boxes, which take the per-cell kernel.  The tile kernels
+// have a fixed block of one thread per tile cell.
+template <typename T, bool ALLW, bool L, int TX, int TY, int TZ>
+void launch_tiles(const Work& w, const T* W, const T* B, T* QL, T* QR, DtSrc dts, T inv_dx, T gam, hipStream_t st) {
+  const long long units = L ? w.items / ((long long)w.box * w.box * w.box) : 1;
+  long long nb = units * (L ? unit_tiles<TX, TY, TZ>(w.box, w.box, w.box) : unit_tiles<TX, TY, TZ>(w.nx, w.ny, w.nz));
+  if (g_max_blocks > 0 && nb > g_max_blocks) nb = g_max_blocks;
+  if (nb < 1) nb = 1;
+  k_ctu_states_tiled<T, ALLW, L, TX, TY, TZ><<<(unsigned)nb, TX * TY * TZ, 0, st>>>(w, W, B, QL, QR, dts, inv_dx,
+                                                                                   gam);
+}
+
+template <typename T, bool ALLW, bool L>
+bool launch_states_tiled(const Work& w, const T* W, const T* B, T* QL, T* QR, DtSrc dts, T inv_dx, T gam,
+                         hipStream_t st) {
+  if constexpr (L) {
+    if (w.box != 20) return false;
+    launch_tiles<T, ALLW, L, 20, 5, 5>(w, W, B, QL, QR, dts, inv_dx, gam, st);
+  } else {
+    launch_tiles<T, ALLW, L, 16, 4, 4>(w, W, B, QL, QR, dts, inv_dx, gam, st);
+  }
+  return true;
+}
+
 template <typename T, int S, int R, bool MIX, bool L>
 void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent_t* ev, const StepBufs& sb) {
   const Mix mix{MIX ? lv->E64 : nullptr, c->cfg.beta_fp64};
@@ -411,7 +438,8 @@ void launch_ctu(mhd_ctx_s* c, const mhd_level* lv, DtSrc dts, bool cfl, hipEvent
     const Work h = batch_of(wh, b, batch), f2 = batch_of(wf2, b, batch), e2 = batch_of(we2, b, batch);
     // the HLL-family solvers (HLLE, HLLD, the learned flux standing in for
     // HLLD) take every wave in the tracing, Roe only those moving toward an edge
-    k_ctu_states<T, R, S != 0, L><<<sblocks(q), nt, 0, st>>>(q, W, B, QL, QR, dts, inv_dx, gam);
+    if (R != 1 || !c->lds_tiles || !launch_states_tiled<T, S != 0, L>(q, W, B, QL, QR, dts, inv_dx, gam, st))
+      k_ctu_states<T, R, S != 0, L><<<sblocks(q), nt, 0, st>>>(q, W, B, QL, QR, dts, inv_dx, gam);
     mark(2);
     if constexpr (kMlp) {
       // the network kernels keep 256-thread blocks (one LDS stage per wave)
@@ -603,6 +631,7 @@ int mhd_init(const mhd_config* cfg, void* hip_stream, mhd_ctx* out) {
   c->elem = cfg->prec == MHD_F64 ? sizeof(double) : sizeof(float);
   c->threads = kBlock;
   c->batch = 0;
+  c->lds_tiles = 0;
   {
     // this device's copy of the static scratch array, looked up once per device
     std::lock_guard<std::mutex> lock(g_static_mutex);
@@ -793,13 +822,14 @@ static void drop_graph(mhd_ctx_s* c) {
   c->graph = nullptr;
 }
 
-int mhd_set_launch(mhd_ctx c, int blocks_per_cu, int threads_per_block, int batch_groups) {
-  if (!c || blocks_per_cu < 0 || batch_groups < 0) return MHD_ERR_INVALID_ARG;
+int mhd_set_launch(mhd_ctx c, int blocks_per_cu, int threads_per_block, int batch_groups, int lds_tiles) {
+  if (!c || blocks_per_cu < 0 || batch_groups < 0 || (lds_tiles != 0 && lds_tiles != 1)) return MHD_ERR_INVALID_ARG;
   if (threads_per_block == 0) threads_per_block = kBlock;
   if (threads_per_block < 64 || threads_per_block > kMaxBlock || threads_per_block % 64) return MHD_ERR_INVALID_ARG;
   c->max_blocks = blocks_per_cu > 0 ? (long long)blocks_per_cu * c->num_cu : 0;
   c->threads = threads_per_block;
   c->batch = batch_groups;
+  c->lds_tiles = lds_tiles;
   drop_graph(c);
   return MHD_OK;
 }

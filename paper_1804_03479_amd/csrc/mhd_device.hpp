@@ -384,14 +384,18 @@ __device__ __forceinline__ T mc_slope(T qm, T q0, T qp) {
   return dc > T(0) ? m : -m;
 }
 
-// PPM (Colella & Woodward 1984) edge values of the centre of q0..q4:
-// interface values from MC-limited slopes, then the monotonicity constraints
+// PPM (Colella & Woodward 1984) interface value between cells a and b (a
+// below) from their values and MC-limited slopes
 template <typename T>
-__device__ __forceinline__ void ppm_edges(T q0, T q1, T q2, T q3, T q4, T& ql, T& qr) {
-  const T dm = mc_slope(q0, q1, q2), d0 = mc_slope(q1, q2, q3), dp = mc_slope(q2, q3, q4);
-  T l = T(0.5) * (q1 + q2) - (d0 - dm) * T(1.0 / 6.0);
-  T r = T(0.5) * (q2 + q3) - (dp - d0) * T(1.0 / 6.0);
-  const T c = q2;
+__device__ __forceinline__ T ppm_interface(T qa, T qb, T sa, T sb) {
+  return T(0.5) * (qa + qb) - (sb - sa) * T(1.0 / 6.0);
+}
+
+// PPM monotonicity constraints on a cell's parabola (centre value c, edge
+// values l and r): flat at an extremum, otherwise edges pulled in so the
+// parabola takes no value outside [l, r]
+template <typename T>
+__device__ __forceinline__ void ppm_limit(T c, T& l, T& r) {
   if ((r - c) * (c - l) <= T(0)) {
     l = c;
     r = c;
@@ -400,42 +404,41 @@ __device__ __forceinline__ void ppm_edges(T q0, T q1, T q2, T q3, T q4, T& ql, T
     if (m6 > dq2) l = T(3) * c - T(2) * r;
     else if (-dq2 > m6) r = T(3) * c - T(2) * l;
   }
+}
+
+// PPM edge values of the centre of q0..q4: interface values from
+// MC-limited slopes, then the monotonicity constraints
+template <typename T>
+__device__ __forceinline__ void ppm_edges(T q0, T q1, T q2, T q3, T q4, T& ql, T& qr) {
+  const T dm = mc_slope(q0, q1, q2), d0 = mc_slope(q1, q2, q3), dp = mc_slope(q2, q3, q4);
+  T l = ppm_interface(q1, q2, dm, d0);
+  T r = ppm_interface(q2, q3, d0, dp);
+  ppm_limit(q2, l, r);
   ql = l;
   qr = r;
 }
 
 // Characteristic tracing of one cell for the CTU predictor (Colella 1990):
-// q[s][m] holds the 1D primitive states of cells -2..2 along the direction,
-// (bn_lo, bn_hi) the cell's two normal-face fields.  Each edge state starts
-// at the reconstructed edge value; every wave moving toward that edge
-// subtracts its share of the profile's average over its domain of dependence
-// during dt (xi = lam dt/dx).  ALLW (the HLL-family solvers, which do not
-// resolve every wave): waves moving away are traced as well, with the
-// profile continued past the edge, so both states of a face are
-// time-centred in every field.  RECON: 0 minmod PLM, 1 PPM.  Then the
-// transverse field gets (dt/2) v_t dBn/dn.  A non-physical result falls back
-// to the cell state.  sl: lower edge, sr: upper edge.
-template <typename T, int RECON, bool ALLW>
-__device__ __forceinline__ void trace_cell(const T q[5][7], T bn_lo, T bn_hi, T dtdx, T gam, T sl[7],
-                                           T sr[7]) {
+// c holds the cell's 1D primitive state, sl / sr its reconstructed lower and
+// upper edge values on entry (the profile's two ends) and the traced edge
+// states on return, (bn_lo, bn_hi) the cell's two normal-face fields.  Each
+// edge state starts at the reconstructed edge value; every wave moving
+// toward that edge subtracts its share of the profile's average over its
+// domain of dependence during dt (xi = lam dt/dx).  ALLW (the HLL-family
+// solvers, which do not resolve every wave): waves moving away are traced as
+// well, with the profile continued past the edge, so both states of a face
+// are time-centred in every field.  Then the transverse field gets
+// (dt/2) v_t dBn/dn.  A non-physical result falls back to the cell state.
+template <typename T, bool ALLW>
+__device__ __forceinline__ void trace_edges(const T c[7], T bn_lo, T bn_hi, T dtdx, T gam, T sl[7], T sr[7]) {
   T dq[7], q6[7];
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
-    T l, r;
-    if (RECON == 1) {
-      ppm_edges(q[0][m], q[1][m], q[2][m], q[3][m], q[4][m], l, r);
-    } else {
-      const T s = minmod(q[2][m] - q[1][m], q[3][m] - q[2][m]);
-      l = q[2][m] - T(0.5) * s;
-      r = q[2][m] + T(0.5) * s;
-    }
-    sl[m] = l;
-    sr[m] = r;
-    dq[m] = r - l;
-    q6[m] = T(6) * (q[2][m] - T(0.5) * (l + r));
+    dq[m] = sr[m] - sl[m];
+    q6[m] = T(6) * (c[m] - T(0.5) * (sl[m] + sr[m]));
   }
   // primitive eigen-system of the cell (Roe & Balsara normalisation)
-  const T d = q[2][0], u = q[2][1], p = q[2][4], by = q[2][5], bz = q[2][6];
+  const T d = c[0], u = c[1], p = c[4], by = c[5], bz = c[6];
   const T bn = T(0.5) * (bn_lo + bn_hi);
   const T isd = drsqrt(d), sd = d * isd, id = isd * isd;
   const T asq = gam * p * id, a = dsqrt(asq);
@@ -514,18 +517,36 @@ __device__ __forceinline__ void trace_cell(const T q[5][7], T bn_lo, T bn_hi, T 
   update(sl, T(1), fsL, fdL, ssL, sdL, asL, adL, eL);
   // multidimensional source term of the transverse field
   const T hb = T(0.5) * dtdx * (bn_hi - bn_lo);   // (dt/2) dBn/dn
-  sl[5] += hb * q[2][2];
-  sl[6] += hb * q[2][3];
-  sr[5] += hb * q[2][2];
-  sr[6] += hb * q[2][3];
+  sl[5] += hb * c[2];
+  sl[6] += hb * c[3];
+  sr[5] += hb * c[2];
+  sr[6] += hb * c[3];
   if (!(sl[0] > T(0)) || !(sl[4] > T(0))) {
 #pragma unroll
-    for (int m = 0; m < 7; ++m) sl[m] = q[2][m];
+    for (int m = 0; m < 7; ++m) sl[m] = c[m];
   }
   if (!(sr[0] > T(0)) || !(sr[4] > T(0))) {
 #pragma unroll
-    for (int m = 0; m < 7; ++m) sr[m] = q[2][m];
+    for (int m = 0; m < 7; ++m) sr[m] = c[m];
   }
+}
+
+// trace_cell: the same from the primitive states q[s][m] of cells -2..2
+// along the direction (RECON 0: minmod PLM edges, 1: PPM edges)
+template <typename T, int RECON, bool ALLW>
+__device__ __forceinline__ void trace_cell(const T q[5][7], T bn_lo, T bn_hi, T dtdx, T gam, T sl[7],
+                                           T sr[7]) {
+#pragma unroll
+  for (int m = 0; m < 7; ++m) {
+    if (RECON == 1) {
+      ppm_edges(q[0][m], q[1][m], q[2][m], q[3][m], q[4][m], sl[m], sr[m]);
+    } else {
+      const T s = minmod(q[2][m] - q[1][m], q[3][m] - q[2][m]);
+      sl[m] = q[2][m] - T(0.5) * s;
+      sr[m] = q[2][m] + T(0.5) * s;
+    }
+  }
+  trace_edges<T, ALLW>(q[2], bn_lo, bn_hi, dtdx, gam, sl, sr);
 }
 
 }  // namespace mhd

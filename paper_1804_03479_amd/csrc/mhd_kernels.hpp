@@ -642,6 +642,247 @@ __global__ void __launch_bounds__(kMaxBlock) k_ctu_states(Work w, const T* __res
   }
 }
 
+// ---- step 1 with PPM, tiled in LDS
+//
+// A block owns a TX x TY x TZ tile of a unit (the whole grid, or the item
+// box of one listed group).  Per direction D it stages the tile's 1D
+// primitives with two more cells on each side along D in LDS, computes each
+// MC slope of the padded tile and each PPM interface value of the tile's
+// faces once (the per-cell form computes every slope three times and every
+// interface twice), and then each thread limits and traces its own cell from
+// the shared values.  Every value is computed with the per-cell form's
+// arithmetic, so the states are the same.
+
+// scratch slot of position (a, b, c) of unit gg (a group's item box in list
+// mode, the grid otherwise); positions up to two cells outside the unit
+template <bool L>
+__device__ __forceinline__ long long unit_slot(const Work& w, long long gg, int a, int b, int c) {
+  if constexpr (L) {
+    const long long sb = w.sb;
+    return (gg + 1) * sb * sb * sb + ((long long)(c + w.soff) * sb + (b + w.soff)) * sb + (a + w.soff);
+  } else {
+    return lin(w, wrapc(a, w.nx), wrapc(b, w.ny), wrapc(c, w.nz));
+  }
+}
+
+// the site of position (a, b, c) inside unit gg
+template <bool L>
+__device__ __forceinline__ Site unit_site(const Work& w, long long gg, int a, int b, int c) {
+  Site st;
+  st.a = a; st.b = b; st.c = c;
+  if constexpr (L) {
+    const int* o = w.groups + 3 * gg;
+    st.i = wrapc((o[0] >> w.oshift) - w.halo + a, w.nx);
+    st.j = wrapc((o[1] >> w.oshift) - w.halo + b, w.ny);
+    st.k = wrapc((o[2] >> w.oshift) - w.halo + c, w.nz);
+  } else {
+    st.i = a; st.j = b; st.k = c;
+  }
+  st.p = lin(w, st.i, st.j, st.k);
+  st.s = L ? unit_slot<L>(w, gg, a, b, c) : st.p;
+  return st;
+}
+
+// extents of the tile padded by P cells on each side along D
+template <int TX, int TY, int TZ, int D, int P>
+struct Padded {
+  static constexpr int x = TX + (D == 0 ? 2 * P : 0);
+  static constexpr int y = TY + (D == 1 ? 2 * P : 0);
+  static constexpr int z = TZ + (D == 2 ? 2 * P : 0);
+  static constexpr int n = x * y * z;
+  static constexpr int stride = D == 0 ? 1 : (D == 1 ? x : x * y);   // index step along D
+};
+
+template <int TX, int TY, int TZ, int P>
+constexpr int padded_max() {
+  return Padded<TX, TY, TZ, 0, P>::n > Padded<TX, TY, TZ, 1, P>::n
+             ? (Padded<TX, TY, TZ, 0, P>::n > Padded<TX, TY, TZ, 2, P>::n ? Padded<TX, TY, TZ, 0, P>::n
+                                                                          : Padded<TX, TY, TZ, 2, P>::n)
+             : (Padded<TX, TY, TZ, 1, P>::n > Padded<TX, TY, TZ, 2, P>::n ? Padded<TX, TY, TZ, 1, P>::n
+                                                                          : Padded<TX, TY, TZ, 2, P>::n);
+}
+
+// faces of the tile along its largest direction count
+template <int TX, int TY, int TZ>
+constexpr int faces_max() {
+  return (TX + 1) * TY * TZ > TX * (TY + 1) * TZ
+             ? ((TX + 1) * TY * TZ > TX * TY * (TZ + 1) ? (TX + 1) * TY * TZ : TX * TY * (TZ + 1))
+             : (TX * (TY + 1) * TZ > TX * TY * (TZ + 1) ? TX * (TY + 1) * TZ : TX * TY * (TZ + 1));
+}
+
+// A tile: its unit, its origin in the unit and the unit's extents.
+struct Tile {
+  long long gg;
+  int a0, b0, c0;
+  int ux, uy, uz;
+};
+
+// LDS arrays of one direction D (component-major, [7][n] each): sW the
+// primitives at positions -2 .. T+1 along D (padding 2), sS the MC slopes at
+// -1 .. T (padding 1), sE the interface values at faces 0 .. T (face f
+// between cells f - 1 and f).
+template <int TX, int TY, int TZ, int D>
+struct TileLayout {
+  using PW = Padded<TX, TY, TZ, D, 2>;
+  using PS = Padded<TX, TY, TZ, D, 1>;
+  static constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2), NF = FX * FY * FZ;
+  static constexpr int SF = D == 0 ? 1 : (D == 1 ? FX : FX * FY);
+  static constexpr int NT = TX * TY * TZ;
+  static constexpr int dx = D == 0, dy = D == 1, dz = D == 2;
+};
+
+// padded cell e of direction D: inside the loaded range (within two cells of
+// the unit along D, inside it across)?  Also returns its unit position.
+template <int TX, int TY, int TZ, int D>
+__device__ __forceinline__ bool padded_cell(const Tile& t, int e, int& a, int& b, int& c) {
+  using Ly = TileLayout<TX, TY, TZ, D>;
+  using PW = typename Ly::PW;
+  const int x = e % PW::x, y = (e / PW::x) % PW::y, z = e / (PW::x * PW::y);
+  a = t.a0 + x - 2 * Ly::dx;
+  b = t.b0 + y - 2 * Ly::dy;
+  c = t.c0 + z - 2 * Ly::dz;
+  return a < t.ux + 2 * Ly::dx && b < t.uy + 2 * Ly::dy && c < t.uz + 2 * Ly::dz;
+}
+
+// the padded primitives of direction D into sW
+template <typename T, bool L, int TX, int TY, int TZ, int D>
+__device__ __forceinline__ void stage_prims(const Work& w, const T* __restrict__ W, const Tile& t, int tid, T* sW) {
+  using Ly = TileLayout<TX, TY, TZ, D>;
+  for (int e = tid; e < Ly::PW::n; e += Ly::NT) {
+    int a, b, c;
+    if (padded_cell<TX, TY, TZ, D>(t, e, a, b, c)) {
+      T q[7];
+      load_w1d<T, D>(W, w.NS, unit_slot<L>(w, t.gg, a, b, c), q);
+#pragma unroll
+      for (int m = 0; m < 7; ++m) sW[m * Ly::PW::n + e] = q[m];
+    }
+  }
+}
+
+// slopes and interface values of direction D from the staged primitives
+// (two block barriers)
+template <typename T, int TX, int TY, int TZ, int D>
+__device__ __forceinline__ void tile_interfaces(int tid, const T* sW, T* sS, T* sE) {
+  using Ly = TileLayout<TX, TY, TZ, D>;
+  using PW = typename Ly::PW;
+  using PS = typename Ly::PS;
+  constexpr int dx = Ly::dx, dy = Ly::dy, dz = Ly::dz;
+  // slopes: position -1 + s along D at padded index s; its cell sits one
+  // further in the primitives' padding
+  for (int e = tid; e < PS::n; e += Ly::NT) {
+    const int x = e % PS::x, y = (e / PS::x) % PS::y, z = e / (PS::x * PS::y);
+    const int iw = (x + dx) + PW::x * ((y + dy) + PW::y * (z + dz));
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      const T* q = sW + m * PW::n + iw;
+      sS[m * PS::n + e] = mc_slope(q[-PW::stride], q[0], q[PW::stride]);
+    }
+  }
+  __syncthreads();
+  // interface values: face f between cell f - 1 (primitive index f + 1,
+  // slope index f along D) and cell f
+  for (int e = tid; e < Ly::NF; e += Ly::NT) {
+    const int x = e % Ly::FX, y = (e / Ly::FX) % Ly::FY, z = e / (Ly::FX * Ly::FY);
+    const int iw = (x + dx) + PW::x * ((y + dy) + PW::y * (z + dz));
+    const int is = x + PS::x * (y + PS::y * z);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      const T* q = sW + m * PW::n + iw;
+      const T* sl = sS + m * PS::n + is;
+      sE[m * Ly::NF + e] = ppm_interface(q[0], q[PW::stride], sl[0], sl[PS::stride]);
+    }
+  }
+  __syncthreads();
+}
+
+// each thread's own cell: limit its parabola, trace, store the two states
+template <typename T, bool ALLW, bool L, int TX, int TY, int TZ, int D>
+__device__ __forceinline__ void tile_trace(const Work& w, const T* __restrict__ B, T* __restrict__ QL,
+                                           T* __restrict__ QR, const Tile& t, int tid, T dtdx, T gam,
+                                           const T* sW, const T* sE) {
+  using Ly = TileLayout<TX, TY, TZ, D>;
+  using PW = typename Ly::PW;
+  constexpr int dx = Ly::dx, dy = Ly::dy, dz = Ly::dz;
+  const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+  const int a = t.a0 + lx, b = t.b0 + ly, c = t.c0 + lz;
+  if (a < t.ux && b < t.uy && c < t.uz) {
+    const int iw = (lx + 2 * dx) + PW::x * ((ly + 2 * dy) + PW::y * (lz + 2 * dz));
+    const int ie = lx + Ly::FX * (ly + Ly::FY * lz);
+    T q[7], sl[7], sr[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      q[m] = sW[m * PW::n + iw];
+      sl[m] = sE[m * Ly::NF + ie];
+      sr[m] = sE[m * Ly::NF + ie + Ly::SF];
+      ppm_limit(q[m], sl[m], sr[m]);
+    }
+    const Site st = unit_site<L>(w, t.gg, a, b, c);
+    const long long N = w.N, NS = w.NS;
+    const long long pu = nbr(w, st.i, st.j, st.k, dx, dy, dz);
+    const long long su = snb<L>(w, st, dx, dy, dz);
+    trace_edges<T, ALLW>(q, B[D * N + st.p], B[D * N + pu], dtdx, gam, sl, sr);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      QR[((long long)D * 7 + m) * NS + st.s] = sl[m];
+      QL[((long long)D * 7 + m) * NS + su] = sr[m];
+    }
+  }
+}
+
+// tiles of one unit
+template <int TX, int TY, int TZ>
+__host__ __device__ __forceinline__ long long unit_tiles(int ux, int uy, int uz) {
+  return (long long)((ux + TX - 1) / TX) * ((uy + TY - 1) / TY) * ((uz + TZ - 1) / TZ);
+}
+
+// one direction of a tile: stage, slopes and interfaces, trace (four block
+// barriers; the last one frees the arrays for the next direction)
+template <typename T, bool ALLW, bool L, int TX, int TY, int TZ, int D>
+__device__ __forceinline__ void tile_direction(const Work& w, const T* __restrict__ W, const T* __restrict__ B,
+                                               T* __restrict__ QL, T* __restrict__ QR, const Tile& t, int tid, T dtdx,
+                                               T gam, T* sW, T* sS, T* sE) {
+  stage_prims<T, L, TX, TY, TZ, D>(w, W, t, tid, sW);
+  __syncthreads();
+  tile_interfaces<T, TX, TY, TZ, D>(tid, sW, sS, sE);
+  tile_trace<T, ALLW, L, TX, TY, TZ, D>(w, B, QL, QR, t, tid, dtdx, gam, sW, sE);
+  __syncthreads();
+}
+
+// One block per tile of TX * TY * TZ cells (one thread per cell), walking
+// the tiles with a grid-wide stride.
+template <typename T, bool ALLW, bool L, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ) k_ctu_states_tiled(Work w, const T* __restrict__ W,
+                                                                     const T* __restrict__ B, T* __restrict__ QL,
+                                                                     T* __restrict__ QR, DtSrc dts, T inv_dx,
+                                                                     T gam) {
+  constexpr int kW = padded_max<TX, TY, TZ, 2>(), kS = padded_max<TX, TY, TZ, 1>();
+  constexpr int kE = faces_max<TX, TY, TZ>();
+  __shared__ T smem[7 * (kW + kS + kE)];
+  T* sW = smem;
+  T* sS = smem + 7 * kW;
+  T* sE = smem + 7 * (kW + kS);
+  const int tid = (int)threadIdx.x;
+  const T dtdx = T(get_dt(dts)) * inv_dx;
+  const int ux = L ? w.box : w.nx, uy = L ? w.box : w.ny, uz = L ? w.box : w.nz;
+  const int tx = (ux + TX - 1) / TX, ty = (uy + TY - 1) / TY;
+  const long long per = unit_tiles<TX, TY, TZ>(ux, uy, uz);
+  const long long units = L ? work_items(w) / ((long long)w.box * w.box * w.box) : 1;
+  const long long ntiles = units * per;
+  for (long long id = block_rank(); id < ntiles; id += gridDim.x) {   // uniform over the block
+    Tile t;
+    const long long g = id / per;
+    const int r = (int)(id - g * per);
+    t.a0 = (r % tx) * TX;
+    t.b0 = ((r / tx) % ty) * TY;
+    t.c0 = (r / (tx * ty)) * TZ;
+    t.gg = L ? w.gbase + g : 0;
+    t.ux = ux; t.uy = uy; t.uz = uz;
+    tile_direction<T, ALLW, L, TX, TY, TZ, 0>(w, W, B, QL, QR, t, tid, dtdx, gam, sW, sS, sE);
+    tile_direction<T, ALLW, L, TX, TY, TZ, 1>(w, W, B, QL, QR, t, tid, dtdx, gam, sW, sS, sE);
+    tile_direction<T, ALLW, L, TX, TY, TZ, 2>(w, W, B, QL, QR, t, tid, dtdx, gam, sW, sS, sE);
+  }
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void store_flux(T* __restrict__ F, long long N, long long p, const T f[7]) {
   constexpr int n = D, t1 = (D + 1) % 3, t2 = (D + 2) % 3;

@@ -100,7 +100,7 @@ def load(path: str = LIB_PATH):
     lib.mhd_mlp_face_flux.argtypes = [P, P, I, P, P]
     lib.mhd_set_capture.argtypes = [P, P, ctypes.c_longlong, P, I]
     lib.mhd_advance_graph.argtypes = [P, ctypes.POINTER(LevelDesc), P, P]
-    lib.mhd_set_launch.argtypes = [P, I, I, I]
+    lib.mhd_set_launch.argtypes = [P, I, I, I, I]
     lib.mhd_cfl_dt_min.argtypes = [P, ctypes.POINTER(LevelDesc), D, P]
     lib.mhd_dt_subdivide.argtypes = [P, P, I, P]
     lib.mhd_prolong_time.argtypes = [P, ctypes.POINTER(LevelDesc), ctypes.POINTER(LevelDesc), D,
@@ -313,11 +313,14 @@ class Solver:
                                           None if t_dev is None else ctypes.c_void_p(t_dev.data_ptr())),
                "mhd_advance_graph")
 
-    def set_launch(self, blocks_per_cu: int = 0, threads: int = 0, batch: int = 0):
+    def set_launch(self, blocks_per_cu: int = 0, threads: int = 0, batch: int = 0, tiles: int = 0):
         """Launch shape of the stage kernels: blocks per CU of the persistent
-        grid (0: one item per thread), threads per block (0: 256) and the
-        group-list batch of the middle stages (0: the whole list)."""
-        _check(self.lib.mhd_set_launch(self.h, int(blocks_per_cu), int(threads), int(batch)), "mhd_set_launch")
+        grid (0: one item per thread), threads per block (0: 256), the
+        group-list batch of the middle stages (0: the whole list) and, for
+        CTU with PPM, the reconstruction stage on LDS tiles (1) or per cell
+        (0)."""
+        _check(self.lib.mhd_set_launch(self.h, int(blocks_per_cu), int(threads), int(batch), int(tiles)),
+               "mhd_set_launch")
 
     def cfl_dt_min(self, lv: Level, dt_dev: torch.Tensor, scale: float = 1.0):
         self._check_level(lv)

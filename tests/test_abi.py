@@ -38,7 +38,7 @@ def test_header_matches_exports(mhd):
 
 def test_abi_version_and_strings(mhd):
     lib = mhd.load()
-    assert lib.mhd_abi_version() == 3
+    assert lib.mhd_abi_version() == 4
     for s in (0, -1, -2, -4, -5, -6, -7, -8):
         assert len(lib.mhd_strerror(s)) > 0 and lib.mhd_strerror(s) != b"unknown status"
     assert lib.mhd_strerror(-3) == b"unknown status"      # retired code

@@ -38,6 +38,30 @@ def test_launch_shape_does_not_change_results(shape):
     assert torch.equal(a.U, b.U) and torch.equal(a.B, b.B)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(1, 0, 0, 1), (3, 512, 0, 1), (0, 64, 0, 1)])
+def test_lds_tile_shapes_do_not_change_results(prec, shape):
+    # with LDS tiles on, the other launch parameters keep the bits; on a grid
+    # whose extents are no multiple of the 16 x 4 x 4 tile (partial tiles along
+    # every axis, a 4-cell extent wrapping inside one tile's padding)
+    p = inputs.abc_problem(64, 0.1, seed=6)
+    U, B = oracle.initial_state(p)
+    U = np.ascontiguousarray(U[:, :36, :4, :20])
+    B = np.ascontiguousarray(B[:, :36, :4, :20])
+    dt = torch.float64 if prec == "f64" else torch.float32
+    ref = Solver("ctu", "ppm", "hlld", prec)
+    ref.set_launch(tiles=1)
+    s = Solver("ctu", "ppm", "hlld", prec)
+    s.set_launch(*shape)
+    a, b = lvl(U, B, p["dx"], dtype=dt), lvl(U, B, p["dx"], dtype=dt)
+    for _ in range(5):
+        ref.advance(a)
+        s.advance(b)
+    torch.cuda.synchronize()
+    assert torch.isfinite(a.U).all()
+    assert torch.equal(a.U, b.U) and torch.equal(a.B, b.B)
+
+
 def test_graph_replay_matches_eager():
     stream = torch.cuda.Stream()
     p = inputs.abc_problem(32, 0.1, seed=5)
@@ -165,14 +189,16 @@ def test_hierarchy_graph_replay_matches_eager(subcycle):
 
 
 @pytest.mark.parametrize("scheme, recon, solver", [("ctu", "ppm", "hlld"), ("vl", "plm", "roe"), ("vl", "ppm", "hlld")])
-@pytest.mark.parametrize("shape", [(0, 0, 1), (2, 512, 3), (0, 64, 5), (1, 256, 8)])
+@pytest.mark.parametrize("shape", [(0, 0, 1), (2, 512, 3), (0, 64, 5), (1, 256, 8), (0, 0, 0, 1), (1, 256, 3, 1)])
 def test_group_batches_do_not_change_results(scheme, recon, solver, shape):
     # a list of 7 groups stepped with the whole list per launch and in batches
+    # (with LDS tiles: against LDS tiles on the whole list)
     p = inputs.abc_problem(64, 0.1, seed=5)
     U, B = oracle.initial_state(p)
     g = torch.tensor([(0, 0, 0), (16, 0, 0), (48, 16, 0), (0, 32, 16), (32, 32, 32), (16, 48, 48), (48, 48, 48)],
                      dtype=torch.int32, device="cuda")
     ref = Solver(scheme, recon, solver)
+    ref.set_launch(tiles=shape[3] if len(shape) > 3 else 0)
     s = Solver(scheme, recon, solver)
     s.set_launch(*shape)
     a, b = lvl(U, B, p["dx"], groups=g), lvl(U, B, p["dx"], groups=g)
@@ -185,7 +211,7 @@ def test_group_batches_do_not_change_results(scheme, recon, solver, shape):
 
 def test_invalid_launch_shapes_are_refused():
     s = Solver("ctu", "ppm", "hlld")
-    for bad in ((-1, 0, 0), (0, 32, 0), (0, 1024, 0), (0, 100, 0), (0, 0, -2)):
+    for bad in ((-1, 0, 0), (0, 32, 0), (0, 1024, 0), (0, 100, 0), (0, 0, -2), (0, 0, 0, 2), (0, 0, 0, -1)):
         with pytest.raises(MHDError):
             s.set_launch(*bad)
 
@@ -204,11 +230,14 @@ def test_autotuner_picks_a_candidate_and_shapes_keep_results(tmp_path):
     h = Hierarchy(32, [5, 9], prec="f32", seed=4)
     r = autotune.tune(h, candidates=(0, 1, 4), reps=2, cache=str(tmp_path / "tune.json"))
     assert len(r["shapes"]) == 3 and all(b[0] in (0, 1, 4) for b in r["shapes"])
-    assert all(len(ms) == 3 and min(ms) > 0 for ms in r["ms"])
+    # three candidates, then the best of them with LDS tiles (CTU + PPM)
+    assert all(len(ms) == 4 and min(ms) > 0 for ms in r["ms"])
+    assert all(c[-1][3] == 1 and c[-1][:3] == c[min(range(3), key=ms.__getitem__)][:3]
+               for c, ms in zip(r["candidates"], r["ms"]))
     again = autotune.tune(h, candidates=(0, 1, 4), cache=str(tmp_path / "tune.json"), use_cache=True)
     assert again["shapes"] == r["shapes"]
     h.close()
-    # the tuned shapes give the same bits as the default shape
+    # shapes without LDS tiles give the same bits as the default shape
     a = Hierarchy(32, [5, 9], prec="f32", seed=4)
     b = Hierarchy(32, [5, 9], prec="f32", seed=4)
     b.set_launch([(1, 512, 0), (4, 128, 2), (1, 64, 3)])

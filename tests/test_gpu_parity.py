@@ -377,15 +377,21 @@ CTU_CASES = [("ppm", "hlld"), ("ppm", "roe"), ("plm", "roe"), ("plm", "hlld"), (
 RECON = {"plm": oracle.PLM, "ppm": oracle.PPM}
 
 
+# tiles=1: the reconstruction stage of CTU + PPM on LDS tiles (16 x 4 x 4
+# cells; the ragged and tiny problems leave partial tiles along every axis)
+@pytest.mark.parametrize("tiles", [0, 1])
 @pytest.mark.parametrize("recon,solver", CTU_CASES)
 @pytest.mark.parametrize("prob", sorted(PROBLEMS))
-def test_ctu_one_step_f64(prob, recon, solver):
+def test_ctu_one_step_f64(prob, recon, solver, tiles):
+    if tiles and recon != "ppm":
+        pytest.skip("LDS tiles apply to PPM only")
     p = PROBLEMS[prob]()
     U, B = oracle.initial_state(p)
     dx = p["dx"]
     dt = oracle.cfl_dt(U, B, dx)
     Uo, Bo = oracle.step(U, B, dt, dx, scheme=oracle.CTU, recon=RECON[recon], riemann=SOLVERS[solver])
     s = Solver("ctu", recon, solver)
+    s.set_launch(tiles=tiles)
     lv = level_from(U, B, dx)
     s.step(lv, dt)
     Ug, Bg = fetch(lv)
@@ -393,12 +399,14 @@ def test_ctu_one_step_f64(prob, recon, solver):
     assert rel_err(Bg, Bo) <= 1e-12
 
 
-def test_ctu_ten_steps_abc32_f64():
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_ctu_ten_steps_abc32_f64(tiles):
     p = inputs.abc_problem(32, 0.1, seed=0)
     U, B = oracle.initial_state(p)
     dx = p["dx"]
     Uo, Bo, t_o, _ = oracle.run(U, B, 10, dx, scheme=oracle.CTU, recon=oracle.PPM, riemann=oracle.HLLD)
     s = Solver("ctu", "ppm", "hlld")
+    s.set_launch(tiles=tiles)
     lv = level_from(U, B, dx)
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
     for _ in range(10):
@@ -432,7 +440,7 @@ def l1_rel(a, b):
     return max(np.abs(a[m] - b[m]).mean() / max(np.abs(b[m]).mean(), 1e-300) for m in range(a.shape[0]))
 
 
-def ctu_f32_step(prob, solver, recon="ppm"):
+def ctu_f32_step(prob, solver, recon="ppm", tiles=0):
     U, B = oracle.initial_state(prob)
     U = U.astype(np.float32).astype(np.float64)
     B = B.astype(np.float32).astype(np.float64)
@@ -440,6 +448,7 @@ def ctu_f32_step(prob, solver, recon="ppm"):
     dt = oracle.cfl_dt(U, B, dx)
     Uo, Bo = oracle.step(U, B, dt, dx, scheme=oracle.CTU, recon=RECON[recon], riemann=SOLVERS[solver])
     s = Solver("ctu", recon, solver, prec="f32")
+    s.set_launch(tiles=tiles)
     lv = level_from(U, B, dx, torch.float32)
     s.step(lv, dt)
     Ug, Bg = fetch(lv)
@@ -455,14 +464,15 @@ def test_ctu_one_step_f32_smooth(solver):
     assert rel_err(Bg, Bo) <= 1e-5
 
 
+@pytest.mark.parametrize("tiles", [0, 1])
 @pytest.mark.parametrize("solver", ["hlld", "roe"])
-def test_ctu_one_step_f32_noisy_abc(solver):
+def test_ctu_one_step_f32_noisy_abc(solver, tiles):
     # cell-scale noise puts some of PPM's discontinuous extremum tests and
     # EMF upwind choices within FP32 rounding of their switch; a flipped
     # decision moves nearby values by a slope-sized amount.  The per-value
     # bar holds outside the oracle's own flip set, which stays small.
     p = inputs.abc_problem(32, 0.1, seed=1)
-    Ug, Bg, Uo, Bo, dt, dx = ctu_f32_step(p, solver)
+    Ug, Bg, Uo, Bo, dt, dx = ctu_f32_step(p, solver, tiles=tiles)
     U, B = oracle.initial_state(p)
     U = U.astype(np.float32).astype(np.float64)
     B = B.astype(np.float32).astype(np.float64)
@@ -475,13 +485,15 @@ def test_ctu_one_step_f32_noisy_abc(solver):
     assert l1_rel(Bg, Bo) <= 1e-5
 
 
-def test_ctu_group_list_subset():
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_ctu_group_list_subset(tiles):
     p = inputs.smooth_problem(48, 32, 32, seed=6)
     U, B = oracle.initial_state(p)
     dx = p["dx"]
     dt = oracle.cfl_dt(U, B, dx)
     Uo, Bo = oracle.step(U, B, dt, dx, scheme=oracle.CTU, recon=oracle.PPM, riemann=oracle.HLLD)
     s = Solver("ctu", "ppm", "hlld")
+    s.set_launch(tiles=tiles)
     origins = [(0, 16, 0), (16, 16, 0), (32, 0, 16)]
     g = torch.tensor(origins, dtype=torch.int32, device="cuda")
     lv = level_from(U, B, dx, groups=g)
