@@ -344,13 +344,15 @@ def run_amr_criterion(n_root: int, steps: int, warmup: int, fraction: float = 0.
 
 
 def run_c4(n_root: int, count: int, steps: int, warmup: int, seed: int, params, drift_root: int = 64,
-           drift_count: int = 7, drift_steps: int = 100):
+           drift_count: int = 7, drift_steps: int = 100, oracle_steps: int = 0):
     """Full stack: FP32 CTU+PPM with the learned flux (HLLD fallback) on an
     AMR hierarchy (n_root^3 ABC root, noise 0.3, one refined level of
     `count` groups), `steps` root steps replayed from one HIP graph; energy
     budget and fallback fraction over the run.  Then the L1 drift of the same
     stack against the FP64 HLLD hierarchy at drift_root^3 + one level after
-    drift_steps steps (root data, which holds the restricted fine data)."""
+    drift_steps steps (root data, which holds the restricted fine data), and,
+    with oracle_steps > 0, the drift of both against the oracle's two-level
+    step after that many steps (each GPU hierarchy takes the oracle's dt)."""
     import numpy as np
     import torch
     from paper_1804_03479_amd.amr import Hierarchy
@@ -402,6 +404,36 @@ def run_c4(n_root: int, count: int, steps: int, warmup: int, seed: int, params, 
                                    "rho": rel(Ug[0], Ur[0]), "e": rel(Ug[4], Ur[4]), "B": rel(Bg, Br)}
     ref.close()
     run.close()
+    if oracle_steps > 0:
+        import oracle
+        from oracle import amr as oamr
+        from paper_1804_03479_amd import inputs
+        ref = Hierarchy(drift_root, [drift_count], "ctu", "ppm", "hlld", "f64", noise=0.3, seed=seed)
+        run = Hierarchy(drift_root, [drift_count], "ctu", "ppm", "mlp", "f32", noise=0.3, seed=seed)
+        for sv in run.solvers:
+            MlpOps(sv).set_weights(params)
+        p = inputs.abc_problem(drift_root, 0.3, seed=seed)
+        Uc, Bc = oracle.initial_state(p)
+        g = ref.groups[0]
+        Uf, Bf = oamr.initial_fine(Uc, Bc, g)
+        t0 = time.perf_counter()
+        for k in range(oracle_steps):
+            Uc, Bc, Uf, Bf, dt = oamr.two_level_step(Uc, Bc, Uf, Bf, g, p["dx"])
+            ref.step(dt_max=dt)
+            run.step(dt_max=dt)
+            if (k + 1) % 10 == 0:
+                print(f"c4 oracle drift: step {k + 1} of {oracle_steps}", file=sys.stderr, flush=True)
+        t_or = time.perf_counter() - t0
+        ref.stream.synchronize()
+        run.stream.synchronize()
+        U64, B64 = ref.levels[0].U.cpu().numpy(), ref.levels[0].B.cpu().numpy()
+        Ug, Bg = run.levels[0].U.double().cpu().numpy(), run.levels[0].B.double().cpu().numpy()
+        out["l1_drift_vs_oracle"] = {
+            "root": drift_root, "groups": drift_count, "steps": oracle_steps, "oracle_s": round(t_or, 1),
+            "mlp_f32_stack": {"rho": rel(Ug[0], Uc[0]), "e": rel(Ug[4], Uc[4]), "B": rel(Bg, Bc)},
+            "hlld_f64_hierarchy": {"rho": rel(U64[0], Uc[0]), "e": rel(U64[4], Uc[4]), "B": rel(B64, Bc)}}
+        ref.close()
+        run.close()
     return out
 
 
@@ -576,6 +608,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--c4-steps", type=int, default=1000,
                     help="root steps of the full-stack form (AMR + learned flux, FP32); 0 skips it")
+    ap.add_argument("--c4-oracle-steps", type=int, default=0,
+                    help="steps of the full stack's drift against the oracle's two-level step at 64^3 + 7 "
+                         "groups (the oracle takes about 3 s per step on 16 host cores)")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print one line with cell-updates/s of the CTU form "
                          "over grid sizes 32^3 .. 512^3 (FP32) and .. 384^3 (FP64)")
@@ -712,7 +747,8 @@ def main():
                      "flop_per_face": MLP_FLOP_PER_FACE}
         forms["ctu_f32_mlp"] = e
         if args.c4_steps > 0:
-            r = run_c4(2 * n, 511, args.c4_steps, args.warmup, args.seed, params)
+            r = run_c4(2 * n, 511, args.c4_steps, args.warmup, args.seed, params,
+                       oracle_steps=args.c4_oracle_steps)
             r["workload"] = f"abc{2 * n}_root_plus_1_level_ctu_ppm_mlp_hlld_fallback_ct_f32"
             forms["c4_full_stack"] = r
 

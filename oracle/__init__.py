@@ -55,6 +55,8 @@ def _load():
     lib.or_cfl_dt.argtypes = [I, I, I, D, D, D, P, P]
     lib.or_step.restype = I
     lib.or_step.argtypes = [I, I, I, D, D, I, I, I, P, P, D, P, P, ctypes.POINTER(I)]
+    lib.or_step_ex.restype = I
+    lib.or_step_ex.argtypes = [I, I, I, D, D, I, I, I, P, P, D, P, P, ctypes.POINTER(I), P, P]
     lib.or_prim_to_cons.argtypes = [I, I, I, D, P, P, P]
     lib.or_cons_to_prim.argtypes = [I, I, I, D, P, P, P]
     lib.or_divb.argtypes = [I, I, I, D, P, P]
@@ -133,20 +135,29 @@ def sums(U, B, dx: float) -> np.ndarray:
 
 
 def step(U, B, dt: float, dx: float, scheme: int = VL, recon: int = PLM, riemann: int = ROE,
-         gamma: float = GAMMA, return_fallbacks: bool = False):
-    """One full update of the periodic grid; returns (U_new, B_new)."""
+         gamma: float = GAMMA, return_fallbacks: bool = False, return_fluxes: bool = False):
+    """One full update of the periodic grid; returns (U_new, B_new), then
+    the fallback count if asked for, then, if asked for, the full update's
+    fluxes F [3, 5, nz, ny, nx] (through the lower d-face of each cell) and
+    edge EMFs E [3, nz, ny, nx] (at each cell's lower corner edges)."""
     U, B = _f64(U), _f64(B)
     nz, ny, nx = U.shape[1:]
     Uo = np.empty_like(U)
     Bo = np.empty_like(B)
+    F = np.empty((3, 5) + U.shape[1:]) if return_fluxes else None
+    E = np.empty((3,) + U.shape[1:]) if return_fluxes else None
     nfb = ctypes.c_int(0)
-    rc = _load().or_step(nx, ny, nz, dx, gamma, scheme, recon, riemann, _p(U), _p(B), float(dt),
-                         _p(Uo), _p(Bo), ctypes.byref(nfb))
+    rc = _load().or_step_ex(nx, ny, nz, dx, gamma, scheme, recon, riemann, _p(U), _p(B), float(dt),
+                            _p(Uo), _p(Bo), ctypes.byref(nfb), _p(F) if return_fluxes else None,
+                            _p(E) if return_fluxes else None)
     if rc != 0:
         raise RuntimeError(f"oracle step failed with status {rc}")
+    out = (Uo, Bo)
     if return_fallbacks:
-        return Uo, Bo, int(nfb.value)
-    return Uo, Bo
+        out += (int(nfb.value),)
+    if return_fluxes:
+        out += (F, E)
+    return out
 
 
 def run(U, B, nsteps: int, dx: float, courant: float = 0.5, **kw):

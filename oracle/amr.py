@@ -96,91 +96,119 @@ def children_cells(Uc, Bc, i, j, k, b2, gamma):
     return kids
 
 
+def face_slope(Bc, a, ti, c):
+    """Limited transverse slope of the coarse a-face of cell c = (i, j, k)
+    along the axis (a+1)%3 (ti = 0) or (a+2)%3 (ti = 1), periodic."""
+    nz, ny, nx = Bc.shape[1:]
+    n = (nx, ny, nz)
+    t = (a + 1 + ti) % 3
+    i, j, k = c
+    up, dn = [i, j, k], [i, j, k]
+    up[t] = (up[t] + 1) % n[t]
+    dn[t] = (dn[t] - 1) % n[t]
+    v = Bc[a, k, j, i]
+    return mc(Bc[a, up[2], up[1], up[0]] - v, v - Bc[a, dn[2], dn[1], dn[0]])
+
+
 def face_slopes(Bc):
     """Limited transverse slopes S[a][t] (t = 0, 1 for the axes (a+1)%3,
     (a+2)%3) of every coarse a-face, shape (3, 2, nz, ny, nx)."""
     S = np.zeros((3, 2) + Bc.shape[1:])
     nz, ny, nx = Bc.shape[1:]
-    n = (nx, ny, nz)
     for a in range(3):
-        for ti, t in enumerate(((a + 1) % 3, (a + 2) % 3)):
+        for ti in range(2):
             for k in range(nz):
                 for j in range(ny):
                     for i in range(nx):
-                        c = [i, j, k]
-                        up, dn = list(c), list(c)
-                        up[t] = (up[t] + 1) % n[t]
-                        dn[t] = (dn[t] - 1) % n[t]
-                        v = Bc[a, k, j, i]
-                        S[a, ti, k, j, i] = mc(Bc[a, up[2], up[1], up[0]] - v, v - Bc[a, dn[2], dn[1], dn[0]])
+                        S[a, ti, k, j, i] = face_slope(Bc, a, ti, (i, j, k))
     return S
 
 
-def prolong(Uc, Bc, gamma=5.0 / 3.0):
+def prolong(Uc, Bc, gamma=5.0 / 3.0, cells=None):
+    """Fine level (2 nc) from the coarse level.  cells: None (every coarse
+    cell) or an iterable of coarse cells (i, j, k); then only their children
+    and the children's faces are filled (NaN elsewhere)."""
     nzc, nyc, nxc = Uc.shape[1:]
     nc = (nxc, nyc, nzc)
     Bf = np.empty((3,) + tuple(2 * x for x in Uc.shape[1:]))
     Uf = np.empty((5,) + Bf.shape[1:])
-    S = face_slopes(Bc)
+    if cells is None:
+        todo = [(i, j, k) for k in range(nzc) for j in range(nyc) for i in range(nxc)]
+    else:
+        Bf.fill(np.nan)
+        Uf.fill(np.nan)
+        todo = sorted({(i % nxc, j % nyc, k % nzc) for (i, j, k) in cells}, key=lambda c: (c[2], c[1], c[0]))
+    # slopes of every face (whole level) or of the faces the subset reads
+    S = face_slopes(Bc) if cells is None else {}
 
     def face(a, c):                      # coarse a-face value and slopes at cell c (lower face), periodic
         i, j, k = c[0] % nc[0], c[1] % nc[1], c[2] % nc[2]
-        return Bc[a, k, j, i], S[a, 0, k, j, i], S[a, 1, k, j, i]
+        if cells is None:
+            return Bc[a, k, j, i], S[a, 0, k, j, i], S[a, 1, k, j, i]
+        key = (a, i, j, k)
+        if key not in S:
+            S[key] = (face_slope(Bc, a, 0, (i, j, k)), face_slope(Bc, a, 1, (i, j, k)))
+        return (Bc[a, k, j, i],) + S[key]
 
-    for k in range(nzc):
-        for j in range(nyc):
-            for i in range(nxc):
-                c = (i, j, k)
-                for a in range(3):
-                    b, cc = (a + 1) % 3, (a + 2) % 3
-                    lo = face(a, c)
-                    up_c = list(c)
-                    up_c[a] += 1
-                    hi = face(a, up_c)
-                    # fine faces on the lower coarse a-face: profile at (+-1/4, +-1/4)
-                    for q in range(4):
-                        ob, oc = (q & 1), (q >> 1)
-                        f = [2 * i, 2 * j, 2 * k]
-                        f[b] += ob
-                        f[cc] += oc
-                        Bf[a, f[2], f[1], f[0]] = lo[0] + lo[1] * (ob - 0.5) * 0.5 + lo[2] * (oc - 0.5) * 0.5
-                    # interior fine faces on the mid-plane of the cell
-                    # slope of the b-face component along a: it is the slope index of axis a
-                    # among (b+1)%3, (b+2)%3 of the b-faces
-                    def slope_along(comp, cell, axis):
-                        v = face(comp, cell)
-                        t1 = (comp + 1) % 3
-                        return v[1] if axis == t1 else v[2]
-                    bl, bh = list(c), list(c)
-                    bh[b] += 1
-                    cl, ch = list(c), list(c)
-                    ch[cc] += 1
-                    b_xy = slope_along(b, bh, a) - slope_along(b, bl, a)
-                    c_xz = slope_along(cc, ch, a) - slope_along(cc, cl, a)
-                    a_xx = -0.5 * (b_xy + c_xz)
-                    a0 = 0.5 * (lo[0] + hi[0]) - 0.25 * a_xx
-                    a_b = 0.5 * (lo[1] + hi[1])
-                    a_c = 0.5 * (lo[2] + hi[2])
-                    for q in range(4):
-                        ob, oc = (q & 1), (q >> 1)
-                        f = [2 * i, 2 * j, 2 * k]
-                        f[a] += 1
-                        f[b] += ob
-                        f[cc] += oc
-                        Bf[a, f[2], f[1], f[0]] = a0 + a_b * (ob - 0.5) * 0.5 + a_c * (oc - 0.5) * 0.5
+    def faces_of(c):                     # the fine faces on c's lower faces and on its mid-planes
+        i, j, k = c
+        for a in range(3):
+            b, cc = (a + 1) % 3, (a + 2) % 3
+            lo = face(a, c)
+            up_c = list(c)
+            up_c[a] += 1
+            hi = face(a, up_c)
+            # fine faces on the lower coarse a-face: profile at (+-1/4, +-1/4)
+            for q in range(4):
+                ob, oc = (q & 1), (q >> 1)
+                f = [2 * i, 2 * j, 2 * k]
+                f[b] += ob
+                f[cc] += oc
+                Bf[a, f[2], f[1], f[0]] = lo[0] + lo[1] * (ob - 0.5) * 0.5 + lo[2] * (oc - 0.5) * 0.5
+            # interior fine faces on the mid-plane of the cell
+            # slope of the b-face component along a: it is the slope index of axis a
+            # among (b+1)%3, (b+2)%3 of the b-faces
+            def slope_along(comp, cell, axis):
+                v = face(comp, cell)
+                t1 = (comp + 1) % 3
+                return v[1] if axis == t1 else v[2]
+            bl, bh = list(c), list(c)
+            bh[b] += 1
+            cl, ch = list(c), list(c)
+            ch[cc] += 1
+            b_xy = slope_along(b, bh, a) - slope_along(b, bl, a)
+            c_xz = slope_along(cc, ch, a) - slope_along(cc, cl, a)
+            a_xx = -0.5 * (b_xy + c_xz)
+            a0 = 0.5 * (lo[0] + hi[0]) - 0.25 * a_xx
+            a_b = 0.5 * (lo[1] + hi[1])
+            a_c = 0.5 * (lo[2] + hi[2])
+            for q in range(4):
+                ob, oc = (q & 1), (q >> 1)
+                f = [2 * i, 2 * j, 2 * k]
+                f[a] += 1
+                f[b] += ob
+                f[cc] += oc
+                Bf[a, f[2], f[1], f[0]] = a0 + a_b * (ob - 0.5) * 0.5 + a_c * (oc - 0.5) * 0.5
+
+    # the children's upper faces are the next coarse cells' lower faces
+    face_cells = set(todo)
+    if cells is not None:
+        for (i, j, k) in todo:
+            for d in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+                face_cells.add(((i + d[0]) % nxc, (j + d[1]) % nyc, (k + d[2]) % nzc))
+    for c in sorted(face_cells, key=lambda c: (c[2], c[1], c[0])):
+        faces_of(c)
     nz, ny, nx = Bf.shape[1:]
-    for k in range(nzc):
-        for j in range(nyc):
-            for i in range(nxc):
-                kids = [(2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2)) for q in range(8)]
-                b2 = []
-                for (I, J, K) in kids:
-                    bf = [0.5 * (Bf[0, K, J, I] + Bf[0, K, J, (I + 1) % nx]),
-                          0.5 * (Bf[1, K, J, I] + Bf[1, K, (J + 1) % ny, I]),
-                          0.5 * (Bf[2, K, J, I] + Bf[2, (K + 1) % nz, J, I])]
-                    b2.append(sum(x * x for x in bf))
-                for (I, J, K), u in zip(kids, children_cells(Uc, Bc, i, j, k, b2, gamma)):
-                    Uf[:, K, J, I] = u
+    for (i, j, k) in todo:
+        kids = [(2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2)) for q in range(8)]
+        b2 = []
+        for (I, J, K) in kids:
+            bf = [0.5 * (Bf[0, K, J, I] + Bf[0, K, J, (I + 1) % nx]),
+                  0.5 * (Bf[1, K, J, I] + Bf[1, K, (J + 1) % ny, I]),
+                  0.5 * (Bf[2, K, J, I] + Bf[2, (K + 1) % nz, J, I])]
+            b2.append(sum(x * x for x in bf))
+        for (I, J, K), u in zip(kids, children_cells(Uc, Bc, i, j, k, b2, gamma)):
+            Uf[:, K, J, I] = u
     return Uf, Bf
 
 
@@ -382,3 +410,214 @@ def prolong_new_groups(Uc, Bc, Uf, Bf, new_groups, old_groups, edge=16, gamma=5.
                             F[cc] += q >> 1
                             Bf[a, F[2] % nf[2], F[1] % nf[1], F[0] % nf[0]] = fine[a, 2, q]
     return Uf, Bf
+
+
+# ---------------------------------------------------------------- two levels, one shared step
+# A root level and one refined level whose listed patch groups (cubes of
+# `edge` fine cells, origins in fine cells) are updated, advanced together
+# by one time step (Sec. 3.3: the refined level's ghost zones are filled from
+# the coarse level by interpolation, both levels are updated, then the
+# correction operation puts the fine fluxes and EMFs on the coarse-fine
+# interface and the restriction replaces refined coarse data by fine means).
+# Fine cells that are neither listed nor ghosts are never read; the driver
+# keeps them at NaN so that a dependence on them would show.
+
+def listed_mask(groups, edge, shape):
+    """Fine cells inside the listed groups."""
+    m = np.zeros(shape, bool)
+    for (i, j, k) in np.asarray(groups).reshape(-1, 3):
+        m[k:k + edge, j:j + edge, i:i + edge] = True
+    return m
+
+
+def ghost_box_mask(groups, edge, halo, shape):
+    """Fine cells from `halo` below to `halo` + 1 above each listed group
+    (periodic): every cell whose state or lower faces a group's update reads
+    (the extra layer holds the last ghost's upper faces)."""
+    nz, ny, nx = shape
+    m = np.zeros(shape, bool)
+    for (i, j, k) in np.asarray(groups).reshape(-1, 3):
+        ks = np.arange(k - halo, k + edge + halo + 1) % nz
+        js = np.arange(j - halo, j + edge + halo + 1) % ny
+        is_ = np.arange(i - halo, i + edge + halo + 1) % nx
+        m[np.ix_(ks, js, is_)] = True
+    return m
+
+
+def _face_of_listed(listed, a):
+    """Lower a-faces of the fine level that touch a listed cell."""
+    return listed | np.roll(listed, 1, axis=2 - a)
+
+
+def initial_fine(Uc, Bc, groups, edge=16, gamma=5.0 / 3.0):
+    """The refined level at the start: listed cells and their faces from the
+    prolongation of their parents, NaN elsewhere."""
+    shape = tuple(2 * n for n in Uc.shape[1:])
+    listed = listed_mask(groups, edge, shape)
+    parents = {(I // 2, J // 2, K // 2) for K, J, I in zip(*np.nonzero(listed))}
+    Up, Bp = prolong(Uc, Bc, gamma, cells=parents)
+    Uf = np.full((5,) + shape, np.nan)
+    Bf = np.full((3,) + shape, np.nan)
+    Uf[:, listed] = Up[:, listed]
+    for a in range(3):
+        m = _face_of_listed(listed, a)
+        Bf[a][m] = Bp[a][m]
+    return Uf, Bf
+
+
+def refill_ghosts(Uc, Bc, Uf, Bf, groups, edge=16, halo=4, gamma=5.0 / 3.0):
+    """Ghost cells of the listed groups (not listed themselves) take the
+    prolongation of the coarse level, cell data and the faces that touch no
+    listed cell; listed cells and every face of a listed cell keep theirs."""
+    listed = listed_mask(groups, edge, Uf.shape[1:])
+    ghost = ghost_box_mask(groups, edge, halo, Uf.shape[1:]) & ~listed
+    parents = {(I // 2, J // 2, K // 2) for K, J, I in zip(*np.nonzero(ghost))}
+    Up, Bp = prolong(Uc, Bc, gamma, cells=parents)
+    Uf, Bf = Uf.copy(), Bf.copy()
+    Uf[:, ghost] = Up[:, ghost]
+    for a in range(3):
+        m = ghost & ~np.roll(listed, 1, axis=2 - a)
+        Bf[a][m] = Bp[a][m]
+    return Uf, Bf
+
+
+def cfl_dt_listed(U, B, dx, mask, gamma=5.0 / 3.0, courant=0.5):
+    """The oracle's CFL step over the masked cells only: the other cells are
+    put at rest with density 1e30 and pressure 1e-6 (1 + |B|^2) (a signal
+    speed of order 1e-15 |B|), the face field (and so each masked cell's
+    centred field) unchanged."""
+    from . import cfl_dt, cons_to_prim
+    Bn = np.nan_to_num(B, nan=0.0)
+    W = cons_to_prim(np.nan_to_num(U, nan=1.0), Bn, gamma)
+    b2 = W[5] ** 2 + W[6] ** 2 + W[7] ** 2
+    Us = np.array(U)
+    out = ~mask
+    Us[0][out] = 1e30
+    Us[1:4][:, out] = 0.0
+    Us[4][out] = 1e-6 * (1.0 + b2[out]) / (gamma - 1.0) + 0.5 * b2[out]
+    return cfl_dt(Us, Bn, dx, gamma, courant)
+
+
+def refined_coarse(groups, edge, shape_c):
+    """Coarse cells under the listed fine groups."""
+    m = np.zeros(shape_c, bool)
+    h = edge // 2
+    for (i, j, k) in np.asarray(groups).reshape(-1, 3):
+        m[k // 2:k // 2 + h, j // 2:j // 2 + h, i // 2:i // 2 + h] = True
+    return m
+
+
+def face_mean(Ff, a):
+    """Mean of the four fine lower a-faces on each coarse lower a-face (Ff
+    [..., nzf, nyf, nxf], result [..., nzc, nyc, nxc])."""
+    ax = Ff.ndim - 1 - a                       # array axis of direction a
+    t = [Ff.ndim - 1 - b for b in range(3) if b != a]
+    sl = [slice(None)] * Ff.ndim
+    sl[ax] = slice(0, None, 2)
+    F = Ff[tuple(sl)]
+    acc = 0.0
+    for p in (0, 1):
+        for q in (0, 1):
+            s2 = [slice(None)] * Ff.ndim
+            s2[t[0]] = slice(p, None, 2)
+            s2[t[1]] = slice(q, None, 2)
+            acc = acc + F[tuple(s2)]
+    return 0.25 * acc
+
+
+def edge_mean(Ef, a):
+    """Mean of the two fine a-edges on each coarse a-edge (the edge along a
+    at the cell's lower corner in the two other directions)."""
+    ax = Ef.ndim - 1 - a
+    sl = [slice(None)] * Ef.ndim
+    for b in range(3):
+        if b != a:
+            sl[Ef.ndim - 1 - b] = slice(0, None, 2)
+    E = Ef[tuple(sl)]
+    s0 = [slice(None)] * Ef.ndim
+    s1 = [slice(None)] * Ef.ndim
+    s0[ax] = slice(0, None, 2)
+    s1[ax] = slice(1, None, 2)
+    return 0.5 * (E[tuple(s0)] + E[tuple(s1)])
+
+
+def correct_and_restrict(Uc, Bc, Fc, Ec, Uf, Bf, Ff, Ef, refined, dt, dxc, correct=True):
+    """The correction operation and the restriction after a shared step dt.
+
+    Uc, Bc: the coarse level after its own update with fluxes Fc [3, 5, ...]
+    and edge EMFs Ec [3, ...]; Uf, Bf, Ff, Ef the same of the refined level;
+    refined: the coarse cells under listed fine groups.
+      - an unrefined coarse cell sharing a face with a refined one takes,
+        through that face, the mean of the four fine fluxes instead of its own;
+      - on coarse edges of the refined region's boundary (some, not all, of
+        the four cells around the edge refined) the EMF difference (mean of
+        the two fine EMFs minus the coarse one) updates, by the CT formula,
+        the coarse faces whose two cells are both unrefined;
+      - refined coarse cells take the mean of their eight children, and every
+        coarse face with a refined cell on either side the mean of its four
+        fine faces.
+    correct=False: the restriction alone (no correction)."""
+    r = dt / dxc
+    Uc, Bc = Uc.copy(), Bc.copy()
+    out = ~refined
+    for a in range(3 if correct else 0):
+        ax = 2 - a
+        dF = face_mean(Ff[a], a) - Fc[a]                 # [5, ...] on each coarse lower a-face
+        m_lo = out & np.roll(refined, 1, axis=ax)         # refined neighbour below: own lower face
+        Uc[:, m_lo] += r * dF[:, m_lo]
+        m_hi = out & np.roll(refined, -1, axis=ax)        # refined neighbour above: its lower face
+        dF_hi = np.roll(dF, -1, axis=ax + 1)
+        Uc[:, m_hi] -= r * dF_hi[:, m_hi]
+    dE = []
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        r00 = refined
+        r10 = np.roll(refined, 1, axis=2 - b)
+        r01 = np.roll(refined, 1, axis=2 - c)
+        r11 = np.roll(r10, 1, axis=2 - c)
+        boundary = (r00 | r10 | r01 | r11) & ~(r00 & r10 & r01 & r11)
+        dE.append(np.where(boundary & correct, edge_mean(Ef[a], a) - Ec[a], 0.0))
+    dEx, dEy, dEz = dE
+
+    def up(f, ax):                       # the value one cell up along an array axis
+        return np.roll(f, -1, axis=ax)
+    dB = [-r * (up(dEz, 1) - dEz) + r * (up(dEy, 0) - dEy),
+          -r * (up(dEx, 0) - dEx) + r * (up(dEz, 2) - dEz),
+          -r * (up(dEy, 2) - dEy) + r * (up(dEx, 1) - dEx)]
+    for a in range(3):
+        both_out = out & np.roll(out, 1, axis=2 - a)
+        Bc[a][both_out] += dB[a][both_out]
+    Ur = restrict(np.nan_to_num(Uf))
+    Uc[:, refined] = Ur[:, refined]
+    for a in range(3):
+        touched = refined | np.roll(refined, 1, axis=2 - a)
+        Bm = face_mean(np.nan_to_num(Bf[a]), a)
+        Bc[a][touched] = Bm[touched]
+    return Uc, Bc
+
+
+def two_level_step(Uc, Bc, Uf, Bf, groups, dxc, edge=16, halo=4, scheme=1, recon=1, riemann=2,
+                   gamma=5.0 / 3.0, courant=0.5, dt_max=np.inf, correct=True):
+    """One shared step of the root (Uc, Bc: a dense periodic level of cell
+    size dxc) and the refined level (Uf, Bf: the dense array of the level,
+    of which the listed groups count).  dt is the smaller CFL step of the
+    two levels (the refined one over its listed cells), at most dt_max.
+    scheme / recon / riemann: the oracle's codes (default CTU, PPM, HLLD).
+    Returns (Uc, Bc, Uf, Bf, dt)."""
+    from . import cfl_dt, step
+    listed = listed_mask(groups, edge, Uf.shape[1:])
+    dxf = 0.5 * dxc
+    dt = min(cfl_dt(Uc, Bc, dxc, gamma, courant), cfl_dt_listed(Uf, Bf, dxf, listed, gamma, courant), dt_max)
+    Ug, Bg = refill_ghosts(Uc, Bc, Uf, Bf, groups, edge, halo, gamma)
+    Ucn, Bcn, Fc, Ec = step(Uc, Bc, dt, dxc, scheme=scheme, recon=recon, riemann=riemann, gamma=gamma,
+                            return_fluxes=True)
+    Ufs, Bfs, Ff, Ef = step(Ug, Bg, dt, dxf, scheme=scheme, recon=recon, riemann=riemann, gamma=gamma,
+                            return_fluxes=True)
+    Ufn, Bfn = Ug.copy(), Bg.copy()
+    Ufn[:, listed] = Ufs[:, listed]
+    for a in range(3):
+        m = _face_of_listed(listed, a)
+        Bfn[a][m] = Bfs[a][m]
+    refined = refined_coarse(groups, edge, Uc.shape[1:])
+    Ucn, Bcn = correct_and_restrict(Ucn, Bcn, Fc, Ec, Ufn, Bfn, Ff, Ef, refined, dt, dxc, correct)
+    return Ucn, Bcn, Ufn, Bfn, dt

@@ -583,13 +583,13 @@ static void apply_update(const grid_t* g, const double* U, const double* B, cons
 /* ------------------------------------------------------------------ */
 int or_ctu_step_impl(int nx, int ny, int nz, double dx, double gam, int recon, int solver,
                      const double* U, const double* B, double dt, double* Uo, double* Bo,
-                     int* nfallback);
+                     int* nfallback, double* Fout, double* Eout);
 
 /* ------------------------------------------------------------------ */
 /* the VL (MUSCL-Hancock) step, paper Sec. 3.2, VL steps 1-7           */
 /* ------------------------------------------------------------------ */
 static int vl_step(const grid_t* g, int recon, int solver, const double* U, const double* B,
-                   double dt, double* Uo, double* Bo, int* nfallback) {
+                   double dt, double* Uo, double* Bo, int* nfallback, double* Fout, double* Eout) {
   size_t N = ncell(g);
   double* W = malloc(8 * N * sizeof(double));
   double* Fd[3];
@@ -614,6 +614,7 @@ static int vl_step(const grid_t* g, int recon, int solver, const double* U, cons
   edge_emfs(g, F, W, E);
   /* 7. full update from time n */
   apply_update(g, U, B, F, E, dt, Uo, Bo);
+  or__copy_final(N, F, E, Fout, Eout);
 
   free(W); free(Fd[0]); free(Fd[1]); free(Fd[2]); free(E); free(Uh); free(Bh);
   return 0;
@@ -736,6 +737,12 @@ void or_sums(int nx, int ny, int nz, double dx, const double* U, const double* B
 
 int or_step(int nx, int ny, int nz, double dx, double gam, int scheme, int recon, int solver,
             const double* U, const double* B, double dt, double* Uo, double* Bo, int* nfallback) {
+  return or_step_ex(nx, ny, nz, dx, gam, scheme, recon, solver, U, B, dt, Uo, Bo, nfallback, NULL, NULL);
+}
+
+int or_step_ex(int nx, int ny, int nz, double dx, double gam, int scheme, int recon, int solver,
+               const double* U, const double* B, double dt, double* Uo, double* Bo, int* nfallback,
+               double* Fout, double* Eout) {
   grid_t g = mkgrid(nx, ny, nz, dx, gam);
   int fb = 0;
   int rc;
@@ -743,9 +750,9 @@ int or_step(int nx, int ny, int nz, double dx, double gam, int scheme, int recon
     /* no unlimited PPM: without limiting or tracing both sides of a face
      * take the same interface value, a central scheme without dissipation */
     if (recon != OR_PLM && recon != OR_FIRST_ORDER && recon != OR_PLM_UNLIMITED && recon != OR_PPM) return -1;
-    rc = vl_step(&g, recon, solver, U, B, dt, Uo, Bo, &fb);
+    rc = vl_step(&g, recon, solver, U, B, dt, Uo, Bo, &fb, Fout, Eout);
   } else if (scheme == OR_CTU) {
-    rc = or_ctu_step_impl(nx, ny, nz, dx, gam, recon, solver, U, B, dt, Uo, Bo, &fb);
+    rc = or_ctu_step_impl(nx, ny, nz, dx, gam, recon, solver, U, B, dt, Uo, Bo, &fb, Fout, Eout);
   } else {
     return -1;
   }
@@ -785,4 +792,10 @@ void or__apply_update(int nx, int ny, int nz, double dx, const double* U, const 
                       const double* const F[3], const double* E, double tau, double* Uo, double* Bo) {
   grid_t g = mkgrid(nx, ny, nz, dx, 1.0);
   apply_update(&g, U, B, F, E, tau, Uo, Bo);
+}
+/* the hydro components of the update's fluxes and its edge EMFs, if asked for */
+void or__copy_final(size_t N, const double* const F[3], const double* E, double* Fout, double* Eout) {
+  if (Fout)
+    for (int d = 0; d < 3; ++d) memcpy(Fout + (size_t)d * 5 * N, F[d], 5 * N * sizeof(double));
+  if (Eout) memcpy(Eout, E, 3 * N * sizeof(double));
 }

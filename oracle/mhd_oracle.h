@@ -4,6 +4,8 @@
 #ifndef MHD_ORACLE_H
 #define MHD_ORACLE_H
 
+#include <stddef.h>
+
 enum { OR_VL = 0, OR_CTU = 1 };
 enum { OR_PLM = 0, OR_PPM = 1, OR_FIRST_ORDER = 2, OR_PLM_UNLIMITED = 3, OR_PPM_UNLIMITED = 4 };
 enum { OR_ROE = 0, OR_HLLE = 1, OR_HLLD = 2 };
@@ -18,6 +20,13 @@ void or_divb(int nx, int ny, int nz, double dx, const double* B, double* div);
 void or_sums(int nx, int ny, int nz, double dx, const double* U, const double* B, double out[7]);
 int or_step(int nx, int ny, int nz, double dx, double gam, int scheme, int recon, int solver,
             const double* U, const double* B, double dt, double* Uo, double* Bo, int* nfallback);
+/* or_step that also returns the fluxes and edge EMFs of the full update (the
+ * ones the paper's correction operation needs): Fout [3][5][N] (mass,
+ * momentum x/y/z, energy through the lower d-face of each cell), Eout [3][N]
+ * (Ex, Ey, Ez on the edge at the cell's lower corner); either may be NULL */
+int or_step_ex(int nx, int ny, int nz, double dx, double gam, int scheme, int recon, int solver,
+               const double* U, const double* B, double dt, double* Uo, double* Bo, int* nfallback,
+               double* Fout, double* Eout);
 
 void or_phys_flux(double gam, const double* w, double bn, double* f);
 void or_w_to_u(double gam, const double* w, double bn, double* u);
@@ -33,5 +42,6 @@ int or__riemann(int solver, const double* wl, const double* wr, double bn, doubl
 void or__edge_emfs(int nx, int ny, int nz, double dx, const double* const F[3], const double* W, double* E);
 void or__apply_update(int nx, int ny, int nz, double dx, const double* U, const double* B,
                       const double* const F[3], const double* E, double tau, double* Uo, double* Bo);
+void or__copy_final(size_t N, const double* const F[3], const double* E, double* Fout, double* Eout);
 
 #endif

@@ -308,7 +308,7 @@ static void store_flux(double* Fd, size_t N, size_t p, int d, const double f[7])
 
 int or_ctu_step_impl(int nx, int ny, int nz, double dx, double gam, int recon, int solver,
                      const double* U, const double* B, double dt, double* Uo, double* Bo,
-                     int* nfallback) {
+                     int* nfallback, double* Fout, double* Eout) {
   if (recon != OR_PLM && recon != OR_PPM && recon != OR_PPM_UNLIMITED) return -1;
   ctu_grid g;
   g.n[0] = nx; g.n[1] = ny; g.n[2] = nz; g.dx = dx; g.gam = gam;
@@ -396,6 +396,7 @@ int or_ctu_step_impl(int nx, int ny, int nz, double dx, double gam, int recon, i
   /* 7. edge EMFs with the half-step reference, 8. full update */
   or__edge_emfs(nx, ny, nz, dx, Fcc, Wh, Ec);
   or__apply_update(nx, ny, nz, dx, U, B, Fcc, Ec, dt, Uo, Bo);
+  or__copy_final(N, Fcc, Ec, Fout, Eout);
 
   free(W); free(Wh); free(QL); free(QR); free(Es); free(Ec); free(Uh); free(Bh);
   for (int d = 0; d < 3; ++d) { free(Fs[d]); free(Fc[d]); }

@@ -288,6 +288,37 @@ def test_correction_conserves_root_totals_and_div_b(counts, subcycle):
     u.close()
 
 
+@pytest.mark.parametrize("count", [3, 7])
+def test_shared_step_hierarchy_matches_the_oracle_two_level_step(count):
+    # root 32^3 + listed 16^3 groups of the 64^3 level, FP64 CTU+PPM+HLLD:
+    # ghost refill, both updates, correction and restriction against the
+    # oracle's two-level step, every step's dt and the state after three
+    n, seed, steps = 32, 2, 3
+    h = Hierarchy(n, [count], "ctu", "ppm", "hlld", "f64", noise=0.1, seed=seed)
+    g = h.groups[0]
+    p = inputs.abc_problem(n, 0.1, seed=seed)
+    Uc, Bc = oracle.initial_state(p)
+    Uf, Bf = oamr.initial_fine(Uc, Bc, g)
+    for _ in range(steps):
+        h.step()
+        h.stream.synchronize()
+        Uc, Bc, Uf, Bf, dt = oamr.two_level_step(Uc, Bc, Uf, Bf, g, p["dx"])
+        assert abs(h.dts[0].item() - dt) <= 1e-13 * dt
+    Ug, Bg = h.levels[0].U.cpu().numpy(), h.levels[0].B.cpu().numpy()
+    for m in range(5):
+        assert np.abs(Ug[m] - Uc[m]).max() <= 1e-12 * np.abs(Uc[m]).max(), m
+    for a in range(3):
+        assert np.abs(Bg[a] - Bc[a]).max() <= 1e-12 * np.abs(Bc[a]).max(), a
+    listed = oamr.listed_mask(g, 16, Uf.shape[1:])
+    Ufg, Bfg = h.levels[1].U.cpu().numpy(), h.levels[1].B.cpu().numpy()
+    for m in range(5):
+        assert np.abs(Ufg[m][listed] - Uf[m][listed]).max() <= 1e-12 * np.abs(Uf[m][listed]).max(), m
+    for a in range(3):
+        f = oamr._face_of_listed(listed, a)
+        assert np.abs(Bfg[a][f] - Bf[a][f]).max() <= 1e-12 * np.abs(Bf[a][f]).max(), a
+    h.close()
+
+
 def test_prolong_time_interpolates_the_parent_states():
     # ghosts of a sub-cycled level: prolongation of old + alpha (new - old);
     # alpha = 0 and 1 read one state alone

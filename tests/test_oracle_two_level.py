@@ -1,0 +1,99 @@
+"""Pins of the oracle's two-level step (a root level and one refined level
+of listed patch groups advanced by one shared step, paper Sec. 3.3): the
+root totals of mass, momentum and energy stay conserved to round-off (the
+correction puts the fine fluxes on the coarse-fine interface; without it
+they drift), the discrete divergence (Eq. 16) stays at round-off on the
+root and on the listed fine cells (the EMF correction must match the
+restricted interface faces), a fine level that covers the domain reduces
+the step to the uniform fine step followed by restriction, and the
+prolongation of a subset of coarse cells equals the whole-level one there.
+Also the layout of the fluxes and EMFs the oracle's step returns: they
+reproduce its update."""
+import numpy as np
+import pytest
+
+from oracle import amr
+from paper_1804_03479_amd import inputs
+from paper_1804_03479_amd.amr import nested_groups
+
+
+@pytest.mark.parametrize("scheme, recon, riemann", [(1, 1, 2), (0, 0, 0)])
+def test_step_fluxes_reproduce_the_update(orc, scheme, recon, riemann):
+    p = inputs.smooth_problem(6, 5, 4, seed=7)
+    U, B = orc.initial_state(p)
+    dx = p["dx"]
+    dt = orc.cfl_dt(U, B, dx)
+    Uo, Bo, F, E = orc.step(U, B, dt, dx, scheme=scheme, recon=recon, riemann=riemann, return_fluxes=True)
+    r = dt / dx
+    up = lambda f, ax: np.roll(f, -1, axis=ax)  # noqa: E731
+    Ur = U - r * sum(up(F[d], 3 - d) - F[d] for d in range(3))
+    Ex, Ey, Ez = E
+    Br = np.stack([B[0] - r * (up(Ez, 1) - Ez) + r * (up(Ey, 0) - Ey),
+                   B[1] - r * (up(Ex, 0) - Ex) + r * (up(Ez, 2) - Ez),
+                   B[2] - r * (up(Ey, 2) - Ey) + r * (up(Ex, 1) - Ex)])
+    assert np.abs(Ur - Uo).max() <= 1e-13 * np.abs(Uo).max()
+    assert np.abs(Br - Bo).max() <= 1e-13 * np.abs(Bo).max()
+
+
+def test_prolong_subset_equals_whole_level(orc):
+    p = inputs.abc_problem(8, 0.1, seed=3)
+    Uc, Bc = orc.initial_state(p)
+    Uf, Bf = amr.prolong(Uc, Bc)
+    rng = np.random.default_rng(1)
+    cells = [tuple(int(x) for x in rng.integers(0, 8, 3)) for _ in range(40)]
+    Us, Bs = amr.prolong(Uc, Bc, cells=cells)
+    for (i, j, k) in cells:
+        kid = (slice(2 * k, 2 * k + 2), slice(2 * j, 2 * j + 2), slice(2 * i, 2 * i + 2))
+        assert np.array_equal(Us[(slice(None),) + kid], Uf[(slice(None),) + kid])
+        assert np.array_equal(Bs[(slice(None),) + kid], Bf[(slice(None),) + kid])
+
+
+def _totals(U):
+    return U.reshape(5, -1).sum(1), np.abs(U).reshape(5, -1).sum(1)
+
+
+def _run(orc, n, count, steps, seed, correct=True):
+    p = inputs.abc_problem(n, 0.1, seed=seed)
+    Uc, Bc = orc.initial_state(p)
+    g = nested_groups(n, [count], 16, seed=seed)[0]
+    Uf, Bf = amr.initial_fine(Uc, Bc, g)
+    t0, _ = _totals(Uc)
+    for _ in range(steps):
+        Uc, Bc, Uf, Bf, dt = amr.two_level_step(Uc, Bc, Uf, Bf, g, p["dx"], correct=correct)
+    return p, g, Uc, Bc, Uf, Bf, t0
+
+
+def test_two_level_step_conserves_and_stays_solenoidal(orc):
+    p, g, Uc, Bc, Uf, Bf, t0 = _run(orc, 16, 2, 3, seed=3)
+    t, mag = _totals(Uc)
+    assert np.all(np.abs(t - t0) <= 1e-14 * mag)
+    dx = p["dx"]
+    assert np.abs(orc.divb(Bc, dx)).max() * dx <= 1e-13
+    listed = amr.listed_mask(g, 16, Uf.shape[1:])
+    assert not np.isnan(Uf[:, listed]).any()
+    assert np.abs(orc.divb(np.nan_to_num(Bf), dx / 2)[listed]).max() * dx / 2 <= 1e-13
+
+
+def test_two_level_step_without_the_correction_drifts(orc):
+    # the conservation pin has teeth: the restriction alone moves the totals
+    p, g, Uc, Bc, Uf, Bf, t0 = _run(orc, 16, 2, 3, seed=3, correct=False)
+    t, mag = _totals(Uc)
+    assert np.abs(t - t0)[0] > 1e-9 * mag[0]
+    assert np.abs(orc.divb(Bc, p["dx"])).max() * p["dx"] > 1e-9
+
+
+def test_full_cover_is_the_uniform_fine_step_and_restriction(orc):
+    p = inputs.abc_problem(16, 0.1, seed=5)
+    Uc, Bc = orc.initial_state(p)
+    g = np.array([(i, j, k) for k in (0, 16) for j in (0, 16) for i in (0, 16)], dtype=np.int32)
+    Uf, Bf = amr.initial_fine(Uc, Bc, g)
+    Uf0, Bf0 = amr.prolong(Uc, Bc)
+    assert np.array_equal(Uf, Uf0) and np.array_equal(Bf, Bf0)
+    dx = p["dx"]
+    Ucn, Bcn, Ufn, Bfn, dt = amr.two_level_step(Uc, Bc, Uf, Bf, g, dx)
+    assert dt == min(orc.cfl_dt(Uc, Bc, dx), orc.cfl_dt(Uf0, Bf0, dx / 2))
+    Ur, Br = orc.step(Uf0, Bf0, dt, dx / 2, scheme=orc.CTU, recon=orc.PPM, riemann=orc.HLLD)
+    assert np.array_equal(Ufn, Ur) and np.array_equal(Bfn, Br)
+    assert np.array_equal(Ucn, amr.restrict(Ur))
+    for a in range(3):
+        assert np.array_equal(Bcn[a], amr.face_mean(Br[a], a))
