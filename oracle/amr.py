@@ -597,27 +597,46 @@ def correct_and_restrict(Uc, Bc, Fc, Ec, Uf, Bf, Ff, Ef, refined, dt, dxc, corre
 
 
 def two_level_step(Uc, Bc, Uf, Bf, groups, dxc, edge=16, halo=4, scheme=1, recon=1, riemann=2,
-                   gamma=5.0 / 3.0, courant=0.5, dt_max=np.inf, correct=True):
-    """One shared step of the root (Uc, Bc: a dense periodic level of cell
-    size dxc) and the refined level (Uf, Bf: the dense array of the level,
-    of which the listed groups count).  dt is the smaller CFL step of the
-    two levels (the refined one over its listed cells), at most dt_max.
-    scheme / recon / riemann: the oracle's codes (default CTU, PPM, HLLD).
+                   gamma=5.0 / 3.0, courant=0.5, dt_max=np.inf, correct=True, subcycle=False):
+    """One step of the root (Uc, Bc: a dense periodic level of cell size
+    dxc) and the refined level (Uf, Bf: the dense array of the level, of
+    which the listed groups count).  scheme / recon / riemann: the oracle's
+    codes (default CTU, PPM, HLLD).
+
+    Shared step (subcycle=False): dt is the smaller CFL step of the two
+    levels (the refined one over its listed cells), at most dt_max; ghosts
+    refilled, both levels updated by dt, then correction and restriction.
+    Sub-cycled (subcycle=True; the paper's level update: the coarse level
+    first, then the fine level evolved to the same time, then the
+    correction; refinement ratio 2 in time): dt = min(coarse CFL step, 2 x
+    fine CFL step), at most dt_max; the root is updated by dt, then the
+    refined level takes two steps of dt / 2, the ghosts of sub-step s
+    refilled from the root state at time fraction s / 2 (linear in time
+    between the root's states before and after its update); the correction
+    uses the mean of the two sub-steps' fluxes and EMFs.
     Returns (Uc, Bc, Uf, Bf, dt)."""
     from . import cfl_dt, step
     listed = listed_mask(groups, edge, Uf.shape[1:])
     dxf = 0.5 * dxc
-    dt = min(cfl_dt(Uc, Bc, dxc, gamma, courant), cfl_dt_listed(Uf, Bf, dxf, listed, gamma, courant), dt_max)
-    Ug, Bg = refill_ghosts(Uc, Bc, Uf, Bf, groups, edge, halo, gamma)
-    Ucn, Bcn, Fc, Ec = step(Uc, Bc, dt, dxc, scheme=scheme, recon=recon, riemann=riemann, gamma=gamma,
-                            return_fluxes=True)
-    Ufs, Bfs, Ff, Ef = step(Ug, Bg, dt, dxf, scheme=scheme, recon=recon, riemann=riemann, gamma=gamma,
-                            return_fluxes=True)
-    Ufn, Bfn = Ug.copy(), Bg.copy()
-    Ufn[:, listed] = Ufs[:, listed]
-    for a in range(3):
-        m = _face_of_listed(listed, a)
-        Bfn[a][m] = Bfs[a][m]
+    kw = dict(scheme=scheme, recon=recon, riemann=riemann, gamma=gamma, return_fluxes=True)
+    dt_f = cfl_dt_listed(Uf, Bf, dxf, listed, gamma, courant)
+    dt = min(cfl_dt(Uc, Bc, dxc, gamma, courant), (2.0 if subcycle else 1.0) * dt_f, dt_max)
+    Ucn, Bcn, Fc, Ec = step(Uc, Bc, dt, dxc, **kw)
+    subs = (0.0, 0.5) if subcycle else (0.0,)
+    tau = dt / len(subs)
+    Ff_mean, Ef_mean = 0.0, 0.0
+    for alpha in subs:
+        Ua = Uc + alpha * (Ucn - Uc) if alpha else Uc
+        Ba = Bc + alpha * (Bcn - Bc) if alpha else Bc
+        Uf, Bf = refill_ghosts(Ua, Ba, Uf, Bf, groups, edge, halo, gamma)
+        Ufs, Bfs, Ff, Ef = step(Uf, Bf, tau, dxf, **kw)
+        Uf, Bf = Uf.copy(), Bf.copy()
+        Uf[:, listed] = Ufs[:, listed]
+        for a in range(3):
+            m = _face_of_listed(listed, a)
+            Bf[a][m] = Bfs[a][m]
+        Ff_mean = Ff_mean + Ff / len(subs)
+        Ef_mean = Ef_mean + Ef / len(subs)
     refined = refined_coarse(groups, edge, Uc.shape[1:])
-    Ucn, Bcn = correct_and_restrict(Ucn, Bcn, Fc, Ec, Ufn, Bfn, Ff, Ef, refined, dt, dxc, correct)
-    return Ucn, Bcn, Ufn, Bfn, dt
+    Ucn, Bcn = correct_and_restrict(Ucn, Bcn, Fc, Ec, Uf, Bf, Ff_mean, Ef_mean, refined, dt, dxc, correct)
+    return Ucn, Bcn, Uf, Bf, dt

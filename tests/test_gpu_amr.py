@@ -288,13 +288,15 @@ def test_correction_conserves_root_totals_and_div_b(counts, subcycle):
     u.close()
 
 
+@pytest.mark.parametrize("subcycle", [False, True])
 @pytest.mark.parametrize("count", [3, 7])
-def test_shared_step_hierarchy_matches_the_oracle_two_level_step(count):
+def test_hierarchy_matches_the_oracle_two_level_step(count, subcycle):
     # root 32^3 + listed 16^3 groups of the 64^3 level, FP64 CTU+PPM+HLLD:
-    # ghost refill, both updates, correction and restriction against the
-    # oracle's two-level step, every step's dt and the state after three
+    # ghost refill (time-interpolated when sub-cycling), the updates, the
+    # correction and the restriction against the oracle's two-level step,
+    # every root step's dt and the state after three
     n, seed, steps = 32, 2, 3
-    h = Hierarchy(n, [count], "ctu", "ppm", "hlld", "f64", noise=0.1, seed=seed)
+    h = Hierarchy(n, [count], "ctu", "ppm", "hlld", "f64", noise=0.1, seed=seed, subcycle=subcycle)
     g = h.groups[0]
     p = inputs.abc_problem(n, 0.1, seed=seed)
     Uc, Bc = oracle.initial_state(p)
@@ -302,7 +304,7 @@ def test_shared_step_hierarchy_matches_the_oracle_two_level_step(count):
     for _ in range(steps):
         h.step()
         h.stream.synchronize()
-        Uc, Bc, Uf, Bf, dt = oamr.two_level_step(Uc, Bc, Uf, Bf, g, p["dx"])
+        Uc, Bc, Uf, Bf, dt = oamr.two_level_step(Uc, Bc, Uf, Bf, g, p["dx"], subcycle=subcycle)
         assert abs(h.dts[0].item() - dt) <= 1e-13 * dt
     Ug, Bg = h.levels[0].U.cpu().numpy(), h.levels[0].B.cpu().numpy()
     for m in range(5):

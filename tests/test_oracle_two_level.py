@@ -52,19 +52,20 @@ def _totals(U):
     return U.reshape(5, -1).sum(1), np.abs(U).reshape(5, -1).sum(1)
 
 
-def _run(orc, n, count, steps, seed, correct=True):
+def _run(orc, n, count, steps, seed, correct=True, subcycle=False):
     p = inputs.abc_problem(n, 0.1, seed=seed)
     Uc, Bc = orc.initial_state(p)
     g = nested_groups(n, [count], 16, seed=seed)[0]
     Uf, Bf = amr.initial_fine(Uc, Bc, g)
     t0, _ = _totals(Uc)
     for _ in range(steps):
-        Uc, Bc, Uf, Bf, dt = amr.two_level_step(Uc, Bc, Uf, Bf, g, p["dx"], correct=correct)
+        Uc, Bc, Uf, Bf, dt = amr.two_level_step(Uc, Bc, Uf, Bf, g, p["dx"], correct=correct, subcycle=subcycle)
     return p, g, Uc, Bc, Uf, Bf, t0
 
 
-def test_two_level_step_conserves_and_stays_solenoidal(orc):
-    p, g, Uc, Bc, Uf, Bf, t0 = _run(orc, 16, 2, 3, seed=3)
+@pytest.mark.parametrize("subcycle", [False, True])
+def test_two_level_step_conserves_and_stays_solenoidal(orc, subcycle):
+    p, g, Uc, Bc, Uf, Bf, t0 = _run(orc, 16, 2, 3, seed=3, subcycle=subcycle)
     t, mag = _totals(Uc)
     assert np.all(np.abs(t - t0) <= 1e-14 * mag)
     dx = p["dx"]
@@ -74,9 +75,10 @@ def test_two_level_step_conserves_and_stays_solenoidal(orc):
     assert np.abs(orc.divb(np.nan_to_num(Bf), dx / 2)[listed]).max() * dx / 2 <= 1e-13
 
 
-def test_two_level_step_without_the_correction_drifts(orc):
+@pytest.mark.parametrize("subcycle", [False, True])
+def test_two_level_step_without_the_correction_drifts(orc, subcycle):
     # the conservation pin has teeth: the restriction alone moves the totals
-    p, g, Uc, Bc, Uf, Bf, t0 = _run(orc, 16, 2, 3, seed=3, correct=False)
+    p, g, Uc, Bc, Uf, Bf, t0 = _run(orc, 16, 2, 3, seed=3, correct=False, subcycle=subcycle)
     t, mag = _totals(Uc)
     assert np.abs(t - t0)[0] > 1e-9 * mag[0]
     assert np.abs(orc.divb(Bc, p["dx"])).max() * p["dx"] > 1e-9
@@ -93,6 +95,23 @@ def test_full_cover_is_the_uniform_fine_step_and_restriction(orc):
     Ucn, Bcn, Ufn, Bfn, dt = amr.two_level_step(Uc, Bc, Uf, Bf, g, dx)
     assert dt == min(orc.cfl_dt(Uc, Bc, dx), orc.cfl_dt(Uf0, Bf0, dx / 2))
     Ur, Br = orc.step(Uf0, Bf0, dt, dx / 2, scheme=orc.CTU, recon=orc.PPM, riemann=orc.HLLD)
+    assert np.array_equal(Ufn, Ur) and np.array_equal(Bfn, Br)
+    assert np.array_equal(Ucn, amr.restrict(Ur))
+    for a in range(3):
+        assert np.array_equal(Bcn[a], amr.face_mean(Br[a], a))
+
+
+def test_full_cover_subcycled_is_two_uniform_fine_half_steps(orc):
+    p = inputs.abc_problem(16, 0.1, seed=5)
+    Uc, Bc = orc.initial_state(p)
+    g = np.array([(i, j, k) for k in (0, 16) for j in (0, 16) for i in (0, 16)], dtype=np.int32)
+    Uf, Bf = amr.initial_fine(Uc, Bc, g)
+    dx = p["dx"]
+    Ucn, Bcn, Ufn, Bfn, dt = amr.two_level_step(Uc, Bc, Uf, Bf, g, dx, subcycle=True)
+    assert dt == min(orc.cfl_dt(Uc, Bc, dx), 2.0 * orc.cfl_dt(Uf, Bf, dx / 2))
+    kw = dict(scheme=orc.CTU, recon=orc.PPM, riemann=orc.HLLD)
+    Ur, Br = orc.step(Uf, Bf, dt / 2, dx / 2, **kw)
+    Ur, Br = orc.step(Ur, Br, dt / 2, dx / 2, **kw)
     assert np.array_equal(Ufn, Ur) and np.array_equal(Bfn, Br)
     assert np.array_equal(Ucn, amr.restrict(Ur))
     for a in range(3):
