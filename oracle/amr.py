@@ -449,18 +449,22 @@ def _face_of_listed(listed, a):
     return listed | np.roll(listed, 1, axis=2 - a)
 
 
-def initial_fine(Uc, Bc, groups, edge=16, gamma=5.0 / 3.0):
-    """The refined level at the start: listed cells and their faces from the
-    prolongation of their parents, NaN elsewhere."""
+def initial_fine(Uc, Bc, groups, edge=16, gamma=5.0 / 3.0, halo=0):
+    """The refined level at the start: listed cells and their faces (with
+    halo > 0 also the cells and faces of the ghost boxes, `halo` cells
+    around each group) from the prolongation of their parents, NaN
+    elsewhere.  A level that has refined levels of its own needs the halo:
+    the prolongation of its cells reads their neighbours."""
     shape = tuple(2 * n for n in Uc.shape[1:])
     listed = listed_mask(groups, edge, shape)
-    parents = {(I // 2, J // 2, K // 2) for K, J, I in zip(*np.nonzero(listed))}
+    fill = listed | ghost_box_mask(groups, edge, halo, shape) if halo else listed
+    parents = {(I // 2, J // 2, K // 2) for K, J, I in zip(*np.nonzero(fill))}
     Up, Bp = prolong(Uc, Bc, gamma, cells=parents)
     Uf = np.full((5,) + shape, np.nan)
     Bf = np.full((3,) + shape, np.nan)
-    Uf[:, listed] = Up[:, listed]
+    Uf[:, fill] = Up[:, fill]
     for a in range(3):
-        m = _face_of_listed(listed, a)
+        m = _face_of_listed(fill, a)
         Bf[a][m] = Bp[a][m]
     return Uf, Bf
 
@@ -596,47 +600,110 @@ def correct_and_restrict(Uc, Bc, Fc, Ec, Uf, Bf, Ff, Ef, refined, dt, dxc, corre
     return Uc, Bc
 
 
+def replace_stored(Fc, Ec, Ff, Ef, refined):
+    """After a correction the coarse level's stored fluxes and EMFs on the
+    faces and edges of refined cells become the fine means, so that the next
+    coarser level is corrected with the finest values (in place)."""
+    for a in range(3):
+        m = refined | np.roll(refined, 1, axis=2 - a)
+        Fm = face_mean(Ff[a], a)
+        Fc[a][:, m] = Fm[:, m]
+        b, c = (a + 1) % 3, (a + 2) % 3
+        r10 = np.roll(refined, 1, axis=2 - b)
+        e = refined | r10 | np.roll(refined, 1, axis=2 - c) | np.roll(r10, 1, axis=2 - c)
+        Em = edge_mean(Ef[a], a)
+        Ec[a][e] = Em[e]
+
+
+def hierarchy_step(levels, groups, dx0, edge=16, halo=4, scheme=1, recon=1, riemann=2, gamma=5.0 / 3.0,
+                   courant=0.5, dt_max=np.inf, correct=True, subcycle=False):
+    """One root step of a hierarchy: levels = [(U0, B0), (U1, B1), ...], the
+    dense arrays of level l (cell size dx0 / 2^l; the root is updated whole),
+    groups = [None, g1, g2, ...] the listed groups of each refined level
+    (origins in its cells, each inside a listed group of its parent).
+    scheme / recon / riemann: the oracle's codes (default CTU, PPM, HLLD).
+
+    Shared step (subcycle=False): dt is the smallest CFL step of the levels
+    (a refined one over its listed cells), at most dt_max; the ghosts of
+    every refined level are refilled from its parent, coarse to fine, all
+    levels are updated by dt, then, fine to coarse, each level corrects its
+    parent, is restricted onto it, and the parent's stored fluxes and EMFs
+    on the faces and edges of refined cells become its means.
+    Sub-cycled (subcycle=True; the paper's level update: a level first,
+    then its finer level evolved to the same time, then the correction;
+    refinement ratio 2 in time): dt = min over l of 2^l times level l's
+    CFL step, at most dt_max, and level l's step is dt / 2^l.  A level
+    keeps its state before its update; its child takes two steps, the ghosts
+    of sub-step s refilled from the parent at time fraction s / 2 (linear
+    between the parent's states before and after its update); the
+    correction uses the mean of the two sub-steps' fluxes and EMFs (as they
+    stand after the child's own correction by its children).
+    Returns (levels after the step, dt)."""
+    from . import cfl_dt, step
+    nl = len(levels)
+    U = [np.array(u) for u, _ in levels]
+    B = [np.array(b) for _, b in levels]
+    dxs = [dx0 / 2 ** l for l in range(nl)]
+    listed = [None] + [listed_mask(groups[l], edge, U[l].shape[1:]) for l in range(1, nl)]
+    refined = [refined_coarse(groups[l + 1], edge, U[l].shape[1:]) for l in range(nl - 1)]
+    kw = dict(scheme=scheme, recon=recon, riemann=riemann, gamma=gamma, return_fluxes=True)
+    cfl = [cfl_dt(U[0], B[0], dxs[0], gamma, courant)] + \
+          [cfl_dt_listed(U[l], B[l], dxs[l], listed[l], gamma, courant) for l in range(1, nl)]
+    dt = min(min((2.0 ** l if subcycle else 1.0) * cfl[l] for l in range(nl)), dt_max)
+
+    def update(l, tau):
+        Un, Bn, F, E = step(U[l], B[l], tau, dxs[l], **kw)
+        if l == 0:
+            U[0], B[0] = Un, Bn
+        else:
+            U[l][:, listed[l]] = Un[:, listed[l]]
+            for a in range(3):
+                m = _face_of_listed(listed[l], a)
+                B[l][a][m] = Bn[a][m]
+        return F, E
+
+    def refill(l, Up, Bp):
+        U[l], B[l] = refill_ghosts(Up, Bp, U[l], B[l], groups[l], edge, halo, gamma)
+
+    def close(l, F, E, Ff, Ef, tau):
+        # level l + 1 corrects level l (own fluxes F, E; the child's Ff, Ef)
+        U[l], B[l] = correct_and_restrict(U[l], B[l], F, E, U[l + 1], B[l + 1], Ff, Ef, refined[l], tau, dxs[l],
+                                          correct)
+        replace_stored(F, E, Ff, Ef, refined[l])
+
+    if not subcycle:
+        for l in range(1, nl):
+            refill(l, U[l - 1], B[l - 1])
+        FE = [update(l, dt) for l in range(nl)]
+        for l in range(nl - 2, -1, -1):
+            close(l, FE[l][0], FE[l][1], FE[l + 1][0], FE[l + 1][1], dt)
+        return list(zip(U, B)), dt
+
+    def advance(l, tau):
+        Uo, Bo = U[l].copy(), B[l].copy()
+        F, E = update(l, tau)
+        if l == nl - 1:
+            return F, E
+        Fm, Em = 0.0, 0.0
+        for alpha in (0.0, 0.5):
+            Ua = Uo + alpha * (U[l] - Uo) if alpha else Uo
+            Ba = Bo + alpha * (B[l] - Bo) if alpha else Bo
+            refill(l + 1, Ua, Ba)
+            Fc, Ec = advance(l + 1, 0.5 * tau)
+            Fm = Fm + 0.5 * Fc
+            Em = Em + 0.5 * Ec
+        close(l, F, E, Fm, Em, tau)
+        return F, E
+
+    advance(0, dt)
+    return list(zip(U, B)), dt
+
+
 def two_level_step(Uc, Bc, Uf, Bf, groups, dxc, edge=16, halo=4, scheme=1, recon=1, riemann=2,
                    gamma=5.0 / 3.0, courant=0.5, dt_max=np.inf, correct=True, subcycle=False):
-    """One step of the root (Uc, Bc: a dense periodic level of cell size
-    dxc) and the refined level (Uf, Bf: the dense array of the level, of
-    which the listed groups count).  scheme / recon / riemann: the oracle's
-    codes (default CTU, PPM, HLLD).
-
-    Shared step (subcycle=False): dt is the smaller CFL step of the two
-    levels (the refined one over its listed cells), at most dt_max; ghosts
-    refilled, both levels updated by dt, then correction and restriction.
-    Sub-cycled (subcycle=True; the paper's level update: the coarse level
-    first, then the fine level evolved to the same time, then the
-    correction; refinement ratio 2 in time): dt = min(coarse CFL step, 2 x
-    fine CFL step), at most dt_max; the root is updated by dt, then the
-    refined level takes two steps of dt / 2, the ghosts of sub-step s
-    refilled from the root state at time fraction s / 2 (linear in time
-    between the root's states before and after its update); the correction
-    uses the mean of the two sub-steps' fluxes and EMFs.
-    Returns (Uc, Bc, Uf, Bf, dt)."""
-    from . import cfl_dt, step
-    listed = listed_mask(groups, edge, Uf.shape[1:])
-    dxf = 0.5 * dxc
-    kw = dict(scheme=scheme, recon=recon, riemann=riemann, gamma=gamma, return_fluxes=True)
-    dt_f = cfl_dt_listed(Uf, Bf, dxf, listed, gamma, courant)
-    dt = min(cfl_dt(Uc, Bc, dxc, gamma, courant), (2.0 if subcycle else 1.0) * dt_f, dt_max)
-    Ucn, Bcn, Fc, Ec = step(Uc, Bc, dt, dxc, **kw)
-    subs = (0.0, 0.5) if subcycle else (0.0,)
-    tau = dt / len(subs)
-    Ff_mean, Ef_mean = 0.0, 0.0
-    for alpha in subs:
-        Ua = Uc + alpha * (Ucn - Uc) if alpha else Uc
-        Ba = Bc + alpha * (Bcn - Bc) if alpha else Bc
-        Uf, Bf = refill_ghosts(Ua, Ba, Uf, Bf, groups, edge, halo, gamma)
-        Ufs, Bfs, Ff, Ef = step(Uf, Bf, tau, dxf, **kw)
-        Uf, Bf = Uf.copy(), Bf.copy()
-        Uf[:, listed] = Ufs[:, listed]
-        for a in range(3):
-            m = _face_of_listed(listed, a)
-            Bf[a][m] = Bfs[a][m]
-        Ff_mean = Ff_mean + Ff / len(subs)
-        Ef_mean = Ef_mean + Ef / len(subs)
-    refined = refined_coarse(groups, edge, Uc.shape[1:])
-    Ucn, Bcn = correct_and_restrict(Ucn, Bcn, Fc, Ec, Uf, Bf, Ff_mean, Ef_mean, refined, dt, dxc, correct)
-    return Ucn, Bcn, Uf, Bf, dt
+    """hierarchy_step of a root (Uc, Bc, cell size dxc) and one refined
+    level (Uf, Bf) with the listed groups `groups`; returns (Uc, Bc, Uf, Bf,
+    dt)."""
+    ((Uc, Bc), (Uf, Bf)), dt = hierarchy_step([(Uc, Bc), (Uf, Bf)], [None, groups], dxc, edge, halo, scheme, recon,
+                                              riemann, gamma, courant, dt_max, correct, subcycle)
+    return Uc, Bc, Uf, Bf, dt

@@ -10,7 +10,14 @@
 
 namespace mhd {
 // ------------------------------------------------------------ AMR support
-__device__ __forceinline__ int wrap_delta(int d, int n) { return d > n / 2 ? d - n : (d < -(n / 2) ? d + n : d); }
+// offset d of a cell from its group's origin on a periodic level of n cells,
+// taken in the group box's own range [lo, lo + n) (lo = minus the box's
+// ghost width): unique for every box position since levels with group
+// lists are at least edge + 8 cells wide
+__device__ __forceinline__ int box_offset(int d, int lo, int n) {
+  const int r = (d - lo) % n;
+  return (r < 0 ? r + n : r) + lo;
+}
 
 // Prolongation from a coarse level (nc) to a fine level (2 nc), paper
 // Sec. 3.3 (refinement operation).  Cell data: conservative limited-linear
@@ -246,8 +253,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong_ghosts(Work wc, Work wf, Coa
     // children inside the requested fine halo box [o - halo, o + edge + halo + 1) of this item's group
     const int* o = wf.groups + 3 * (t / per);
     auto in_box = [&](int x, int y, int z) {
-      const int dx = wrap_delta(x - o[0], wf.nx), dy = wrap_delta(y - o[1], wf.ny), dz = wrap_delta(z - o[2], wf.nz);
       const int blo = -wf.halo, bhi = wf.edge + wf.halo + 1;
+      const int dx = box_offset(x - o[0], blo, wf.nx), dy = box_offset(y - o[1], blo, wf.ny),
+                dz = box_offset(z - o[2], blo, wf.nz);
       return dx >= blo && dx < bhi && dy >= blo && dy < bhi && dz >= blo && dz < bhi;
     };
     bool cell_ok[8], face_ok[8][3];
@@ -351,8 +359,8 @@ __device__ __forceinline__ long long slot_at(const LevelScratch& v, int i, int j
   if (!v.sb) return ((long long)wrapc(k, v.nz) * v.ny + wrapc(j, v.ny)) * v.nx + wrapc(i, v.nx);
   const int* o = v.groups + 3 * g;
   const long long sb = v.sb;
-  const int a = wrap_delta(i - o[0], v.nx) + v.ghost, b = wrap_delta(j - o[1], v.ny) + v.ghost,
-            c = wrap_delta(k - o[2], v.nz) + v.ghost;
+  const int a = box_offset(i - o[0], -v.ghost, v.nx) + v.ghost, b = box_offset(j - o[1], -v.ghost, v.ny) + v.ghost,
+            c = box_offset(k - o[2], -v.ghost, v.nz) + v.ghost;
   return (long long)(g + 1) * sb * sb * sb + ((long long)c * sb + b) * sb + a;
 }
 

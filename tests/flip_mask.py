@@ -64,3 +64,29 @@ def check_outside(Ug, Bg, Uo, Bo, mu, mb, su, sb, bar=1e-5, max_frac=0.02, what=
     assert worst <= 1.0, (what, worst)
     assert frac <= max_frac, (what, frac)
     return worst, frac
+
+
+def level_flip_masks(run, levels, masks, bar=1e-12, eps=1e-14, seeds=(201, 202)):
+    """The same test for a hierarchy in double precision.  run(levels) ->
+    levels, each a (U, B) pair; masks[l] = (cell mask, [face masks]) of the
+    values of level l that count.  Each seed's relative noise eps (about 45
+    double ulps, well above the rounding by which two implementations of the
+    step differ) is applied to every level with both signs; a value that
+    moves by more than bar times its component's largest magnitude over the
+    counted values sits next to a decision within that noise of its switch.
+    Returns (reference levels, per level (U mask, B mask) of such values)."""
+    ref = run(levels)
+    out = [(np.zeros(U.shape, bool), np.zeros(B.shape, bool)) for U, B in ref]
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        noise = [(eps * rng.uniform(-1, 1, U.shape), eps * rng.uniform(-1, 1, B.shape)) for U, B in levels]
+        for sgn in (1.0, -1.0):
+            per = run([(U * (1 + sgn * nu), B * (1 + sgn * nb)) for (U, B), (nu, nb) in zip(levels, noise)])
+            for (Ur, Br), (Up, Bp), (cm, fm), (mu, mb) in zip(ref, per, masks, out):
+                for c in range(Ur.shape[0]):
+                    s = np.abs(Ur[c][cm]).max()
+                    mu[c] |= cm & (np.abs(np.nan_to_num(Up[c] - Ur[c])) > bar * s)
+                for a in range(3):
+                    s = np.abs(Br[a][fm[a]]).max()
+                    mb[a] |= fm[a] & (np.abs(np.nan_to_num(Bp[a] - Br[a])) > bar * s)
+    return ref, out

@@ -116,3 +116,24 @@ def test_full_cover_subcycled_is_two_uniform_fine_half_steps(orc):
     assert np.array_equal(Ucn, amr.restrict(Ur))
     for a in range(3):
         assert np.array_equal(Bcn[a], amr.face_mean(Br[a], a))
+
+
+@pytest.mark.parametrize("subcycle", [False, True])
+def test_three_levels_conserve_and_stay_solenoidal(orc, subcycle):
+    # root 16^3, two and three nested groups on the 32^3 and 64^3 levels; the
+    # level-1 start state carries its ghost boxes (its cells' prolongation
+    # reads their neighbours)
+    p = inputs.abc_problem(16, 0.1, seed=3)
+    U0, B0 = orc.initial_state(p)
+    g1, g2 = nested_groups(16, [2, 3], 16, seed=3)
+    U1, B1 = amr.initial_fine(U0, B0, g1, halo=4)
+    U2, B2 = amr.initial_fine(U1, B1, g2)
+    t0, _ = _totals(U0)
+    lv, dt = amr.hierarchy_step([(U0, B0), (U1, B1), (U2, B2)], [None, g1, g2], p["dx"], subcycle=subcycle)
+    t, mag = _totals(lv[0][0])
+    assert np.all(np.abs(t - t0) <= 1e-14 * mag)
+    for l, ((U, B), g) in enumerate(zip(lv, [None, g1, g2])):
+        dx = p["dx"] / 2 ** l
+        m = np.ones(U.shape[1:], bool) if g is None else amr.listed_mask(g, 16, U.shape[1:])
+        assert not np.isnan(U[:, m]).any()
+        assert np.abs(orc.divb(np.nan_to_num(B), dx)[m]).max() * dx <= 1e-13
