@@ -78,3 +78,36 @@ def wave_setup(n: int, wave: str, amp: float = 1e-6, bpar: float = 1.0, bperp: f
     wavelength = 2.0 * math.pi / kabs
     period = wavelength / abs(speed)
     return W5, B, period, dx
+
+
+def pencil_setup(nx: int, n_perp: int, wave: str, amp: float = 1e-6, t: float = 0.0,
+                 bpar: float = 1.0, bperp: float = 1.5):
+    """A linear wave along x on an nx x n_perp x n_perp pencil of unit length:
+    the background of wave_setup with the field (bpar, bperp, 0), the
+    perturbation cos(2 pi (x - c t)) along the wave's eigenvector (cell and
+    face averages exact; the normal field is uniform, so the discrete
+    divergence is zero).  Returns (W5, B, dx, c) with c the wave's speed."""
+    rho0, p0 = 1.0, 1.0 / GAMMA
+    A = prim_jacobian(rho0, 0.0, 0.0, 0.0, p0, bpar, bperp, 0.0)
+    lam, R = np.linalg.eig(A)
+    order = np.argsort(lam.real)
+    lam, R = lam.real[order], R.real[:, order]
+    idx = WAVES[wave]
+    c = lam[idx]
+    r = R[:, idx] / np.max(np.abs(R[:, idx]))
+    k = 2.0 * math.pi
+    dx = 1.0 / nx
+    xc = (np.arange(nx) + 0.5) * dx
+    h = 0.5 * k * dx
+    cosc = np.cos(k * (xc - c * t)) * math.sin(h) / h
+    shape = (n_perp, n_perp, nx)
+    W5 = np.empty((5,) + shape)
+    W5[0] = rho0 + amp * r[0] * cosc
+    for a in range(3):
+        W5[1 + a] = amp * r[1 + a] * cosc
+    W5[4] = p0 + amp * r[4] * cosc
+    B = np.empty((3,) + shape)
+    B[0] = bpar
+    B[1] = bperp + amp * r[5] * cosc
+    B[2] = amp * r[6] * cosc
+    return W5, B, dx, c
