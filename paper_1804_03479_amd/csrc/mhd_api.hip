@@ -1113,7 +1113,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_faces(const float* __restrict__ 
     wr[m] = active ? S[(long long)i * 15 + 7 + m] : 1.0f;
   }
   if (active) bn = S[(long long)i * 15 + 14];
-  const int h = mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
+  const int h = mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f, Capture{nullptr, 0, nullptr, 1}, 0);
   if (active) {
 #pragma unroll
     for (int m = 0; m < 7; ++m) F[(long long)i * 7 + m] = f[m];

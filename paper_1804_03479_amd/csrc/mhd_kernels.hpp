@@ -1049,9 +1049,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_ctu_correct(Work w, const T* __re
 // Learned flux (HLLD at strong jumps) of the D-faces in step 2 from the
 // traced states QLd[m * NS + s], QRd[m * NS + s] (m = 0..6) and the level's
 // time-n normal field B[D * N + p].  With capture on, the face's states and
-// the flux it used are recorded.
+// the flux it used are recorded.  Held to 128 VGPRs (four waves per SIMD,
+// a few spilled words): the network's dependent MFMA and transcendental
+// chains need the extra waves to hide their latency (12 % faster than
+// three waves at 135 VGPRs without spills).
 template <int D, bool L>
-__global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __restrict__ QLd,
+__global__ void __launch_bounds__(kBlock, 4) k_flux_dir_mlp(Work w, const float* __restrict__ QLd,
                                                          const float* __restrict__ QRd, const float* __restrict__ Bn,
                                                          float* __restrict__ F, float gam, const MlpWeights* mw,
                                                          float dp, float drho, unsigned long long* nfb,
@@ -1079,11 +1082,8 @@ __global__ void __launch_bounds__(kBlock) k_flux_dir_mlp(Work w, const float* __
       wr[m] = active ? QRd[(long long)m * NS + s] : 1.0f;
     }
     if (active) bn = Bn[D * N + p];
-    fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
-    if (active) {
-      capture_face(cp, 3 * p + D, wl, wr, bn, f);
-      store_flux<float, D>(F, NS, s, f);
-    }
+    fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f, cp, 3 * p + D);
+    if (active) store_flux<float, D>(F, NS, s, f);
   }
   block_count_atomic(fb, nfb);
 }
@@ -1123,11 +1123,8 @@ __global__ void __launch_bounds__(kBlock) k_ctu_correct_mlp(Work w, const float*
       bn = Bh[D * NS + s];
       corrected_states<float, D, L>(w, QL, QR, F1, E1, B, bn, st, hr, gam, wl, wr);
     }
-    fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f);
-    if (active) {
-      capture_face(cp, 3 * p + D, wl, wr, bn, f);
-      store_flux<float, D>(F2, NS, s, f);
-    }
+    fb += mlp_or_hlld(sh, active, wl, wr, bn, gam, dp, drho, f, cp, 3 * p + D);
+    if (active) store_flux<float, D>(F2, NS, s, f);
   }
   block_count_atomic(fb, nfb);
 }

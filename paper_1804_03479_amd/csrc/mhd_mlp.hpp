@@ -2,7 +2,8 @@
 // network that stands in for HLLD at smooth interfaces (HLLD stays in use
 // where the pressure or density jump exceeds a threshold), its training
 // kernels, and the capture of interface samples.  BF16 operands, FP32
-// accumulation on the MFMA units (v_mfma_f32_16x16x16_bf16).
+// accumulation on the MFMA units (v_mfma_f32_16x16x16_bf16, and for the
+// 64-deep layers of inference v_mfma_f32_16x16x32_bf16).
 //
 // Features: the mean of the two face-frame primitive states (rho, vn, vt1,
 // vt2, p, Bt1, Bt2), the unit jump and the jump size s, and Bn, all in units
@@ -32,6 +33,8 @@ constexpr int kParams = 15 * 64 + 64 + 64 * 64 + 64 + 64 * 7 + 7;
 constexpr int oW1 = 0, ob1 = 960, oW2 = 1024, ob2 = 5120, oW3 = 5184, ob3 = 5632;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -51,21 +54,35 @@ __device__ __forceinline__ bf16x4 f2bf4(float a, float b, float c, float d) {
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 // GELU, tanh form: 0.5 x (1 + tanh u) = x s with s = 1 / (1 + exp(-2u)),
-// u = sqrt(2/pi) (x + 0.044715 x^3); the derivative is
+// u = sqrt(2/pi) (x + 0.044715 x^3); exp(-2u) = 2^q with
+// q = x (a + b x^2), a = -2 sqrt(2/pi) log2(e), b = 0.044715 a, so one GELU
+// is three multiply-adds, v_exp_f32, an add, v_rcp_f32 and a multiply
+// (the hardware reciprocal needs no range scaling: a denominator beyond
+// 2^126 gives s = 0, the limit).  The derivative is
 // s + 2 x s (1 - s) du/dx.
-__device__ __forceinline__ float gelu_u2(float x) {
-  const float c2 = 1.5957691216057308f;  // 2 sqrt(2/pi)
-  return c2 * (x + 0.044715f * x * x * x);
+__device__ __forceinline__ float gelu_sig(float x) {
+  const float a = -2.302208198144325f, b = -0.1029432395800235f;
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x * __builtin_fmaf(b, x * x, a)));
 }
-__device__ __forceinline__ float gelu(float x) { return __fdividef(x, 1.0f + __expf(-gelu_u2(x))); }
+__device__ __forceinline__ float gelu(float x) { return x * gelu_sig(x); }
 __device__ __forceinline__ float gelu_prime(float x) {
-  const float sg = __fdividef(1.0f, 1.0f + __expf(-gelu_u2(x)));
-  const float du = 0.7978845608028654f * (1.0f + 3.0f * 0.044715f * x * x);
-  return sg + 2.0f * x * sg * (1.0f - sg) * du;
+  const float sg = gelu_sig(x);
+  const float du2 = 1.5957691216057308f * (1.0f + 3.0f * 0.044715f * x * x);   // 2 du/dx
+  return sg + x * sg * (1.0f - sg) * du2;
 }
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+// v_mfma_f32_16x16x32_bf16 (gfx950) on two 16-deep fragment pairs: lane l
+// supplies k = 8 (l / 16) + 0..7, here the 4 values of the first pair's
+// fragment followed by the 4 of the second.  Both operands take their k
+// slots in that same order, so the product is the sum of the two 16-deep
+// products: half the MFMA issues for the same contraction.
+__device__ __forceinline__ f32x4 mfma32(bf16x4 a0, bf16x4 a1, bf16x4 b0, bf16x4 b1, f32x4 c) {
+  const bf16x8 a = __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7));
+  const bf16x8 b = __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7));
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // Inference weights as the kernels read them: transposed, BF16, padded.
@@ -168,7 +185,7 @@ __device__ __forceinline__ void mlp_features(const float wl[7], const float wr[7
 // (lane (li, lk) reads W^T[16 t + li][16 s + 4 lk + 0..3] from LDS), so the
 // accumulator tile of one layer is already the B operand of the next, and
 // GELU and the BF16 rounding of each hidden layer act on it in registers.
-// Per 16-face tile: 4 + 16 + 4 MFMA 16x16x16.
+// Per 16-face tile: 4 MFMA 16x16x16 (layer 1) and 8 + 2 MFMA 16x16x32.
 __device__ __forceinline__ void mlp_forward_wave(MlpShared& sh, const float x[16], float y[7]) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   MlpStage& S = sh.st[threadIdx.x >> 6];
@@ -197,18 +214,20 @@ __device__ __forceinline__ void mlp_forward_wave(MlpShared& sh, const float x[16
     for (int t = 0; t < 4; ++t) {
       f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const bf16x4 wa = *reinterpret_cast<const bf16x4*>(g.W2t + (16 * t + li) * 64 + 16 * ks + 4 * lk);
-        z = mfma16(wa, h1[ks], z);
+      for (int kc = 0; kc < 2; ++kc) {
+        const unsigned short* wr = g.W2t + (16 * t + li) * 64 + 32 * kc + 4 * lk;
+        z = mfma32(*reinterpret_cast<const bf16x4*>(wr), *reinterpret_cast<const bf16x4*>(wr + 16), h1[2 * kc],
+                   h1[2 * kc + 1], z);
       }
       const float4 bb = *reinterpret_cast<const float4*>(g.b2 + 16 * t + 4 * lk);
       h2[t] = f2bf4(gelu(z[0] + bb.x), gelu(z[1] + bb.y), gelu(z[2] + bb.z), gelu(z[3] + bb.w));
     }
     f32x4 o = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const bf16x4 wa = *reinterpret_cast<const bf16x4*>(g.W3t + li * 64 + 16 * ks + 4 * lk);
-      o = mfma16(wa, h2[ks], o);
+    for (int kc = 0; kc < 2; ++kc) {
+      const unsigned short* wr = g.W3t + li * 64 + 32 * kc + 4 * lk;
+      o = mfma32(*reinterpret_cast<const bf16x4*>(wr), *reinterpret_cast<const bf16x4*>(wr + 16), h2[2 * kc],
+                 h2[2 * kc + 1], o);
     }
     // lane (li, lk) holds outputs 4 lk + 0..3 of face 16 ft + li
     if (lk < 2) {
@@ -225,44 +244,7 @@ __device__ __forceinline__ void mlp_forward_wave(MlpShared& sh, const float x[16
   wave_sync();   // the stage is rewritten by the next call
 }
 
-// Learned flux with HLLD fallback for one face per lane.  Returns 1 when the
-// face used HLLD (a strong jump), 0 when it used the network.
-__device__ __forceinline__ int mlp_or_hlld(MlpShared& sh, bool active, const float wl[7], const float wr[7], float bn,
-                                           float gam, float dp, float drho, float f[7]) {
-  bool fall = true;
-  float x[16], sc[7];
-  if (active) {
-    const float jp = fabsf(wr[4] - wl[4]) / fminf(wl[4], wr[4]);
-    const float jr = fabsf(wr[0] - wl[0]) / fminf(wl[0], wr[0]);
-    fall = (jp > dp) || (jr > drho);
-  }
-  if (active && !fall) {
-    mlp_features(wl, wr, bn, x, sc);
-  } else {
-#pragma unroll
-    for (int m = 0; m < 16; ++m) x[m] = 0.0f;
-#pragma unroll
-    for (int m = 0; m < 7; ++m) sc[m] = 0.0f;
-  }
-  float y[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  // the network runs when any lane of the wave needs it (wave-uniform test)
-  if (__ballot(active && !fall) != 0ull) mlp_forward_wave(sh, x, y);
-  if (!active) return 0;
-  if (fall) {
-    riemann_hlld(wl, wr, bn, gam, f);
-    return 1;
-  }
-  // the network gives the dissipative part; the central part is exact
-  const float gm1inv = 1.0f / (gam - 1.0f);
-  float ul[7], ur[7], fl[7], fr[7];
-  state_and_flux(wl, bn, gm1inv, ul, fl);
-  state_and_flux(wr, bn, gm1inv, ur, fr);
-#pragma unroll
-  for (int m = 0; m < 7; ++m) f[m] = 0.5f * (fl[m] + fr[m]) + y[m] * sc[m];
-  return 0;
-}
-
-// Interface capture: (wl[7], wr[7], bn, HLLD flux[7]) of every stride-th face
+// Interface capture: (wl[7], wr[7], bn, flux[7]) of every stride-th face
 struct Capture {
   float* buf;                    // [cap][22], nullptr = off
   long long cap;
@@ -270,19 +252,78 @@ struct Capture {
   int stride;
 };
 
-__device__ __forceinline__ void capture_face(const Capture& cp, long long face, const float wl[7], const float wr[7],
-                                             float bn, const float f[7]) {
-  if (!cp.buf || face % cp.stride) return;
+// the record of a face (its states written), or nullptr when the face is not
+// sampled or the buffer is full; capture_flux completes it
+__device__ __forceinline__ float* capture_states(const Capture& cp, long long face, const float wl[7],
+                                                 const float wr[7], float bn) {
+  if (!cp.buf || face % cp.stride) return nullptr;
   const unsigned long long slot = atomicAdd(cp.count, 1ull);
-  if ((long long)slot >= cp.cap) return;
+  if ((long long)slot >= cp.cap) return nullptr;
   float* o = cp.buf + slot * 22;
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
     o[m] = wl[m];
     o[7 + m] = wr[m];
-    o[15 + m] = f[m];
   }
   o[14] = bn;
+  return o;
+}
+__device__ __forceinline__ void capture_flux(float* o, const float f[7]) {
+  if (!o) return;
+#pragma unroll
+  for (int m = 0; m < 7; ++m) o[15 + m] = f[m];
+}
+__device__ __forceinline__ void capture_face(const Capture& cp, long long face, const float wl[7], const float wr[7],
+                                             float bn, const float f[7]) {
+  capture_flux(capture_states(cp, face, wl, wr, bn), f);
+}
+
+// Learned flux with HLLD fallback for one face per lane (capture: face id
+// `face` recorded with the flux used).  Returns 1 when the face used HLLD (a
+// strong jump), 0 when it used the network.  Every lane of the wave calls it
+// (lanes without a face pass active = false).  The fallback flux, or the
+// exact central part, is computed before the network, so that only the flux
+// and the output scales stay live across it.
+__device__ __forceinline__ int mlp_or_hlld(MlpShared& sh, bool active, const float wl[7], const float wr[7], float bn,
+                                           float gam, float dp, float drho, float f[7], const Capture& cp,
+                                           long long face) {
+  bool fall = true;
+  float x[16], sc[7];
+  if (active) {
+    const float jp = fabsf(wr[4] - wl[4]) / fminf(wl[4], wr[4]);
+    const float jr = fabsf(wr[0] - wl[0]) / fminf(wl[0], wr[0]);
+    fall = (jp > dp) || (jr > drho);
+  }
+  float* rec = nullptr;
+  if (active) rec = capture_states(cp, face, wl, wr, bn);
+#pragma unroll
+  for (int m = 0; m < 7; ++m) f[m] = 0.0f;
+  if (active && !fall) {
+    mlp_features(wl, wr, bn, x, sc);
+    // the network gives the dissipative part; the central part is exact
+    const float gm1inv = 1.0f / (gam - 1.0f);
+    float ul[7], ur[7], fl[7], fr[7];
+    state_and_flux(wl, bn, gm1inv, ul, fl);
+    state_and_flux(wr, bn, gm1inv, ur, fr);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = 0.5f * (fl[m] + fr[m]);
+  } else {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) x[m] = 0.0f;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) sc[m] = 0.0f;
+    if (active) riemann_hlld(wl, wr, bn, gam, f);
+  }
+  float y[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // the network runs when any lane of the wave needs it (wave-uniform test)
+  if (__ballot(active && !fall) != 0ull) mlp_forward_wave(sh, x, y);
+  if (!active) return 0;
+  if (!fall) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] += y[m] * sc[m];
+  }
+  capture_flux(rec, f);
+  return fall ? 1 : 0;
 }
 
 // ------------------------------------------------------------ training
