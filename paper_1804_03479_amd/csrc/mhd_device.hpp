@@ -366,22 +366,29 @@ __device__ __forceinline__ int riemann(const T wl[7], const T wr[7], T bn, T gam
   }
 }
 
-// minmod limiter: 0 if the one-sided differences differ in sign, else the
-// smaller in magnitude
+// minmod limiter: 0 if the one-sided differences differ in sign (or one is
+// zero), else the smaller in magnitude -- the median of a, b and 0: one
+// v_med3_f32 in float; in double the sum of max(min(a, b), 0) and
+// min(max(a, b), 0), of which one term is exactly zero (no compare and
+// select chains)
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b) {
-  if (a * b <= T(0)) return T(0);
-  return a > T(0) ? dmin(a, b) : dmax(a, b);
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+  } else {
+    return fmax(fmin(a, b), T(0)) + fmin(fmax(a, b), T(0));
+  }
 }
 
-// monotonised-central slope of q0 between neighbours qm and qp
+// monotonised-central slope of q0 between neighbours qm and qp: 0 where the
+// one-sided differences dl, dr differ in sign, else the central difference
+// dc limited to twice the smaller one-sided one -- minmod(dc, 2 minmod(dl,
+// dr)), since dc has the sign of dl and dr where they agree
 template <typename T>
 __device__ __forceinline__ T mc_slope(T qm, T q0, T qp) {
   const T dl = q0 - qm, dr = qp - q0;
-  if (dl * dr <= T(0)) return T(0);
   const T dc = T(0.5) * (qp - qm);
-  const T m = dmin(dabs(dc), T(2) * dmin(dabs(dl), dabs(dr)));
-  return dc > T(0) ? m : -m;
+  return minmod(dc, T(2) * minmod(dl, dr));
 }
 
 // PPM (Colella & Woodward 1984) interface value between cells a and b (a
