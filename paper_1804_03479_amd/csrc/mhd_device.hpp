@@ -398,19 +398,30 @@ __device__ __forceinline__ T ppm_interface(T qa, T qb, T sa, T sb) {
   return T(0.5) * (qa + qb) - (sb - sa) * T(1.0 / 6.0);
 }
 
+// median of three values (one v_med3_f32 in float)
+template <typename T>
+__device__ __forceinline__ T med3(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_amdgcn_fmed3f(a, b, c);
+  } else {
+    return fmax(fmin(a, b), fmin(fmax(a, b), c));
+  }
+}
+
 // PPM monotonicity constraints on a cell's parabola (centre value c, edge
-// values l and r): flat at an extremum, otherwise edges pulled in so the
-// parabola takes no value outside [l, r]
+// values l and r): flat at an extremum, otherwise an edge more than twice as
+// far from c as the other is pulled in to 3c - 2(other edge), so the
+// parabola takes no value outside [l, r].  Written as medians: l becomes the
+// median of l, c and c - 2 (r - c), r likewise -- at an extremum (l and r on
+// the same side of c) both medians are c; otherwise the median keeps l
+// unless it lies beyond c - 2 (r - c).  (The usual form compares
+// (r - l)(c - (l + r)/2) with (r - l)^2 / 6; the two tests are the same
+// inequality.)
 template <typename T>
 __device__ __forceinline__ void ppm_limit(T c, T& l, T& r) {
-  if ((r - c) * (c - l) <= T(0)) {
-    l = c;
-    r = c;
-  } else {
-    const T dq = r - l, m6 = dq * (c - T(0.5) * (l + r)), dq2 = dq * dq * T(1.0 / 6.0);
-    if (m6 > dq2) l = T(3) * c - T(2) * r;
-    else if (-dq2 > m6) r = T(3) * c - T(2) * l;
-  }
+  const T l0 = l, r0 = r;
+  l = med3(l0, c, c - T(2) * (r0 - c));
+  r = med3(r0, c, c - T(2) * (l0 - c));
 }
 
 // PPM edge values of the centre of q0..q4: interface values from
