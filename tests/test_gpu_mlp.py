@@ -143,6 +143,29 @@ def test_face_flux_network_and_fallback(ops, theta):
         assert np.allclose(F[i], fo, rtol=2e-5, atol=2e-5 * np.abs(fo).max())
 
 
+@pytest.mark.parametrize("scale", [8.0, 40.0])
+def test_saturated_activations_match_oracle(ops, theta, scale):
+    # weights scaled up so that the hidden pre-activations reach tens in
+    # magnitude: GELU's two limits (0 for large negative arguments, the
+    # argument itself for large positive ones) through the exponential and
+    # reciprocal of the inference and training kernels, finite everywhere
+    th = (theta * scale).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(int(scale))
+    X = (2.0 * rng.standard_normal((500, 15))).astype(np.float32).astype(np.float64)
+    Y = ops.forward(dev(th), dev(X)).cpu().numpy()
+    assert np.isfinite(Y).all()
+    Yo, cache = omlp.forward(th, X, bf16_ops=True)
+    assert_elementwise(Y, Yo, what="forward, saturated")
+    wl, wr, bn = smooth_states(rng, 400, 0.5)
+    ops.set_weights(dev(th))
+    F, used = ops.face_flux(dev(np.concatenate([wl, wr, bn[:, None]], axis=1)))
+    F, used = F.cpu().numpy(), used.cpu().numpy().astype(bool)
+    assert np.isfinite(F).all()
+    Fo = omlp.surrogate_flux(th, wl[~used], wr[~used], bn[~used], bf16_ops=True)
+    assert_elementwise(F[~used], Fo, what="face flux, saturated")
+    ops.set_weights(dev(theta))
+
+
 def abc_level(s, n, noise, seed):
     p = inputs.abc_problem(n, noise, seed=seed)
     W5 = torch.from_numpy(np.stack([p["rho"], p["vx"], p["vy"], p["vz"], p["p"]]))
