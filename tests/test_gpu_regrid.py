@@ -179,6 +179,83 @@ def test_hierarchy_regrid_conserves_and_stays_solenoidal(subcycle):
     h.close()
 
 
+def test_regrid_inside_a_run_matches_the_oracle():
+    # root 32^3 FP64 CTU+PPM+HLLD with 3 listed groups: two shared steps, a
+    # regrid by the criterion (buffer 1; the threshold keeps two of the three
+    # groups, drops one and creates 59, many next to the kept ones), two more
+    # steps.  The GPU hierarchy (its list from its own criterion kernels, the
+    # created groups from its own prolongation) against the oracle's
+    # hierarchy step, refine_groups and prolong_new_groups; both start from
+    # the oracle's level states.  Values next to a decision within rounding
+    # of its switch are excluded as in the hierarchy tests (the oracle's
+    # own response to a 1e-14 perturbation, the regrid list held fixed)
+    from flip_mask import level_flip_masks
+    n, seed, thr = 32, 2, 0.2010
+    h = Hierarchy(n, [3], "ctu", "ppm", "hlld", "f64", noise=0.1, seed=seed, capacity=64)
+    g1 = h.groups[0]
+    p = inputs.abc_problem(n, 0.1, seed=seed)
+    U0, B0 = oracle.initial_state(p)
+    lv0 = [(U0, B0), oamr.initial_fine(U0, B0, g1)]
+    for gl, (U, B) in zip(h.levels, lv0):
+        for gt, a in ((gl.U, U), (gl.B, B)):
+            have = torch.from_numpy(~np.isnan(a)).cuda()
+            gt.copy_(torch.where(have, torch.from_numpy(np.nan_to_num(a)).cuda(), gt))
+    torch.cuda.synchronize()
+
+    def run(levels, new=None, dts=None):
+        out = levels
+        for _ in range(2):
+            out, dt = oamr.hierarchy_step(out, [None, g1], p["dx"])
+            if dts is not None:
+                dts.append(dt)
+        if new is None:
+            new = oamr.refine_groups(out[0][1], thr, buffer=1)
+        out = [out[0], oamr.prolong_new_groups(out[0][0], out[0][1], out[1][0], out[1][1], new, g1)]
+        for _ in range(2):
+            out, dt = oamr.hierarchy_step(out, [None, new], p["dx"])
+            if dts is not None:
+                dts.append(dt)
+        return out, new
+
+    dts = []
+    _, g2 = run(lv0, dts=dts)
+    kept = {tuple(x) for x in g1.tolist()} & {tuple(x) for x in g2.tolist()}
+    assert len(kept) == 2 and len(g2) == 61
+    m1 = oamr.listed_mask(g2, 16, lv0[1][0].shape[1:])
+    m0 = np.ones(U0.shape[1:], bool)
+    masks = [(m, [oamr._face_of_listed(m, a) if m is m1 else m for a in range(3)]) for m in (m0, m1)]
+    ref, flips = level_flip_masks(lambda lv: run(lv, new=g2)[0], lv0, masks)
+    for s_ in range(2):
+        h.step()
+        h.stream.synchronize()
+        assert abs(h.dts[0].item() - dts[s_]) <= 1e-13 * dts[s_]
+    h.regrid(thr, buffer=1)
+    h.check_regrid()
+    n1 = h.group_counts()[0]
+    assert np.array_equal(h.levels[1].groups[:n1].cpu().numpy(), g2)
+    for s_ in range(2, 4):
+        h.step()
+        h.stream.synchronize()
+        assert abs(h.dts[0].item() - dts[s_]) <= 1e-13 * dts[s_]
+    total = excluded = 0
+    for l, ((Uo, Bo), (cm, fm), (mu, mb)) in enumerate(zip(ref, masks, flips)):
+        Ug, Bg = h.levels[l].U.cpu().numpy(), h.levels[l].B.cpu().numpy()
+        for c in range(5):
+            keep = cm & ~mu[c]
+            assert np.abs(Ug[c][keep] - Uo[c][keep]).max() <= 1e-12 * np.abs(Uo[c][cm]).max(), (l, c)
+            total += int(cm.sum())
+            excluded += int(mu[c].sum())
+        for a in range(3):
+            keep = fm[a] & ~mb[a]
+            assert np.abs(Bg[a][keep] - Bo[a][keep]).max() <= 1e-12 * np.abs(Bo[a][fm[a]]).max(), (l, a)
+            total += int(fm[a].sum())
+            excluded += int(mb[a].sum())
+    print(f"\nregrid inside a run: {excluded} of {total} values ({100 * excluded / total:.2f} %) "
+          "next to a switch within 1e-14")
+    assert excluded <= 0.03 * total
+    h.close()
+
+
 def test_captured_step_stays_valid_across_a_regrid():
     a = Hierarchy(32, [5, 9], prec="f32", seed=2, capacity=128)
     b = Hierarchy(32, [5, 9], prec="f32", seed=2, capacity=128)
