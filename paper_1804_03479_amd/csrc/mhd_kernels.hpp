@@ -433,6 +433,21 @@ __device__ __forceinline__ T upwind(T m, T pos, T neg) {
   return m > T(0) ? pos : (m < T(0) ? neg : T(0.5) * (pos + neg));
 }
 
+// The upwind CT average of one edge from its four face EMFs (eb0, eb1 on the
+// b-faces below and at the cell, ec0, ec1 on the c-faces), the faces' mass
+// fluxes (mb*, mc*) and the reference EMFs of the four cells around the edge
+// (r00 at the cell below in b and c, r10 below in c, r01 below in b, r11 the
+// cell itself)
+template <typename T>
+__device__ __forceinline__ T edge_emf_core(T eb0, T eb1, T ec0, T ec1, T mb0, T mb1, T mc0, T mc1, T r00, T r10,
+                                           T r01, T r11) {
+  const T dc1 = upwind(mb1, r01 - ec0, r11 - ec1);
+  const T dc0 = upwind(mb0, ec0 - r00, ec1 - r10);
+  const T db1 = upwind(mc1, r10 - eb0, r11 - eb1);
+  const T db0 = upwind(mc0, eb0 - r00, eb1 - r01);
+  return T(0.25) * (eb0 + eb1 + ec0 + ec1) + T(0.25) * ((dc0 - dc1) + (db0 - db1));
+}
+
 // E_a on the edge at the lower (b, c) corner of cell (i, j, k), (a, b, c)
 // cyclic, from the four faces around the edge (upwind CT average of
 // Gardiner & Stone 2005): each face value is extrapolated to the edge with
@@ -456,11 +471,7 @@ __device__ __forceinline__ T edge_emf(const Work& w, const T* __restrict__ F, co
   const T mb0 = Fb[pc], mb1 = Fb[p], mc0 = Fc[pb], mc1 = Fc[p];
   const T r00 = ref_emf(W, N, pbc, A), r10 = ref_emf(W, N, pc, A);
   const T r01 = ref_emf(W, N, pb, A), r11 = ref_emf(W, N, p, A);
-  const T dc1 = upwind(mb1, r01 - ec0, r11 - ec1);
-  const T dc0 = upwind(mb0, ec0 - r00, ec1 - r10);
-  const T db1 = upwind(mc1, r10 - eb0, r11 - eb1);
-  const T db0 = upwind(mc0, eb0 - r00, eb1 - r01);
-  return T(0.25) * (eb0 + eb1 + ec0 + ec1) + T(0.25) * ((dc0 - dc1) + (db0 - db1));
+  return edge_emf_core(eb0, eb1, ec0, ec1, mb0, mb1, mc0, mc1, r00, r10, r01, r11);
 }
 
 template <typename T, bool L>
@@ -471,6 +482,54 @@ __global__ void __launch_bounds__(kMaxBlock) k_emf(Work w, const T* __restrict__
     E[st.s] = edge_emf<T, 0, L>(w, F, W, st);
     E[w.NS + st.s] = edge_emf<T, 1, L>(w, F, W, st);
     E[2 * w.NS + st.s] = edge_emf<T, 2, L>(w, F, W, st);
+  }
+}
+
+// Edge EMFs of a whole grid on LDS tiles: each block stages, for its
+// TX x TY x TZ cells and the layer below them along every direction, the
+// cells' reference EMFs -v x B (three components) and, per face direction,
+// the face's mass flux and its two EMF components (twelve values per cell,
+// each loaded once per tile instead of once per edge that uses it), then
+// computes the three lower-corner edges of each of its cells from LDS with
+// the arithmetic of k_emf.  Grids need not be multiples of the tile (cells
+// past the grid idle; the staged layer wraps periodically).
+template <typename T, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ) k_emf_tiled(Work w, const T* __restrict__ F, const T* __restrict__ W,
+                                                         T* __restrict__ E) {
+  constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NH = HX * HY * HZ, NT = TX * TY * TZ;
+  __shared__ T sR[3][NH];
+  __shared__ T sF[3][3][NH];
+  const int ntx = (w.nx + TX - 1) / TX, nty = (w.ny + TY - 1) / TY;
+  const int tile = (int)block_rank();
+  const int tx0 = (tile % ntx) * TX, ty0 = ((tile / ntx) % nty) * TY, tz0 = (tile / (ntx * nty)) * TZ;
+  const long long N = w.NS;
+  for (int h = threadIdx.x; h < NH; h += NT) {
+    const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+    const long long q = lin(w, wrapc(tx0 - 1 + hx, w.nx), wrapc(ty0 - 1 + hy, w.ny), wrapc(tz0 - 1 + hz, w.nz));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sR[a][h] = ref_emf(W, N, q, a);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      sF[d][0][h] = F[(long long)(7 * d) * N + q];
+      sF[d][1][h] = F[(long long)(7 * d + 5) * N + q];
+      sF[d][2][h] = F[(long long)(7 * d + 6) * N + q];
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int ax = t % TX, ay = (t / TX) % TY, az = t / (TX * TY);
+  const int i = tx0 + ax, j = ty0 + ay, k = tz0 + az;
+  if (i >= w.nx || j >= w.ny || k >= w.nz) return;
+  const int h = ((az + 1) * HY + (ay + 1)) * HX + (ax + 1);
+  const long long p = lin(w, i, j, k);
+  constexpr int st[3] = {1, HX, HX * HY};
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    const int b = (A + 1) % 3, c = (A + 2) % 3;
+    const int hb = h - st[b], hc = h - st[c], hbc = h - st[b] - st[c];
+    E[(long long)A * N + p] = edge_emf_core(sF[b][2][hc], sF[b][2][h], sF[c][1][hb], sF[c][1][h], sF[b][0][hc],
+                                            sF[b][0][h], sF[c][0][hb], sF[c][0][h], sR[A][hbc], sR[A][hc],
+                                            sR[A][hb], sR[A][h]);
   }
 }
 
